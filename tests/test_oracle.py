@@ -1,0 +1,385 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test names what fixes the expected result: exact rational arithmetic
+(correct rounding by definition), hand-worked values, the paper's worked
+examples (Sec. 3.1.1 uniform partition, Sec. 3.1.2 adaptive partition,
+Sec. 3.2 cubic DAG example), Theorem 1 (refinement excess width orders),
+inclusion (Definition "Inclusion function"), inclusion isotonicity under
+refinement, finite differences and high-precision decimal exp/log.
+"""
+import decimal
+import math
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_20769_amd import inputs as I
+
+ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG = O.ADD, O.SUB, O.MUL, O.DIV, O.SQR, O.SQRT, O.EXP, O.LOG
+
+
+# --------------------------------------------------------------------------
+# exact rational reference for one correctly rounded operation
+# --------------------------------------------------------------------------
+
+_MAXF = Fraction(np.finfo(np.float64).max)
+
+
+def _rd(q: Fraction) -> float:
+    if q > _MAXF:
+        return float(_MAXF)
+    if q < -_MAXF:
+        return -math.inf
+    d = float(q)                      # correctly rounded to nearest
+    if Fraction(d) > q:
+        d = math.nextafter(d, -math.inf)
+    return d
+
+
+def _ru(q: Fraction) -> float:
+    return -_rd(-q)
+
+
+def _sqrt_rd(a: float) -> float:
+    s = math.sqrt(a)
+    A = Fraction(a)
+    while Fraction(s) ** 2 > A:
+        s = math.nextafter(s, -math.inf)
+    while Fraction(math.nextafter(s, math.inf)) ** 2 <= A:
+        s = math.nextafter(s, math.inf)
+    return s
+
+
+def _sqrt_ru(a: float) -> float:
+    s = _sqrt_rd(a)
+    return s if Fraction(s) ** 2 == Fraction(a) else math.nextafter(s, math.inf)
+
+
+def _edge_doubles(rng: random.Random, count: int, emax: int):
+    vals = [0.0, -0.0, 1.0, -1.0, 0.1, 0.2, 0.3, 1 / 3, 2.0 ** -1074, -(2.0 ** -1074), 2.0 ** -1022,
+            math.nextafter(1.0, 2.0), math.nextafter(1.0, 0.0), 3.0, 7.0, 1e-300, 123456789.0]
+    while len(vals) < count:
+        m = rng.random() * 2 - 1
+        vals.append(math.ldexp(m, rng.randint(-emax, emax)))
+    return vals
+
+
+def test_directed_ops_match_exact_rationals():
+    rng = random.Random(7)
+    xs = _edge_doubles(rng, 300, 400)
+    ys = _edge_doubles(rng, 300, 400)
+    rng.shuffle(ys)
+    for a, b in zip(xs, ys):
+        A, B = Fraction(a), Fraction(b)
+        for op, q in ((ADD, A + B), (SUB, A - B), (MUL, A * B)):
+            assert O.round_op(op, -1, a, b) == _rd(q), (op, a, b)
+            assert O.round_op(op, +1, a, b) == _ru(q), (op, a, b)
+        if b != 0:
+            assert O.round_op(DIV, -1, a, b) == _rd(A / B), (a, b)
+            assert O.round_op(DIV, +1, a, b) == _ru(A / B), (a, b)
+        if a >= 0:
+            assert O.round_op(SQRT, -1, a, 0) == _sqrt_rd(a), a
+            assert O.round_op(SQRT, +1, a, 0) == _sqrt_ru(a), a
+
+
+def test_directed_ops_hand_values():
+    # 0.1 + 0.2 lies strictly between two doubles
+    h = lambda x: np.float64(x).view(np.uint64)
+    assert h(O.round_op(ADD, -1, 0.1, 0.2)) == 0x3FD3333333333333
+    assert h(O.round_op(ADD, +1, 0.1, 0.2)) == 0x3FD3333333333334
+    assert h(O.round_op(DIV, -1, 1.0, 3.0)) == 0x3FD5555555555555
+    assert h(O.round_op(DIV, +1, 1.0, 3.0)) == 0x3FD5555555555556
+    assert h(O.round_op(SQRT, -1, 2.0, 0)) == 0x3FF6A09E667F3BCC
+    assert h(O.round_op(SQRT, +1, 2.0, 0)) == 0x3FF6A09E667F3BCD
+    z = O.interval_op(MUL, [0.1, 0.1], [3.0, 3.0])
+    assert h(z[0]) == 0x3FD3333333333333 and h(z[1]) == 0x3FD3333333333334
+
+
+def test_interval_ops_hand_worked():
+    assert list(O.interval_op(MUL, [-1, 2], [-3, 4])) == [-6.0, 8.0]
+    assert list(O.interval_op(SQR, [-2, 1])) == [0.0, 4.0]
+    assert list(O.interval_op(SQR, [-3, -2])) == [4.0, 9.0]
+    assert list(O.interval_op(DIV, [1, 2], [4, 8])) == [0.125, 0.5]
+    assert list(O.interval_op(DIV, [-1, 2], [-4, -2])) == [-1.0, 0.5]
+    assert list(O.interval_op(ADD, [1, 2], [-5, 3])) == [-4.0, 5.0]
+    assert list(O.interval_op(SUB, [1, 2], [-5, 3])) == [-2.0, 7.0]
+    assert list(O.interval_op(SQRT, [4, 9])) == [2.0, 3.0]
+
+
+def test_interval_ops_enclose_sampled_images():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        u = np.sort(rng.uniform(-5, 5, 2))
+        v = np.sort(rng.uniform(-5, 5, 2))
+        xs = rng.uniform(u[0], u[1], 50)
+        ys = rng.uniform(v[0], v[1], 50)
+        for op, f in ((ADD, xs + ys), (SUB, xs - ys), (MUL, xs * ys)):
+            z = O.interval_op(op, u, v)
+            assert z[0] <= f.min() and f.max() <= z[1]
+        if v[0] > 0 or v[1] < 0:
+            z = O.interval_op(DIV, u, v)
+            f = xs / ys
+            assert z[0] <= f.min() and f.max() <= z[1]
+        z = O.interval_op(SQR, u)
+        assert z[0] <= (xs * xs).min() and (xs * xs).max() <= z[1]
+
+
+def test_exp_log_padding_encloses_high_precision_values():
+    decimal.getcontext().prec = 60
+    rng = np.random.default_rng(11)
+    for a in np.concatenate([rng.uniform(-30, 30, 300), [0.0, 1.0, -1.0, 5.0, -5.0, 700.0, -700.0]]):
+        z = O.interval_op(EXP, [a, a])
+        t = decimal.Decimal(float(a)).exp()
+        assert decimal.Decimal(z[0]) <= t <= decimal.Decimal(z[1]), a
+        assert z[0] >= 0
+    for a in np.concatenate([np.exp(rng.uniform(-40, 40, 300)), [1.0, 2.0, 0.5, 1e-300, 1e300]]):
+        z = O.interval_op(LOG, [a, a])
+        t = decimal.Decimal(float(a)).ln()
+        assert decimal.Decimal(z[0]) <= t <= decimal.Decimal(z[1]), a
+
+
+# --------------------------------------------------------------------------
+# Step 1: splitting
+# --------------------------------------------------------------------------
+
+def test_uniform_partition_worked_example():
+    # Sec. 3.1.1: X = [-3,1] x [0,2] into four subdomains X_1..X_4
+    box = np.array([[-3.0, 1.0], [0.0, 2.0]])
+    want = [[[-3, -1], [0, 1]], [[-1, 1], [0, 1]], [[-3, -1], [1, 2]], [[-1, 1], [1, 2]]]
+    for k, w in enumerate(want):
+        X, c = O.subdomain(box, np.array([2, 2]), k)
+        assert X.tolist() == w
+        assert c.tolist() == [0.5 * (w[0][0] + w[0][1]), 0.5 * (w[1][0] + w[1][1])]
+
+
+def test_partition_covers_box_exactly():
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        lo = rng.uniform(-10, 10)
+        hi = lo + rng.uniform(1e-3, 20)
+        s = int(rng.integers(1, 40))
+        box = np.array([[lo, hi]])
+        prev = None
+        for k in range(s):
+            X, c = O.subdomain(box, np.array([s]), k)
+            assert X[0, 0] <= c[0] <= X[0, 1]
+            if k == 0:
+                assert X[0, 0] == lo
+            else:
+                assert X[0, 0] == prev            # shared breakpoints, no gaps
+            prev = X[0, 1]
+        assert prev == hi
+
+
+def test_adaptive_partition_worked_example():
+    # Sec. 3.1.2: five dimensions, 2560 cores -> uniform 4^5 = 1024, adaptive 5^4 * 4 = 2500
+    s, count = O.adaptive_splits(np.ones(5), 2560)
+    assert count == 2500 and sorted(s.tolist()) == [4, 5, 5, 5, 5]
+    s, count = O.adaptive_splits(np.ones(5), 1024)
+    assert count == 1024 and s.tolist() == [4] * 5
+    # uniform 8x8 = 64 first, then the relatively wider dimension grows: 8x9, 8x10
+    s, count = O.adaptive_splits(np.array([1.0, 4.0]), 80)
+    assert count == 80 and s.tolist() == [8, 10]
+
+
+# --------------------------------------------------------------------------
+# Step 2: the cubic of the DAG example, f = 3x^3 + x^2 - 5x - 1
+# --------------------------------------------------------------------------
+
+CUBIC_TRUE_MIN = (lambda x: 3 * x ** 3 + x ** 2 - 5 * x - 1)((-1 + math.sqrt(46)) / 9)
+
+
+def test_cubic_hand_worked_n1():
+    # By hand on X = [-1, 2] (all values dyadic, no rounding):
+    #   sqr x = [0,4]; x*v1 = [-4,8]; 3*v2 = [-12,24]; +v1 = [-12,28]; 5x = [-5,10];
+    #   v4 - v5 = [-22,33]; -1 -> NIE = [-23,32].
+    #   tangents: 2X = [-2,4]; dv2 = [0,4] + [-1,2]*[-2,4] = [-4,12]; dv3 = [-12,36];
+    #   dv4 = [-14,40]; dv6 = [-14,40] - [5,5] = [-19,35] = G.
+    #   c = 0.5, f(c) = -2.875;  MVF = -2.875 + [-19,35]*[-1.5,1.5] = [-55.375, 49.625].
+    t = I.cubic_tape()
+    box = np.array([[-1.0, 2.0]])
+    assert O.bound(t, box, [1], mode=O.MODE_NIE)["reduced"][0].tolist() == [-23.0, 32.0]
+    assert O.bound(t, box, [1], mode=O.MODE_MVF)["reduced"][0].tolist() == [-55.375, 49.625]
+    assert O.bound(t, box, [1], mode=O.MODE_BOTH)["reduced"][0].tolist() == [-23.0, 32.0]
+    G, _ = O.gradient_boxes(t, box[None], 0, O.GRAD_FWD)
+    assert G[0, 0].tolist() == [-19.0, 35.0]
+    f = O.eval_points(t, np.array([[0.5]]))
+    assert f[0, 0].tolist() == [-2.875, -2.875]
+
+
+def test_cubic_theorem1_orders_and_crossover():
+    # Theorem 1: excess width of the refinement is O(w/N) for the NIE and
+    # O((w/N)^2) for the MVF.  True range of the cubic on [-1, 2]: max f(2) = 17,
+    # min at x = (-1 + sqrt(46)) / 9.
+    t = I.cubic_tape()
+    box = np.array([[-1.0, 2.0]])
+    true_w = 17.0 - CUBIC_TRUE_MIN
+    Ns = [16, 32, 64, 128, 256, 512, 1024, 2048]
+    res = {m: np.array([O.bound(t, box, [N], mode=m, per_sub=False)["reduced"][0] for N in Ns])
+           for m in (O.MODE_NIE, O.MODE_MVF, O.MODE_BOTH)}
+    for m in res:                                              # inclusion
+        assert np.all(res[m][:, 0] <= CUBIC_TRUE_MIN) and np.all(res[m][:, 1] >= 17.0)
+    for m, order in ((O.MODE_NIE, 1.0), (O.MODE_MVF, 2.0)):
+        ex = res[m][:, 1] - res[m][:, 0] - true_w
+        slope = np.polyfit(np.log(Ns), np.log(ex), 1)[0]
+        assert abs(-slope - order) < 0.1, (m, slope)
+    # Sec. 4.1: the MVF is looser than the NIE with few subdomains, tighter with many
+    lb = {m: [O.bound(t, box, [N], mode=m, per_sub=False)["reduced"][0, 0] for N in (1, 256)]
+          for m in (O.MODE_NIE, O.MODE_MVF, O.MODE_BOTH)}
+    assert lb[O.MODE_MVF][0] < lb[O.MODE_NIE][0]
+    assert lb[O.MODE_MVF][1] > lb[O.MODE_NIE][1]
+    for a, b_, c in zip(lb[O.MODE_NIE], lb[O.MODE_MVF], lb[O.MODE_BOTH]):
+        assert c == max(a, b_)                                 # the intersection
+
+
+def test_cubic_gradient_encloses_symbolic_derivative():
+    t = I.cubic_tape()
+    box = np.array([[-1.0, 2.0]])
+    for N in (3, 7, 16):
+        for k in range(N):
+            X, c = O.subdomain(box, np.array([N]), k)
+            xs = np.linspace(X[0, 0], X[0, 1], 33)
+            d = 9 * xs ** 2 + 2 * xs - 5
+            for g in (O.GRAD_FWD, O.GRAD_REV):
+                G, _ = O.gradient_boxes(t, X[None], 0, g)
+                assert G[0, 0, 0] <= d.min() + 1e-12 and d.max() - 1e-12 <= G[0, 0, 1]
+
+
+# --------------------------------------------------------------------------
+# Step 2 on random tapes: inclusion, isotonic refinement, derivatives
+# --------------------------------------------------------------------------
+
+def _small_cases():
+    out = []
+    for seed in (1, 2, 3):
+        t = I.random_small_tape(seed, n=3, ops=40, n_con=2, con_ops=15, window=8)
+        out.append((seed, t, np.array([[-2.0, 2.0]] * 3)))
+    w = I.tiny(1)
+    out.append(("tiny", w.tape, w.box))
+    out.append(("peaks", I.peaks_tape(), np.array([[-3.0, 3.0], [-3.0, 3.0]])))
+    return out
+
+
+@pytest.mark.parametrize("case", _small_cases(), ids=lambda c: str(c[0]))
+@pytest.mark.parametrize("grad", [O.GRAD_FWD, O.GRAD_REV])
+def test_bounds_enclose_sampled_values(case, grad):
+    name, t, box = case
+    n = box.shape[0]
+    splits = np.array([4] * n, dtype=np.int32)
+    res = O.bound(t, box, splits, mode=O.MODE_BOTH, grad=grad)
+    ps = res["per_sub"]
+    rng = np.random.default_rng(17)
+    S = int(np.prod(splits))
+    for k in rng.choice(S, size=min(S, 24), replace=False):
+        X, c = O.subdomain(box, splits, int(k))
+        pts = X[:, 0] + (X[:, 1] - X[:, 0]) * rng.random((200, n))
+        pts = np.concatenate([pts, X[:, 0][None], X[:, 1][None], c[None]])
+        vals = I.eval_points_np(t, pts)
+        scale = np.maximum(1.0, np.abs(vals).max(axis=0))
+        for r in range(t.n_roots):
+            slack = 1e-12 * scale[r]
+            assert ps[r, 0, k] - slack <= vals[:, r].min(), (name, r, k)
+            assert vals[:, r].max() <= ps[r, 1, k] + slack, (name, r, k)
+    # reduced = hull of the per-subdomain bounds; argmin = first subdomain attaining it
+    assert np.array_equal(res["reduced"][:, 0], ps[:, 0, :].min(axis=1))
+    assert np.array_equal(res["reduced"][:, 1], ps[:, 1, :].max(axis=1))
+    assert res["argmin"] == int(np.argmax(ps[0, 0, :] == ps[0, 0, :].min()))
+
+
+@pytest.mark.parametrize("case", _small_cases(), ids=lambda c: str(c[0]))
+def test_refinement_never_loosens_nested_partitions(case):
+    # inclusion isotonicity: N -> 2N subdomains are nested (shared RN breakpoints halve exactly)
+    name, t, box = case
+    n = box.shape[0]
+    prev = {}
+    for N in (1, 2, 4, 8):
+        splits = np.array([N] * n, dtype=np.int32)
+        for mode in (O.MODE_NIE, O.MODE_BOTH):
+            lb = O.bound(t, box, splits, mode=mode, per_sub=False)["reduced"]
+            if mode in prev:
+                scale = np.maximum(1.0, np.abs(prev[mode]).max(axis=1))
+                tol = 0.0 if mode == O.MODE_NIE else 1e-13 * scale
+                assert np.all(lb[:, 0] >= prev[mode][:, 0] - tol), (name, N, mode)
+                assert np.all(lb[:, 1] <= prev[mode][:, 1] + tol), (name, N, mode)
+            prev[mode] = lb
+
+
+def _fd_grad(t, x, h=1e-6):
+    n = x.shape[0]
+    g = np.zeros((t.n_roots, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = h
+        f = I.eval_points_np(t, np.stack([x + e, x - e]))
+        g[:, j] = (f[0] - f[1]) / (2 * h)
+    return g
+
+
+@pytest.mark.parametrize("case", _small_cases(), ids=lambda c: str(c[0]))
+def test_gradients_enclose_finite_differences(case):
+    name, t, box = case
+    n = box.shape[0]
+    rng = np.random.default_rng(23)
+    for _ in range(8):
+        x = box[:, 0] + 0.1 + (box[:, 1] - box[:, 0] - 0.2) * rng.random(n)
+        fd = _fd_grad(t, x)
+        boxes = np.stack([x - 1e-9, x + 1e-9], axis=1)[None]
+        for r in range(t.n_roots):
+            Gf, _ = O.gradient_boxes(t, boxes, r, O.GRAD_FWD)
+            Gr, _ = O.gradient_boxes(t, boxes, r, O.GRAD_REV)
+            for G in (Gf, Gr):
+                tol = 1e-5 * np.maximum(1.0, np.abs(fd[r]))
+                assert np.all(G[0, :, 0] <= fd[r] + tol), (name, r)
+                assert np.all(fd[r] - tol <= G[0, :, 1]), (name, r)
+            # both modes enclose the same true gradient: they intersect
+            assert np.all(np.maximum(Gf[0, :, 0], Gr[0, :, 0]) <= np.minimum(Gf[0, :, 1], Gr[0, :, 1]))
+
+
+def test_vjp_points_matches_finite_differences():
+    t = I.random_small_tape(4, n=3, ops=30, n_con=2, con_ops=12)
+    rng = np.random.default_rng(29)
+    x = rng.uniform(-1.5, 1.5, (6, 3))
+    gout = rng.normal(size=(6, t.n_roots))
+    gx = O.vjp_points(t, x, gout)
+    for b in range(6):
+        want = gout[b] @ _fd_grad(t, x[b])
+        mid = 0.5 * (gx[b, :, 0] + gx[b, :, 1])
+        assert np.allclose(mid, want, rtol=1e-5, atol=1e-6)
+        assert np.all(gx[b, :, 0] <= gx[b, :, 1])
+
+
+# --------------------------------------------------------------------------
+# domain policy
+# --------------------------------------------------------------------------
+
+def _tape_from(nodes, consts, roots, n):
+    arr = np.array(nodes, dtype=I.NODE_DTYPE)
+    return I.Tape(arr, np.array(consts, dtype=np.float64), np.array(roots, dtype=np.int32), n)
+
+
+@pytest.mark.parametrize("op", ["div", "sqrt", "log", "nan"])
+def test_domain_violation_flags_subdomain(op):
+    # x in [-1, 1]: 1/x, sqrt(x) and log(x) leave their domains; a NaN constant poisons the bound
+    if op == "div":
+        nodes = [(I.CONST, 0, -1), (I.VAR, 0, -1), (I.DIV, 0, 1)]
+        consts = [1.0]
+    elif op == "sqrt":
+        nodes = [(I.VAR, 0, -1), (I.SQRT, 0, -1)]
+        consts = []
+    elif op == "log":
+        nodes = [(I.VAR, 0, -1), (I.LOG, 0, -1)]
+        consts = []
+    else:
+        nodes = [(I.CONST, 0, -1), (I.VAR, 0, -1), (I.ADD, 0, 1)]
+        consts = [float("nan")]
+    t = _tape_from(nodes, consts, [len(nodes) - 1, 1 if op != "nan" else 1], 1)
+    res = O.bound(t, np.array([[-1.0, 1.0]]), [2])
+    # subdomain 0 = [-1, 0] violates every domain; all its roots become [-inf, inf]
+    assert res["flags"][0] == 1
+    assert np.all(res["per_sub"][:, 0, 0] == -np.inf) and np.all(res["per_sub"][:, 1, 0] == np.inf)
+    if op in ("sqrt", "log"):
+        # [0, 1]: sqrt is fine; log still sees a zero end point
+        assert res["flags"][1] == (1 if op == "log" else 0)
