@@ -1,0 +1,135 @@
+/*
+ * mvf.h -- C ABI of the MI355X (gfx950) subdomain Mean-Value-Form bounding library.
+ *
+ * Method (arXiv 2507.20769): a branch-and-bound node's box is temporarily
+ * split into many subdomains (Sec. 3.1 Step 1; Sec. 2.2 "splitting
+ * technique", step i; Sec. 3.1.1 uniform partitioning, dimension 1 varying
+ * fastest).  On every subdomain X_k each function of the problem (objective
+ * first, then constraints; Sec. 3.1 NLP) is bounded in outward-rounded FP64
+ * interval arithmetic (Sec. 2.2 "Interval Arithmetic", Sec. 3.2): the Natural
+ * Interval Extension NIE(X_k), an interval gradient enclosure G(X_k) and the
+ * Mean Value Form  f([c]) + sum_i G_i * (X_{k,i} - c_i)  (Sec. 2.2,
+ * Definition "Mean Value Form"), intersected with the NIE.  The bounds are
+ * then reduced to their interval hull over the subdomains (Sec. 3.1 Step 3;
+ * Sec. 2.2 splitting step iii).
+ *
+ * Conventions
+ *   - Every pointer argument documented as "device" must point to memory on
+ *     the current HIP device; "host" pointers are read during the call only.
+ *   - The caller owns all buffers and streams.  The library allocates device
+ *     memory only inside mvf_tape_create and mvf_batch_graph_create, and frees
+ *     it in the matching destroy call.
+ *   - Launch entry points are asynchronous on the given stream and return
+ *     after enqueueing; results are valid after the caller synchronises.
+ *   - No entry point aborts or throws.  Errors are returned as negative
+ *     codes; mvf_last_error() gives a thread-local message for the last
+ *     failing call.  Asynchronous device faults surface at the caller's next
+ *     synchronisation.
+ *   - Intervals are stored as (lo, hi) pairs of doubles.
+ */
+#ifndef MVF_H
+#define MVF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define MVF_OK 0
+#define MVF_EINVAL (-1)   /* bad argument (null pointer, size, mode) */
+#define MVF_ETAPE (-2)    /* malformed tape */
+#define MVF_ELIMIT (-3)   /* tape, dimension or subdomain count beyond a library limit */
+#define MVF_ENOMEM (-4)   /* device allocation failed */
+#define MVF_EHIP (-5)     /* a HIP runtime call failed (message kept) */
+#define MVF_ENOTSUP (-6)  /* current device is not gfx950 */
+
+/* ---- limits --------------------------------------------------------- */
+#define MVF_MAX_VARS 64
+#define MVF_MAX_ROOTS 16
+#define MVF_MAX_NODES 65535
+#define MVF_MAX_TABLE 4096      /* sum over dimensions of the split counts */
+
+/* ---- tape ------------------------------------------------------------
+ * A factorable function is given as a DAG in SSA order (Sec. 2.2
+ * "Factorable function"; Sec. 3.2, Fig. DAG_NIE): node i may only use nodes
+ * with smaller indices.  One DAG holds all functions; roots[] names them.
+ *   VAR   a = variable index in [0, n_vars)
+ *   CONST a = index into consts[] (finite)
+ *   ADD SUB MUL DIV  z = node a (op) node b
+ *   SQR SQRT EXP LOG z = op(node a)
+ */
+enum { MVF_VAR = 0, MVF_CONST = 1, MVF_ADD = 2, MVF_SUB = 3, MVF_MUL = 4, MVF_DIV = 5,
+       MVF_SQR = 6, MVF_SQRT = 7, MVF_EXP = 8, MVF_LOG = 9 };
+
+typedef struct { int32_t op, a, b; } mvf_node;
+typedef struct mvf_tape mvf_tape;
+
+/* Bound kind per subdomain: NIE only, MVF only, or MVF intersected with NIE. */
+enum { MVF_MODE_NIE = 0, MVF_MODE_MVF = 1, MVF_MODE_BOTH = 2 };
+/* Interval gradient: tangent (forward) mode, reverse-mode adjoint, or library choice. */
+enum { MVF_GRAD_FWD = 0, MVF_GRAD_REV = 1, MVF_GRAD_AUTO = 2 };
+
+/*
+ * Validate the tape (SSA order, opcodes, operand ranges, finite constants,
+ * roots), compile one register program per root (its cone in index order,
+ * with slots assigned by linear-scan liveness) and upload it to the current
+ * device.  Host arrays are copied; the library owns *out.
+ * Returns MVF_ETAPE for a malformed tape, MVF_ELIMIT when a limit above is
+ * exceeded or a root needs more register slots than the slot file holds.
+ */
+int mvf_tape_create(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
+                    int32_t n_vars, const int32_t *roots, int32_t n_roots, mvf_tape **out);
+
+/* Same validation and compilation without touching any device (host only). */
+typedef struct {
+    int32_t n_vars, n_roots;
+    int32_t n_instr;          /* total instructions over all root programs */
+    int32_t max_slots;        /* largest live set of any root program */
+    int32_t tangent_chunk;    /* tangent components carried per forward pass */
+    int64_t ref_ops_fwd;      /* reference FP64 op count per subdomain, forward mode */
+    int64_t ref_ops_rev;      /* reference FP64 op count per subdomain, reverse mode */
+} mvf_tape_stats;
+int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
+                   int32_t n_vars, const int32_t *roots, int32_t n_roots, mvf_tape_stats *stats);
+
+int mvf_tape_stats_get(const mvf_tape *tape, mvf_tape_stats *stats);
+int mvf_tape_destroy(mvf_tape *tape);
+
+/* ---- bounding one box ----------------------------------------------- */
+typedef struct {
+    const double *box;        /* device [n][2]: lo_i, hi_i with lo_i <= hi_i */
+    const int32_t *splits;    /* host [n]: split count s_i >= 1 per dimension */
+    int32_t mode;             /* MVF_MODE_* */
+    int32_t grad;             /* MVF_GRAD_* */
+    double *reduced;          /* device [m][2]: hull of the subdomain bounds of each root */
+    int64_t *argmin;          /* device [1] or NULL: smallest k attaining reduced[0][0] */
+    double *per_sub;          /* device [m][2][S] or NULL: bounds of every subdomain */
+    uint32_t *flags;          /* device [S] or NULL: 1 where a domain violation or NaN
+                                 made every bound of that subdomain [-inf, +inf] */
+    void *workspace;          /* device scratch of mvf_bound_workspace() bytes */
+    size_t workspace_bytes;
+} mvf_bound_args;
+
+/*
+ * Subdomain k (0 <= k < S = prod s_i) has indices j_i = (k / prod_{l<i} s_l) mod s_i
+ * and box X_{k,i} = [b_{i,j_i}, b_{i,j_i+1}] with breakpoints b_{i,0} = lo_i,
+ * b_{i,s_i} = hi_i, b_{i,j} = min(hi_i, RN(lo_i + RN(j * RN(RN(hi_i - lo_i) / s_i))));
+ * centre c_i = RN(0.5 * RN(b_lo + b_hi)).
+ * Workspace bytes needed by mvf_bound for this tape and these splits.
+ */
+int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mode, int32_t grad,
+                        size_t *bytes);
+int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
+
+/* ---- diagnostics ----------------------------------------------------- */
+const char *mvf_strerror(int code);
+const char *mvf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MVF_H */

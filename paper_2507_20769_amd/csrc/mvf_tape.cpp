@@ -1,0 +1,181 @@
+// mvf_tape.cpp -- tape validation and compilation into per-root register programs.
+//
+// The DAG of a factorable function (Sec. 2.2 "Factorable function"; Sec. 3.2,
+// Fig. DAG_NIE) is evaluated by every lane on its own subdomain.  Each root's
+// cone (the nodes it depends on) becomes a straight program in node-index
+// order.  Variable and constant leaves are folded into operand fields, and
+// intermediate results are assigned register slots by linear-scan liveness,
+// so one program serves value passes and tangent passes of any chunk size.
+#include <math.h>
+
+#include <algorithm>
+#include <cstdio>
+
+#include "mvf_internal.h"
+
+namespace mvf {
+
+namespace {
+
+bool is_leaf(int op) { return op == MVF_VAR || op == MVF_CONST; }
+bool is_binary(int op) { return op >= MVF_ADD && op <= MVF_DIV; }
+bool is_unary(int op) { return op >= MVF_SQR && op <= MVF_LOG; }
+
+// Reference FP64 op counts (value, per tangent component, adjoint) of one
+// instruction; interval products use the four-endpoint form, a constant
+// operand makes + - * / cheap.
+void ref_cost(int op, bool a_const, bool b_const, int *val, int *tan, int *adj) {
+    bool c = a_const || b_const;
+    switch (op) {
+    case MVF_ADD: case MVF_SUB:
+        *val = 2; *tan = c ? 0 : 2; *adj = c ? 2 : 4; return;
+    case MVF_MUL:
+        if (c) { *val = 2; *tan = 2; *adj = 4; } else { *val = 14; *tan = 30; *adj = 32; }
+        return;
+    case MVF_DIV:
+        if (b_const) { *val = 2; *tan = 2; *adj = 4; } else { *val = 14; *tan = 30; *adj = 32; }
+        return;
+    case MVF_SQR: *val = 5; *tan = 14; *adj = 18; return;
+    case MVF_SQRT: *val = 2; *tan = 14; *adj = 18; return;
+    case MVF_EXP: case MVF_LOG: *val = 2; *tan = 14; *adj = 16; return;
+    default: *val = 0; *tan = 0; *adj = 0;
+    }
+}
+
+int fail(std::string *err, int code, const char *fmt, long a = 0, long b = 0) {
+    if (err) {
+        char buf[256];
+        snprintf(buf, sizeof buf, fmt, a, b);
+        *err = buf;
+    }
+    return code;
+}
+
+}  // namespace
+
+int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                 const int32_t *roots, int32_t n_roots, Compiled *out, std::string *err) {
+    if (!nodes || !roots || !out) return fail(err, MVF_EINVAL, "null tape array");
+    if (n_nodes < 1 || n_nodes > MVF_MAX_NODES) return fail(err, MVF_ELIMIT, "n_nodes %ld outside [1, %ld]", n_nodes, MVF_MAX_NODES);
+    if (n_vars < 1 || n_vars > MVF_MAX_VARS) return fail(err, MVF_ELIMIT, "n_vars %ld outside [1, %ld]", n_vars, MVF_MAX_VARS);
+    if (n_roots < 1 || n_roots > MVF_MAX_ROOTS) return fail(err, MVF_ELIMIT, "n_roots %ld outside [1, %ld]", n_roots, MVF_MAX_ROOTS);
+    if (n_consts < 0 || (n_consts > 0 && !consts)) return fail(err, MVF_EINVAL, "bad constant array");
+    for (int i = 0; i < n_nodes; ++i) {
+        const mvf_node &nd = nodes[i];
+        if (nd.op < MVF_VAR || nd.op > MVF_LOG) return fail(err, MVF_ETAPE, "node %ld: bad opcode %ld", i, nd.op);
+        if (nd.op == MVF_VAR && (nd.a < 0 || nd.a >= n_vars))
+            return fail(err, MVF_ETAPE, "node %ld: variable index %ld out of range", i, nd.a);
+        if (nd.op == MVF_CONST) {
+            if (nd.a < 0 || nd.a >= n_consts) return fail(err, MVF_ETAPE, "node %ld: constant index %ld out of range", i, nd.a);
+            if (!isfinite(consts[nd.a])) return fail(err, MVF_ETAPE, "node %ld: constant %ld is not finite", i, nd.a);
+        }
+        if ((is_binary(nd.op) || is_unary(nd.op)) && (nd.a < 0 || nd.a >= i))
+            return fail(err, MVF_ETAPE, "node %ld: operand a=%ld is not an earlier node", i, nd.a);
+        if (is_binary(nd.op) && (nd.b < 0 || nd.b >= i))
+            return fail(err, MVF_ETAPE, "node %ld: operand b=%ld is not an earlier node", i, nd.b);
+    }
+    for (int r = 0; r < n_roots; ++r)
+        if (roots[r] < 0 || roots[r] >= n_nodes) return fail(err, MVF_ETAPE, "root %ld = %ld is not a node", r, roots[r]);
+
+    Compiled C;
+    C.n_vars = n_vars;
+    std::vector<uint8_t> in_cone(n_nodes);
+    std::vector<int32_t> slot_of(n_nodes, -1), last_use(n_nodes, -1);
+    int64_t sum_val = 0, sum_tan = 0, sum_adj = 0, n_ops = 0;
+
+    for (int r = 0; r < n_roots; ++r) {
+        RootProg P;
+        P.begin = (int32_t)C.instr.size();
+        std::fill(in_cone.begin(), in_cone.end(), 0);
+        in_cone[roots[r]] = 1;
+        for (int i = roots[r]; i >= 0; --i) {
+            if (!in_cone[i]) continue;
+            if (is_binary(nodes[i].op) || is_unary(nodes[i].op)) in_cone[nodes[i].a] = 1;
+            if (is_binary(nodes[i].op)) in_cone[nodes[i].b] = 1;
+        }
+        const mvf_node &rn = nodes[roots[r]];
+        if (is_leaf(rn.op)) {
+            uint32_t ak = rn.op == MVF_VAR ? K_VAR : K_CONST;
+            double k = rn.op == MVF_CONST ? consts[rn.a] : 0.0;
+            C.instr.push_back(make_instr(I_LOAD, ak, rn.op == MVF_VAR ? (uint32_t)rn.a : 0, K_SLOT, 0, 0, k));
+            P.len = 1; P.result_slot = 0; P.n_slots = 1;
+            C.roots.push_back(P);
+            continue;
+        }
+        // program position of each arithmetic node, then last uses
+        std::vector<int32_t> order;
+        for (int i = 0; i <= roots[r]; ++i)
+            if (in_cone[i] && !is_leaf(nodes[i].op)) order.push_back(i);
+        std::vector<int32_t> pos(n_nodes, -1);
+        for (size_t p = 0; p < order.size(); ++p) pos[order[p]] = (int32_t)p;
+        for (int i : order) last_use[i] = -1;
+        for (size_t p = 0; p < order.size(); ++p) {
+            const mvf_node &nd = nodes[order[p]];
+            if (!is_leaf(nodes[nd.a].op)) last_use[nd.a] = (int32_t)p;
+            if (is_binary(nd.op) && !is_leaf(nodes[nd.b].op)) last_use[nd.b] = (int32_t)p;
+        }
+        // linear scan over a pool of slots (lowest free id first)
+        std::vector<uint8_t> busy;
+        auto take = [&]() {
+            for (size_t s = 0; s < busy.size(); ++s)
+                if (!busy[s]) { busy[s] = 1; return (int32_t)s; }
+            busy.push_back(1);
+            return (int32_t)busy.size() - 1;
+        };
+        for (size_t p = 0; p < order.size(); ++p) {
+            int i = order[p];
+            const mvf_node &nd = nodes[i];
+            const bool bin = is_binary(nd.op);
+            const mvf_node &na = nodes[nd.a];
+            const mvf_node *nb = bin ? &nodes[nd.b] : nullptr;
+            uint32_t ak, a, bk = K_SLOT, b = 0;
+            double k = 0.0;
+            bool a_const = na.op == MVF_CONST, b_const = bin && nb->op == MVF_CONST;
+            int32_t tmp = -1;
+            if (a_const && b_const) {        // materialise operand a so at most one constant remains
+                tmp = take();
+                C.instr.push_back(make_instr(I_LOAD, K_CONST, 0, K_SLOT, 0, (uint32_t)tmp, consts[na.a]));
+                ak = K_SLOT; a = (uint32_t)tmp;
+            } else if (na.op == MVF_VAR) { ak = K_VAR; a = (uint32_t)na.a; }
+            else if (a_const) { ak = K_CONST; a = 0; k = consts[na.a]; }
+            else { ak = K_SLOT; a = (uint32_t)slot_of[nd.a]; }
+            if (bin) {
+                if (nb->op == MVF_VAR) { bk = K_VAR; b = (uint32_t)nb->a; }
+                else if (b_const) { bk = K_CONST; b = 0; k = consts[nb->a]; }
+                else { bk = K_SLOT; b = (uint32_t)slot_of[nd.b]; }
+            }
+            // release operands dying here, then allocate the result (it may reuse them)
+            if (tmp >= 0) busy[tmp] = 0;
+            if (!is_leaf(na.op) && last_use[nd.a] == (int32_t)p) busy[slot_of[nd.a]] = 0;
+            if (bin && !is_leaf(nb->op) && last_use[nd.b] == (int32_t)p) busy[slot_of[nd.b]] = 0;
+            int32_t d = take();
+            slot_of[i] = d;
+            C.instr.push_back(make_instr((uint32_t)nd.op, ak, a, bk, b, (uint32_t)d, k));
+            int cv, ct, ca;
+            ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
+            sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
+            if (nd.op == MVF_SQR || nd.op == MVF_SQRT) sum_val += 2;   // 2U or 1/(2Z), once per op
+        }
+        P.len = (int32_t)C.instr.size() - P.begin;
+        P.result_slot = slot_of[roots[r]];
+        P.n_slots = (int32_t)busy.size();
+        C.roots.push_back(P);
+    }
+    for (auto &P : C.roots) C.max_slots = std::max(C.max_slots, P.n_slots);
+
+    // tangent components per forward pass: the largest chunk whose slots fit
+    const int avail = usable_dwords(n_roots);
+    C.chunk = 0;
+    for (int c = MAX_CHUNK; c >= 1; --c)
+        if (C.max_slots * (4 + 4 * c) <= avail) { C.chunk = c; break; }
+    if (C.max_slots * 4 > avail)
+        return fail(err, MVF_ELIMIT, "a root needs %ld live slots; the slot file holds %ld values", C.max_slots, avail / 4);
+
+    const int64_t n = n_vars, m = n_roots;
+    C.ref_fwd = sum_val + n * sum_tan + 2 * n_ops + m * (16 * n + 2) + 10 * n;
+    C.ref_rev = sum_val + sum_adj + 2 * n_ops + m * (16 * n + 2) + 10 * n;
+    *out = std::move(C);
+    return MVF_OK;
+}
+
+}  // namespace mvf

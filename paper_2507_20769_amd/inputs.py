@@ -25,7 +25,10 @@ whose weights are not public, Sec. 4.1 and Sec. 4.3)
 Random DAG tapes with the op mix add .20, sub .15, mul .25, div .08, sqr .12,
 sqrt .07, log .07, exp .06.  Operands come with p=.70 from the last ``window``
 arithmetic nodes of the same function (an ANN-like, layer-local live set),
-p=.25 from a variable and p=.05 from a constant U[-2,2].  Guards keep every
+p=.25 from a variable and p=.05 from a constant U[-2,2].  Every result is used:
+a result about to leave the window unused is taken first, half of the window
+draws go to unused results, and what is left at the end is summed into the
+root, so the whole tape lies in the root's cone (no dead code).  Guards keep every
 evaluation finite on any sub-box of the root box:
 
 * denominators, sqrt and log arguments are ``sqr(u) + c`` with c ~ U[0.5, 2],
@@ -198,13 +201,27 @@ def _random_function(tb: TapeBuilder, rng: np.random.Generator, n: int, budget: 
         used_ops[0] += 1
         return z
 
+    pending: List[int] = []        # results not yet used as an operand (oldest first)
+
+    def take_recent() -> int:
+        lo = max(0, len(recent) - window)
+        # a result about to leave the window unused is consumed now; otherwise
+        # half of the draws go to a pending result, so every node feeds the root
+        if pending and pending[0] <= recent[lo]:
+            return pending.pop(0)
+        if pending and rng.random() < 0.5:
+            return pending.pop(int(rng.integers(0, len(pending))))
+        z = recent[int(rng.integers(lo, len(recent)))]
+        if z in pending:
+            pending.remove(z)
+        return z
+
     def pick(allow_const: bool) -> int:
         if unused:
             return vnode(unused.pop())
         u = rng.random()
         if recent and u < 0.70:
-            lo = max(0, len(recent) - window)
-            return recent[int(rng.integers(lo, len(recent)))]
+            return take_recent()
         if allow_const and u >= 0.95:
             return cnode(float(rng.uniform(-2.0, 2.0)))
         return vnode(int(rng.integers(0, n)))
@@ -272,6 +289,11 @@ def _random_function(tb: TapeBuilder, rng: np.random.Generator, n: int, budget: 
                 z = emit(EXP, t, -1, np.exp(vals[t]), np.exp(mag[t]))
             last = renorm(z)
             recent.append(last)
+            pending.append(last)
+        pending.remove(last)
+        while pending:                                 # every result reaches the root
+            a = pending.pop(0)
+            last = emit(ADD, last, a, vals[last] + vals[a], mag[last] + mag[a])
         while unused:                                  # every variable appears
             a = vnode(unused.pop())
             last = emit(ADD, last, a, vals[last] + vals[a], mag[last] + mag[a])

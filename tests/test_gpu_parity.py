@@ -1,0 +1,129 @@
+"""GPU parity: libmvf (through the C ABI) against the CPU oracle, element by element.
+
+Bit-exact (==) where the tape uses only + - * / sqr sqrt; within 1e-12 of the
+root's scale where exp or log appear (the two sides call different libms).
+Every case also checks that the GPU's own bounds enclose sampled values.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_20769_amd import inputs as I
+
+from gpu_util import assert_parity, gpu_bound, has_transcendental, scale_of
+
+pytestmark = pytest.mark.gpu
+
+MODES = {"nie": O.MODE_NIE, "mvf": O.MODE_MVF, "both": O.MODE_BOTH}
+
+
+def _compare(tape, box, splits, mode="both", per_sub=True):
+    print(f"[case] n={tape.n_vars} nodes={tape.n_nodes} splits={list(splits)} mode={mode}", flush=True)
+    g = gpu_bound(tape, box, splits, mode=mode, per_sub=per_sub)
+    o = O.bound(tape, box, splits, mode=MODES[mode], per_sub=per_sub, nthreads=8)
+    exact = not has_transcendental(tape)
+    sc = scale_of(O.bound(tape, box, splits, mode=O.MODE_NIE, per_sub=False, nthreads=8)["reduced"])
+    if per_sub:
+        assert_parity(g["per_sub"], o["per_sub"], exact, sc, "per_sub")
+        assert np.array_equal(g["flags"].astype(np.uint32), o["flags"])
+        # the reduction is the hull of the GPU's own per-subdomain output, bitwise
+        assert np.array_equal(g["reduced"][:, 0], g["per_sub"][:, 0, :].min(axis=1))
+        assert np.array_equal(g["reduced"][:, 1], g["per_sub"][:, 1, :].max(axis=1))
+        lo0 = g["per_sub"][0, 0, :]
+        assert int(g["argmin"][0]) == int(np.argmax(lo0 == lo0.min()))
+    assert_parity(g["reduced"], o["reduced"], exact, sc, "reduced")
+    if exact:
+        assert int(g["argmin"][0]) == o["argmin"]
+    return g, o
+
+
+def test_cubic_refinement_table():
+    # the DAG example of Sec. 3.2 on [-1, 2]: N = 1 gives NIE [-23, 32], MVF [-55.375, 49.625]
+    t = I.cubic_tape()
+    box = np.array([[-1.0, 2.0]])
+    g = gpu_bound(t, box, [1], mode="nie")
+    assert g["reduced"][0].tolist() == [-23.0, 32.0]
+    g = gpu_bound(t, box, [1], mode="mvf")
+    assert g["reduced"][0].tolist() == [-55.375, 49.625]
+    for N in (1, 2, 3, 8, 64, 255, 256, 1000):
+        for mode in MODES:
+            _compare(t, box, [N], mode)
+
+
+def test_tiny_workload_full():
+    w = I.tiny(1)
+    for mode in MODES:
+        _compare(w.tape, w.box, w.splits, mode)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_rational_tapes_ragged(seed):
+    # + - * / sqr sqrt only; 5*7*11 = 385 subdomains: a full 256-lane block plus a ragged tail
+    rng = np.random.default_rng(seed)
+    t = I.random_small_tape(seed, n=3, ops=60, n_con=2, con_ops=20, window=8)
+    nodes = t.nodes.copy()
+    nodes["op"][nodes["op"] == I.EXP] = I.SQR      # exp -> sqr, log (positive argument) -> sqrt
+    nodes["op"][nodes["op"] == I.LOG] = I.SQRT
+    t = I.Tape(nodes, t.consts, t.roots, t.n_vars)
+    box = np.array([[-2.0, 2.0], [-1.5, 2.5], [-2.0, 1.0]]) + rng.uniform(-0.3, 0.3, (3, 1))
+    for mode in MODES:
+        _compare(t, box, [5, 7, 11], mode)
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_random_tapes_with_exp_log(seed):
+    t = I.random_small_tape(seed, n=4, ops=80, n_con=3, con_ops=25, window=8)
+    assert has_transcendental(t)
+    box = np.array([[-2.0, 2.0]] * 4)
+    _compare(t, box, [4, 5, 3, 6], "both")
+
+
+def test_peaks_function():
+    t = I.peaks_tape()
+    _compare(t, np.array([[-3.0, 3.0], [-3.0, 3.0]]), [40, 37], "both")
+
+
+def test_single_subdomain_and_degenerate_box():
+    t = I.random_small_tape(9, n=2, ops=30, n_con=1, con_ops=10)
+    _compare(t, np.array([[-1.0, 1.0], [0.5, 0.5]]), [1, 1], "both")      # zero-width dimension
+    _compare(t, np.array([[-1.0, 1.0], [0.5, 0.5]]), [3, 1], "both")
+
+
+def test_domain_violations_flag_subdomains():
+    # 1/x on [-1, 1]: the subdomains touching 0 are flagged and bounded by [-inf, inf]
+    nodes = np.array([(I.CONST, 0, -1), (I.VAR, 0, -1), (I.DIV, 0, 1), (I.VAR, 1, -1), (I.SQRT, 3, -1),
+                      (I.ADD, 2, 4)], dtype=I.NODE_DTYPE)
+    t = I.Tape(nodes, np.array([1.0]), np.array([5, 4], dtype=np.int32), 2)
+    g, o = _compare(t, np.array([[-1.0, 1.0], [-0.5, 1.0]]), [4, 3], "both")
+    assert g["flags"].sum() > 0
+
+
+def test_mid_workload_full_size_sampled():
+    # the 262,144-subdomain mid workload in the benchmark's launch; 512 sampled subdomains
+    # are recomputed by the oracle one by one
+    w = I.mid(1)
+    g = gpu_bound(w.tape, w.box, w.splits, mode="both")
+    S = w.n_sub
+    rng = np.random.default_rng(0)
+    ks = np.unique(np.concatenate([rng.choice(S, 500, replace=False), [0, S - 1, 255, 256]]))
+    o = O.bound(w.tape, w.box, w.splits, mode=O.MODE_BOTH, ks=ks, nthreads=8)
+    sc = scale_of(O.bound(w.tape, w.box, w.splits, mode=O.MODE_NIE, ks=ks, per_sub=False, nthreads=8)["reduced"])
+    assert_parity(g["per_sub"][:, :, ks], o["per_sub"], not has_transcendental(w.tape), sc, "mid sampled")
+    assert np.array_equal(g["reduced"][:, 0], g["per_sub"][:, 0, :].min(axis=1))
+    assert np.array_equal(g["reduced"][:, 1], g["per_sub"][:, 1, :].max(axis=1))
+    assert not g["flags"].any()
+
+
+def test_gpu_bounds_enclose_samples():
+    t = I.random_small_tape(7, n=3, ops=50, n_con=2, con_ops=15)
+    box = np.array([[-2.0, 2.0]] * 3)
+    splits = np.array([4, 4, 4])
+    g = gpu_bound(t, box, splits, mode="both")
+    rng = np.random.default_rng(1)
+    for k in range(0, 64, 5):
+        X, c = O.subdomain(box, splits, k)
+        pts = X[:, 0] + (X[:, 1] - X[:, 0]) * rng.random((300, 3))
+        v = I.eval_points_np(t, pts)
+        sl = 1e-12 * np.maximum(1, np.abs(v).max(axis=0))
+        assert np.all(g["per_sub"][:, 0, k] - sl <= v.min(axis=0))
+        assert np.all(v.max(axis=0) <= g["per_sub"][:, 1, k] + sl)
