@@ -313,45 +313,56 @@ static int eval_tangents(const orc_tape *t, const ivl *X, ivl *val, ivl *tan) {
 }
 
 /* Reverse sweep over the nodes with nonzero cone mask, in descending index,
- * starting from adjoints adj[] (already seeded).  Accumulates variable
- * adjoints into G[n].  val holds the values from eval_values. */
+ * starting from adjoints adj[] (already seeded).  A contribution to a
+ * variable leaf goes straight into that variable's gradient accumulator G[]
+ * (in sweep order); contributions to constants are dropped.  val holds the
+ * values from eval_values. */
+static void acc_to(const orc_tape *t, int x, ivl c, ivl *adj, ivl *G) {
+    const orc_node *nd = &t->nodes[x];
+    if (nd->op == OP_VAR) G[nd->a] = iadd(G[nd->a], c);
+    else if (nd->op != OP_CONST) adj[x] = iadd(adj[x], c);
+}
+static void sub_from(const orc_tape *t, int x, ivl c, ivl *adj, ivl *G) {
+    const orc_node *nd = &t->nodes[x];
+    if (nd->op == OP_VAR) G[nd->a] = isub(G[nd->a], c);
+    else if (nd->op != OP_CONST) adj[x] = isub(adj[x], c);
+}
+
 static void reverse_sweep(const orc_tape *t, const uint8_t *mask, const ivl *val, ivl *adj, ivl *G) {
     for (int i = t->n_nodes - 1; i >= 0; --i) {
         if (!mask[i]) continue;
         const orc_node *nd = &t->nodes[i];
-        ivl zb = adj[i], T, R;
+        ivl zb = adj[i], T;
         switch (nd->op) {
-        case OP_VAR: G[nd->a] = iadd(G[nd->a], zb); break;
-        case OP_CONST: break;
+        case OP_VAR: case OP_CONST: break;        /* handled by the consumers */
         case OP_ADD:   /* ub += zb; vb += zb */
-            adj[nd->a] = iadd(adj[nd->a], zb);
-            adj[nd->b] = iadd(adj[nd->b], zb);
+            acc_to(t, nd->a, zb, adj, G);
+            acc_to(t, nd->b, zb, adj, G);
             break;
         case OP_SUB:   /* ub += zb; vb -= zb */
-            adj[nd->a] = iadd(adj[nd->a], zb);
-            adj[nd->b] = isub(adj[nd->b], zb);
+            acc_to(t, nd->a, zb, adj, G);
+            sub_from(t, nd->b, zb, adj, G);
             break;
         case OP_MUL:   /* ub += zb*V; vb += zb*U */
-            adj[nd->a] = iadd(adj[nd->a], imul(zb, val[nd->b]));
-            adj[nd->b] = iadd(adj[nd->b], imul(zb, val[nd->a]));
+            acc_to(t, nd->a, imul(zb, val[nd->b]), adj, G);
+            acc_to(t, nd->b, imul(zb, val[nd->a]), adj, G);
             break;
         case OP_DIV:   /* t = zb*(1/V); ub += t; vb -= t*Z */
             T = imul(zb, irecip(val[nd->b]));
-            adj[nd->a] = iadd(adj[nd->a], T);
-            adj[nd->b] = isub(adj[nd->b], imul(T, val[i]));
+            acc_to(t, nd->a, T, adj, G);
+            sub_from(t, nd->b, imul(T, val[i]), adj, G);
             break;
         case OP_SQR:   /* ub += zb*(2U) */
-            adj[nd->a] = iadd(adj[nd->a], imul(zb, itwice(val[nd->a])));
+            acc_to(t, nd->a, imul(zb, itwice(val[nd->a])), adj, G);
             break;
         case OP_SQRT:  /* ub += zb*1/(2Z) */
-            R = isqrt_deriv(val[i]);
-            adj[nd->a] = iadd(adj[nd->a], imul(zb, R));
+            acc_to(t, nd->a, imul(zb, isqrt_deriv(val[i])), adj, G);
             break;
         case OP_EXP:   /* ub += zb*Z */
-            adj[nd->a] = iadd(adj[nd->a], imul(zb, val[i]));
+            acc_to(t, nd->a, imul(zb, val[i]), adj, G);
             break;
         case OP_LOG:   /* ub += zb*(1/U) */
-            adj[nd->a] = iadd(adj[nd->a], imul(zb, irecip(val[nd->a])));
+            acc_to(t, nd->a, imul(zb, irecip(val[nd->a])), adj, G);
             break;
         }
     }
@@ -361,7 +372,7 @@ static void reverse_sweep(const orc_tape *t, const uint8_t *mask, const ivl *val
 static int gradient_rev(const orc_tape *t, int r, const ivl *val, ivl *adj, ivl *G) {
     for (int i = 0; i < t->n_nodes; ++i) adj[i] = I(0, 0);
     for (int j = 0; j < t->n_vars; ++j) G[j] = I(0, 0);
-    adj[t->roots[r]] = I(1, 1);
+    acc_to(t, t->roots[r], I(1, 1), adj, G);
     reverse_sweep(t, t->cone + (size_t)r * t->n_nodes, val, adj, G);
     return 0;
 }
@@ -652,7 +663,7 @@ int orc_vjp_points(const orc_node *nodes, int32_t n_nodes, const double *consts,
         for (int j = 0; j < n_vars; ++j) G[j] = I(0, 0);
         for (int r = 0; r < n_roots; ++r) {
             double g = gout[b * n_roots + r];
-            adj[roots[r]] = iadd(adj[roots[r]], I(g, g));
+            acc_to(&t, roots[r], I(g, g), adj, G);
         }
         if (!bad) reverse_sweep(&t, t.live, val, adj, G);
         for (int j = 0; j < n_vars; ++j) {
