@@ -89,7 +89,8 @@ typedef struct {
     int32_t n_vars, n_roots;
     int32_t n_instr;          /* total instructions over all root programs */
     int32_t max_slots;        /* largest live set of any root program */
-    int32_t tangent_chunk;    /* tangent components carried per forward pass */
+    int32_t tangent_chunk;    /* tangent components carried per forward pass (0: forward mode unavailable) */
+    int32_t max_records;      /* reverse-mode tape records per subdomain (largest root program) */
     int64_t ref_ops_fwd;      /* reference FP64 op count per subdomain, forward mode */
     int64_t ref_ops_rev;      /* reference FP64 op count per subdomain, reverse mode */
 } mvf_tape_stats;
@@ -123,7 +124,86 @@ typedef struct {
  */
 int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mode, int32_t grad,
                         size_t *bytes);
+/*
+ * Bound every subdomain of one box.  grad selects the interval gradient of
+ * the MVF: MVF_GRAD_FWD = tangent mode (the paper's choice, Sec. 3.2),
+ * MVF_GRAD_REV = reverse-mode interval adjoint (per-lane tape of local
+ * partials in the workspace), MVF_GRAD_AUTO = the cheaper of the two by the
+ * reference op count.  Returns MVF_ELIMIT when the forward mode is asked for
+ * a tape whose live set leaves no room for tangent components.
+ */
 int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
+
+/* ---- tuning ----------------------------------------------------------- */
+typedef struct {
+    int32_t grad;             /* MVF_GRAD_FWD or MVF_GRAD_REV; other values: keep the call's choice */
+    int32_t chunk;            /* tangent components per forward pass (1 .. tangent_chunk); 0: default */
+    int32_t grid_blocks;      /* persistent workgroups of a batched launch; 0: two per compute unit */
+    float best_ms;            /* written by mvf_autotune: time of the chosen configuration */
+} mvf_tuning;
+
+/*
+ * Adaptive partitioning (Sec. 3.1.2): the largest uniform split N with
+ * N^n <= budget, then +1 on one dimension at a time, the one with the
+ * largest relative width w_i / s_i first (ties to the lower index), while
+ * the product stays <= budget.  Host only; returns the subdomain count or a
+ * negative error code.
+ */
+int64_t mvf_adaptive_splits(int32_t n, const double *widths, int64_t budget, int32_t *splits);
+
+/* ---- batched bounding of many nodes ----------------------------------- */
+typedef struct {
+    int32_t n_nodes;          /* nodes in this call, 0 <= n_nodes <= max_nodes */
+    int32_t max_nodes;        /* capacity the workspace was sized for */
+    int64_t max_subdomains;   /* capacity: total subdomains over the nodes */
+    const double *boxes;      /* device [N][n][2] */
+    const int32_t *splits;    /* device [N][n] */
+    int32_t mode, grad;
+    double *reduced;          /* device [N][m][2]; NaN for an invalid node */
+    int64_t *argmin;          /* device [N] or NULL: per node, smallest k attaining reduced[i][0][0] */
+    int32_t *status;          /* device [N]: 0; 1 for a node with a split outside [1, 65535],
+                                 more than 2^40 subdomains or more than 1024 breakpoints; 2 for
+                                 every node when the batch exceeds max_subdomains (nothing runs) */
+    void *workspace;          /* device scratch of mvf_batch_workspace() bytes */
+    size_t workspace_bytes;
+} mvf_batch_args;
+
+int mvf_batch_workspace(const mvf_tape *tape, int32_t max_nodes, int64_t max_subdomains, int32_t mode,
+                        int32_t grad, const mvf_tuning *tuning, size_t *bytes);
+/*
+ * Bound every node of a batch in one persistent launch: per node the same
+ * result as mvf_bound on that node's box and splits, bit for bit.  The node
+ * list lives in device memory; work is split into chunks of 256 subdomains
+ * that persistent workgroups take from an atomic counter.  tuning may be NULL.
+ */
+int mvf_bound_batch(const mvf_tape *tape, const mvf_batch_args *args, const mvf_tuning *tuning,
+                    hipStream_t stream);
+
+/*
+ * A batched bound captured once in a HIP graph: {H2D of node count, boxes
+ * and splits from pinned staging} -> plan -> persistent kernel -> per-node
+ * reduction -> {D2H of reduced, argmin, status to pinned memory}.  Replays
+ * take the node count through device memory, so the graph is never
+ * re-instantiated.  create allocates all buffers; launch validates the staged
+ * splits on the host and enqueues one graph launch; results are valid after
+ * the caller synchronises the stream.
+ */
+typedef struct mvf_batch_graph mvf_batch_graph;
+int mvf_batch_graph_create(const mvf_tape *tape, int32_t max_nodes, int64_t max_subdomains, int32_t mode,
+                           int32_t grad, const mvf_tuning *tuning, hipStream_t stream, mvf_batch_graph **out);
+int mvf_batch_graph_staging(mvf_batch_graph *g, double **boxes, int32_t **splits);
+int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stream);
+int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int64_t **argmin,
+                           const int32_t **status);
+int mvf_batch_graph_destroy(mvf_batch_graph *g);
+
+/*
+ * Autotuner: times the batched launch on the given nodes (device arrays)
+ * for each gradient mode, tangent chunk and persistent grid size, and
+ * returns the fastest configuration.  Allocates temporary device memory.
+ */
+int mvf_autotune(const mvf_tape *tape, int32_t n_nodes, const double *boxes, const int32_t *splits,
+                 int64_t n_subdomains, int32_t mode, mvf_tuning *out, hipStream_t stream);
 
 /* ---- diagnostics ----------------------------------------------------- */
 const char *mvf_strerror(int code);

@@ -1,0 +1,611 @@
+// mvf_api.cpp -- the C ABI of libmvf (include/mvf.h): argument checks, workspace
+// layout, launches, the batched graph and the autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "mvf.h"
+#include "mvf_internal.h"
+#include "mvf_kernels.h"
+
+using namespace mvf;
+
+struct mvf_tape {
+    Compiled C;
+    Instr *d_prog = nullptr;
+    int device = 0;
+    int n_cu = 256;
+};
+
+struct mvf_batch_graph {
+    const mvf_tape *tape = nullptr;
+    int32_t max_nodes = 0;
+    int64_t max_subdomains = 0;
+    int32_t mode = 0, grad = 0;
+    mvf_tuning tuning{};
+    void *d_ws = nullptr;
+    size_t ws_bytes = 0;
+    double *d_boxes = nullptr;
+    int32_t *d_splits = nullptr, *d_count = nullptr, *d_status = nullptr;
+    double *d_reduced = nullptr;
+    int64_t *d_argmin = nullptr;
+    double *h_boxes = nullptr, *h_reduced = nullptr;
+    int32_t *h_splits = nullptr, *h_count = nullptr, *h_status = nullptr;
+    int64_t *h_argmin = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_err(hipError_t e, const char *what) { return set_err(MVF_EHIP, std::string(what) + ": " + hipGetErrorString(e)); }
+
+#define HIP_TRY(expr)                                    \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_err(_e, #expr); \
+    } while (0)
+
+int check_device(int *n_cu) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_err(MVF_ENOTSUP, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+    *n_cu = prop.multiProcessorCount;
+    return MVF_OK;
+}
+
+void fill_stats(const Compiled &C, mvf_tape_stats *st) {
+    st->n_vars = C.n_vars;
+    st->n_roots = (int32_t)C.roots.size();
+    st->n_instr = (int32_t)C.instr.size();
+    st->max_slots = C.max_slots;
+    st->tangent_chunk = C.chunk;
+    st->max_records = C.max_rec;
+    st->ref_ops_fwd = C.ref_fwd;
+    st->ref_ops_rev = C.ref_rev;
+}
+
+TapeArgs tape_args(const mvf_tape *t, int mode) {
+    TapeArgs T;
+    std::memset(&T, 0, sizeof T);
+    T.prog = t->d_prog;
+    T.n_instr = (int32_t)t->C.instr.size();
+    T.n_roots = (int32_t)t->C.roots.size();
+    T.n = t->C.n_vars;
+    T.mode = mode;
+    for (int r = 0; r < T.n_roots; ++r) {
+        T.root_begin[r] = t->C.roots[r].begin;
+        T.root_len[r] = t->C.roots[r].len;
+        T.root_slot[r] = t->C.roots[r].result_slot;
+        T.root_rec[r] = t->C.roots[r].n_rec;
+    }
+    return T;
+}
+
+// resolve the gradient mode: AUTO takes the cheaper reference cost; forward
+// needs at least one tangent component's slots
+int resolve_grad(const mvf_tape *t, int mode, int grad, const mvf_tuning *tu, bool *rev, int *chunk) {
+    if (tu && tu->grad >= MVF_GRAD_FWD && tu->grad <= MVF_GRAD_REV) grad = tu->grad;
+    if (mode == MVF_MODE_NIE) { *rev = false; *chunk = 0; return MVF_OK; }
+    if (grad == MVF_GRAD_AUTO) grad = (t->C.chunk == 0 || t->C.ref_rev < t->C.ref_fwd) ? MVF_GRAD_REV : MVF_GRAD_FWD;
+    *rev = grad == MVF_GRAD_REV;
+    *chunk = *rev ? 0 : t->C.chunk;
+    if (tu && !*rev && tu->chunk >= 1 && tu->chunk <= t->C.chunk) *chunk = tu->chunk;
+    if (!*rev && *chunk == 0)
+        return set_err(MVF_ELIMIT, "a root's live set is too large for tangent passes; use MVF_GRAD_REV");
+    return MVF_OK;
+}
+
+constexpr int MAX_GRID = 2048;
+
+int single_grid(const mvf_tape *t, int64_t S, bool rev) {
+    const int64_t need = (S + BLK - 1) / BLK;
+    const int cap = rev ? 2 * t->n_cu : MAX_GRID;       // the reverse tape scales with the grid
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
+}
+
+int batch_grid(const mvf_tape *t, const mvf_tuning *tu) {
+    if (tu && tu->grid_blocks > 0) return tu->grid_blocks;
+    return 2 * t->n_cu;
+}
+
+constexpr int BATCH_TAB_CAP = 512;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct SingleLayout {
+    size_t partial, lo0, k, rec, gacc, total;
+    bool g_lds;
+};
+
+SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total) {
+    const size_t m = t->C.roots.size();
+    SingleLayout L;
+    L.g_lds = grad_in_lds((int)t->C.instr.size(), tab_total, t->C.n_vars, (int)m);
+    L.partial = 0;
+    L.lo0 = align_up(L.partial + (size_t)grid * m * 2 * 8);
+    L.k = align_up(L.lo0 + (size_t)grid * 8);
+    L.rec = align_up(L.k + (size_t)grid * 8);
+    L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
+    L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
+    return L;
+}
+
+struct BatchLayout {
+    size_t node_S, item_off, counter, partial, lo0, k, rec, gacc, total;
+    bool g_lds;
+};
+
+BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int grid, bool rev) {
+    const size_t m = t->C.roots.size();
+    const size_t items = (size_t)(max_sub / BLK) + (size_t)max_nodes + 1;
+    BatchLayout L;
+    L.node_S = 0;
+    L.item_off = align_up(L.node_S + (size_t)max_nodes * 8);
+    L.counter = align_up(L.item_off + ((size_t)max_nodes + 1) * 8);
+    L.partial = align_up(L.counter + 8);
+    L.lo0 = align_up(L.partial + items * m * 2 * 8);
+    L.k = align_up(L.lo0 + items * 8);
+    L.rec = align_up(L.k + items * 8);
+    L.g_lds = grad_in_lds((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, (int)m);
+    L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
+    L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
+    return L;
+}
+
+int check_splits(const mvf_tape *t, const int32_t *splits, int64_t *S, int *tab_total) {
+    if (!splits) return set_err(MVF_EINVAL, "splits is null");
+    int64_t s = 1;
+    int tt = 0;
+    for (int i = 0; i < t->C.n_vars; ++i) {
+        if (splits[i] < 1 || splits[i] > 65535) return set_err(MVF_EINVAL, "split count outside [1, 65535]");
+        tt += splits[i];
+        if (s > (INT64_C(1) << 40) / splits[i]) return set_err(MVF_ELIMIT, "more than 2^40 subdomains");
+        s *= splits[i];
+    }
+    if (tt > MVF_MAX_TABLE) return set_err(MVF_ELIMIT, "sum of split counts above MVF_MAX_TABLE");
+    *S = s;
+    *tab_total = tt;
+    return MVF_OK;
+}
+
+int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_dev, int max_nodes, int64_t max_sub,
+                    const double *boxes, const int32_t *splits, double *reduced, int64_t *argmin, int32_t *status,
+                    void *ws, size_t ws_bytes, int grid, bool rev, BatchArgs *A) {
+    const BatchLayout L = batch_layout(t, max_nodes, max_sub, grid, rev);
+    if (ws_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    std::memset(A, 0, sizeof *A);
+    A->n_nodes_dev = n_nodes_dev;
+    A->n_nodes_val = n_nodes;
+    A->n = t->C.n_vars;
+    A->tab_cap = BATCH_TAB_CAP;
+    A->boxes = boxes;
+    A->splits = splits;
+    A->reduced = reduced;
+    A->argmin = argmin;
+    A->status = status;
+    A->node_S = reinterpret_cast<int64_t *>(w + L.node_S);
+    A->item_off = reinterpret_cast<int64_t *>(w + L.item_off);
+    A->counter = reinterpret_cast<int64_t *>(w + L.counter);
+    A->partial = reinterpret_cast<double *>(w + L.partial);
+    A->partial_lo0 = reinterpret_cast<double *>(w + L.lo0);
+    A->partial_k = reinterpret_cast<int64_t *>(w + L.k);
+    A->rec = reinterpret_cast<double2 *>(w + L.rec);
+    A->gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
+    A->item_cap = (int64_t)(max_sub / BLK) + max_nodes + 1;
+    return MVF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *mvf_strerror(int code) {
+    switch (code) {
+    case MVF_OK: return "ok";
+    case MVF_EINVAL: return "invalid argument";
+    case MVF_ETAPE: return "malformed tape";
+    case MVF_ELIMIT: return "limit exceeded";
+    case MVF_ENOMEM: return "out of device memory";
+    case MVF_EHIP: return "HIP runtime error";
+    case MVF_ENOTSUP: return "unsupported device";
+    default: return "unknown error";
+    }
+}
+
+const char *mvf_last_error(void) { return g_err.c_str(); }
+
+int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                   const int32_t *roots, int32_t n_roots, mvf_tape_stats *stats) {
+    Compiled C;
+    std::string err;
+    int rc = compile_tape(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, &C, &err);
+    if (rc != MVF_OK) return set_err(rc, err);
+    if (stats) fill_stats(C, stats);
+    return MVF_OK;
+}
+
+int mvf_tape_create(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                    const int32_t *roots, int32_t n_roots, mvf_tape **out) {
+    if (!out) return set_err(MVF_EINVAL, "out is null");
+    *out = nullptr;
+    mvf_tape *t = new (std::nothrow) mvf_tape;
+    if (!t) return set_err(MVF_ENOMEM, "host allocation failed");
+    std::string err;
+    int rc = compile_tape(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, &t->C, &err);
+    if (rc != MVF_OK) { delete t; return set_err(rc, err); }
+    rc = check_device(&t->n_cu);
+    if (rc != MVF_OK) { delete t; return rc; }
+    hipGetDevice(&t->device);
+    if (lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, n_roots, false) > LDS_BUDGET - 1024) {
+        delete t;
+        return set_err(MVF_ELIMIT, "programs and tables exceed the 160 KiB LDS budget");
+    }
+    const size_t bytes = t->C.instr.size() * sizeof(Instr);
+    hipError_t e = hipMalloc(&t->d_prog, bytes);
+    if (e != hipSuccess) { delete t; return set_err(MVF_ENOMEM, "hipMalloc of the program failed"); }
+    e = hipMemcpy(t->d_prog, t->C.instr.data(), bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { hipFree(t->d_prog); delete t; return hip_err(e, "hipMemcpy program"); }
+    *out = t;
+    return MVF_OK;
+}
+
+int mvf_tape_stats_get(const mvf_tape *t, mvf_tape_stats *stats) {
+    if (!t || !stats) return set_err(MVF_EINVAL, "null argument");
+    fill_stats(t->C, stats);
+    return MVF_OK;
+}
+
+int mvf_tape_destroy(mvf_tape *t) {
+    if (!t) return MVF_OK;
+    if (t->d_prog) hipFree(t->d_prog);
+    delete t;
+    return MVF_OK;
+}
+
+int mvf_bound_workspace(const mvf_tape *t, const int32_t *splits, int32_t mode, int32_t grad, size_t *bytes) {
+    if (!t || !bytes) return set_err(MVF_EINVAL, "null argument");
+    int64_t S;
+    int tt;
+    int rc = check_splits(t, splits, &S, &tt);
+    if (rc != MVF_OK) return rc;
+    bool rev;
+    int chunk;
+    rc = resolve_grad(t, mode, grad, nullptr, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    *bytes = single_layout(t, single_grid(t, S, rev), rev, tt).total;
+    return MVF_OK;
+}
+
+int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
+    if (!t || !a) return set_err(MVF_EINVAL, "null argument");
+    if (!a->box || !a->reduced || !a->workspace) return set_err(MVF_EINVAL, "box, reduced and workspace are required");
+    if (a->mode < MVF_MODE_NIE || a->mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
+    if (a->grad < MVF_GRAD_FWD || a->grad > MVF_GRAD_AUTO) return set_err(MVF_EINVAL, "bad grad");
+    int64_t S;
+    int tt;
+    int rc = check_splits(t, a->splits, &S, &tt);
+    if (rc != MVF_OK) return rc;
+    bool rev;
+    int chunk;
+    rc = resolve_grad(t, a->mode, a->grad, nullptr, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    const int grid = single_grid(t, S, rev);
+    const SingleLayout L = single_layout(t, grid, rev, tt);
+    if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
+    const int m = (int)t->C.roots.size(), n = t->C.n_vars;
+    const size_t lds = lds_bytes((int)t->C.instr.size(), tt, n, m, rev && L.g_lds);
+    if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
+
+    const TapeArgs T = tape_args(t, a->mode);
+    BoxArgs B;
+    std::memset(&B, 0, sizeof B);
+    B.tab_off[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        B.splits[i] = a->splits[i];
+        B.tab_off[i + 1] = B.tab_off[i] + a->splits[i];
+    }
+    B.box = a->box;
+    B.S = S;
+    B.per_sub = a->per_sub;
+    B.flags = a->flags;
+    B.reduced = a->reduced;
+    B.argmin = a->argmin;
+    uint8_t *w = static_cast<uint8_t *>(a->workspace);
+    B.partial = reinterpret_cast<double *>(w + L.partial);
+    B.partial_lo0 = reinterpret_cast<double *>(w + L.lo0);
+    B.partial_k = reinterpret_cast<int64_t *>(w + L.k);
+    B.rec = reinterpret_cast<double2 *>(w + L.rec);
+    B.gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
+    hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
+    if (e != hipSuccess) return hip_err(e, "launch_bound");
+    return MVF_OK;
+}
+
+int mvf_batch_workspace(const mvf_tape *t, int32_t max_nodes, int64_t max_subdomains, int32_t mode, int32_t grad,
+                        const mvf_tuning *tuning, size_t *bytes) {
+    if (!t || !bytes || max_nodes < 1 || max_subdomains < 1) return set_err(MVF_EINVAL, "bad argument");
+    bool rev;
+    int chunk;
+    int rc = resolve_grad(t, mode, grad, tuning, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    *bytes = batch_layout(t, max_nodes, max_subdomains, batch_grid(t, tuning), rev).total;
+    return MVF_OK;
+}
+
+int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning *tuning, hipStream_t stream) {
+    if (!t || !a) return set_err(MVF_EINVAL, "null argument");
+    if (a->n_nodes < 0 || a->n_nodes > a->max_nodes) return set_err(MVF_EINVAL, "n_nodes outside [0, max_nodes]");
+    if (!a->boxes || !a->splits || !a->reduced || !a->status || !a->workspace)
+        return set_err(MVF_EINVAL, "boxes, splits, reduced, status and workspace are required");
+    if (a->mode < MVF_MODE_NIE || a->mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
+    bool rev;
+    int chunk;
+    int rc = resolve_grad(t, a->mode, a->grad, tuning, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    const int grid = batch_grid(t, tuning);
+    BatchArgs A;
+    rc = fill_batch_args(t, a->n_nodes, nullptr, a->max_nodes, a->max_subdomains, a->boxes, a->splits, a->reduced,
+                         a->argmin, a->status, a->workspace, a->workspace_bytes, grid, rev, &A);
+    if (rc != MVF_OK) return rc;
+    if (a->n_nodes == 0) return MVF_OK;
+    const int m = (int)t->C.roots.size();
+    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr);
+    hipError_t e = launch_batch(tape_args(t, a->mode), A, chunk, rev, grid, lds, a->n_nodes, stream);
+    if (e != hipSuccess) return hip_err(e, "launch_batch");
+    return MVF_OK;
+}
+
+int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_subdomains, int32_t mode, int32_t grad,
+                           const mvf_tuning *tuning, hipStream_t stream, mvf_batch_graph **out) {
+    if (!t || !out || max_nodes < 1 || max_subdomains < 1) return set_err(MVF_EINVAL, "bad argument");
+    *out = nullptr;
+    bool rev;
+    int chunk;
+    int rc = resolve_grad(t, mode, grad, tuning, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    mvf_batch_graph *g = new (std::nothrow) mvf_batch_graph;
+    if (!g) return set_err(MVF_ENOMEM, "host allocation failed");
+    g->tape = t;
+    g->max_nodes = max_nodes;
+    g->max_subdomains = max_subdomains;
+    g->mode = mode;
+    g->grad = rev ? MVF_GRAD_REV : MVF_GRAD_FWD;
+    if (tuning) g->tuning = *tuning;
+    g->tuning.grad = g->grad;
+    g->tuning.chunk = chunk;
+    g->tuning.grid_blocks = batch_grid(t, tuning);
+    const int n = t->C.n_vars, m = (int)t->C.roots.size();
+    const int grid = g->tuning.grid_blocks;
+    g->ws_bytes = batch_layout(t, max_nodes, max_subdomains, grid, rev).total;
+    auto fail = [&](int code, const char *what) {
+        mvf_batch_graph_destroy(g);
+        return set_err(code, what);
+    };
+    if (hipMalloc(&g->d_ws, g->ws_bytes) != hipSuccess) return fail(MVF_ENOMEM, "hipMalloc workspace");
+    if (hipMalloc(&g->d_boxes, (size_t)max_nodes * n * 2 * 8) != hipSuccess ||
+        hipMalloc(&g->d_splits, (size_t)max_nodes * n * 4) != hipSuccess ||
+        hipMalloc(&g->d_count, 4) != hipSuccess || hipMalloc(&g->d_status, (size_t)max_nodes * 4) != hipSuccess ||
+        hipMalloc(&g->d_reduced, (size_t)max_nodes * m * 2 * 8) != hipSuccess ||
+        hipMalloc(&g->d_argmin, (size_t)max_nodes * 8) != hipSuccess)
+        return fail(MVF_ENOMEM, "hipMalloc node buffers");
+    if (hipHostMalloc(reinterpret_cast<void **>(&g->h_boxes), (size_t)max_nodes * n * 2 * 8, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_splits), (size_t)max_nodes * n * 4, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_count), 4, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_status), (size_t)max_nodes * 4, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_reduced), (size_t)max_nodes * m * 2 * 8,
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_argmin), (size_t)max_nodes * 8, hipHostMallocDefault) !=
+            hipSuccess)
+        return fail(MVF_ENOMEM, "hipHostMalloc staging");
+    std::memset(g->h_boxes, 0, (size_t)max_nodes * n * 2 * 8);
+    for (size_t i = 0; i < (size_t)max_nodes * n; ++i) g->h_splits[i] = 1;
+    *g->h_count = 0;
+
+    BatchArgs A;
+    rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
+                         g->d_argmin, g->d_status, g->d_ws, g->ws_bytes, grid, rev, &A);
+    if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
+    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr);
+    (void)stream;
+    hipStream_t cs = nullptr;                    // private capture stream, default priority
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MVF_EHIP, "hipStreamCreate");
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipStreamDestroy(cs);
+        return fail(MVF_EHIP, "hipStreamBeginCapture");
+    }
+    bool ok = hipMemcpyAsync(g->d_count, g->h_count, 4, hipMemcpyHostToDevice, cs) == hipSuccess &&
+              hipMemcpyAsync(g->d_boxes, g->h_boxes, (size_t)max_nodes * n * 2 * 8, hipMemcpyHostToDevice, cs) ==
+                  hipSuccess &&
+              hipMemcpyAsync(g->d_splits, g->h_splits, (size_t)max_nodes * n * 4, hipMemcpyHostToDevice, cs) ==
+                  hipSuccess;
+    ok = ok && launch_batch(tape_args(t, mode), A, chunk, rev, grid, lds, max_nodes, cs) == hipSuccess;
+    ok = ok && hipMemcpyAsync(g->h_reduced, g->d_reduced, (size_t)max_nodes * m * 2 * 8, hipMemcpyDeviceToHost, cs) ==
+                   hipSuccess &&
+         hipMemcpyAsync(g->h_argmin, g->d_argmin, (size_t)max_nodes * 8, hipMemcpyDeviceToHost, cs) == hipSuccess &&
+         hipMemcpyAsync(g->h_status, g->d_status, (size_t)max_nodes * 4, hipMemcpyDeviceToHost, cs) == hipSuccess;
+    hipError_t ee = hipStreamEndCapture(cs, &g->graph);
+    hipStreamDestroy(cs);
+    if (!ok || ee != hipSuccess) return fail(MVF_EHIP, "graph capture failed");
+    if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(MVF_EHIP, "hipGraphInstantiate");
+    *out = g;
+    return MVF_OK;
+}
+
+int mvf_batch_graph_staging(mvf_batch_graph *g, double **boxes, int32_t **splits) {
+    if (!g || !boxes || !splits) return set_err(MVF_EINVAL, "null argument");
+    *boxes = g->h_boxes;
+    *splits = g->h_splits;
+    return MVF_OK;
+}
+
+int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stream) {
+    if (!g) return set_err(MVF_EINVAL, "null graph");
+    if (n_nodes < 0 || n_nodes > g->max_nodes) return set_err(MVF_EINVAL, "n_nodes outside [0, max_nodes]");
+    const int n = g->tape->C.n_vars;
+    int64_t total = 0;
+    for (int32_t i = 0; i < n_nodes; ++i) {
+        int64_t S = 1;
+        for (int j = 0; j < n; ++j) {
+            const int32_t s = g->h_splits[(size_t)i * n + j];
+            if (s < 1 || s > 65535) return set_err(MVF_EINVAL, "split count outside [1, 65535]");
+            if (S > (INT64_C(1) << 40) / s) return set_err(MVF_ELIMIT, "node with more than 2^40 subdomains");
+            S *= s;
+        }
+        total += S;
+    }
+    if (total > g->max_subdomains) return set_err(MVF_ELIMIT, "total subdomains above the graph's capacity");
+    *g->h_count = n_nodes;
+    HIP_TRY(hipGraphLaunch(g->exec, stream));
+    return MVF_OK;
+}
+
+int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int64_t **argmin,
+                           const int32_t **status) {
+    if (!g) return set_err(MVF_EINVAL, "null graph");
+    if (reduced) *reduced = g->h_reduced;
+    if (argmin) *argmin = g->h_argmin;
+    if (status) *status = g->h_status;
+    return MVF_OK;
+}
+
+int mvf_batch_graph_destroy(mvf_batch_graph *g) {
+    if (!g) return MVF_OK;
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    hipFree(g->d_ws);
+    hipFree(g->d_boxes);
+    hipFree(g->d_splits);
+    hipFree(g->d_count);
+    hipFree(g->d_status);
+    hipFree(g->d_reduced);
+    hipFree(g->d_argmin);
+    hipHostFree(g->h_boxes);
+    hipHostFree(g->h_splits);
+    hipHostFree(g->h_count);
+    hipHostFree(g->h_status);
+    hipHostFree(g->h_reduced);
+    hipHostFree(g->h_argmin);
+    delete g;
+    return MVF_OK;
+}
+
+int64_t mvf_adaptive_splits(int32_t n, const double *widths, int64_t budget, int32_t *splits) {
+    if (n < 1 || !widths || !splits || budget < 1) return set_err(MVF_EINVAL, "bad argument");
+    int64_t N = 1;
+    for (;;) {                                   // largest uniform N with N^n <= budget
+        int64_t p = 1;
+        bool over = false;
+        for (int i = 0; i < n && !over; ++i) {
+            p *= (N + 1);
+            over = p > budget;
+        }
+        if (over) break;
+        ++N;
+    }
+    int64_t count = 1;
+    for (int i = 0; i < n; ++i) { splits[i] = (int32_t)N; count *= N; }
+    for (;;) {                                   // +1 on the relatively widest dimension while it fits
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (widths[i] / splits[i] > widths[best] / splits[best]) best = i;
+        const int64_t next = count / splits[best] * (splits[best] + 1);
+        if (next > budget) break;
+        count = next;
+        splits[best] += 1;
+    }
+    return count;
+}
+
+int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const int32_t *splits, int64_t n_sub,
+                 int32_t mode, mvf_tuning *out, hipStream_t stream) {
+    if (!t || !out || n_nodes < 1 || !boxes || !splits || n_sub < 1) return set_err(MVF_EINVAL, "bad argument");
+    // candidates: gradient mode x tangent chunk x persistent grid size
+    std::vector<mvf_tuning> cand;
+    const int cu = t->n_cu;
+    for (int grad = MVF_GRAD_FWD; grad <= MVF_GRAD_REV; ++grad) {
+        for (int chunk = 1; chunk <= (grad == MVF_GRAD_FWD ? t->C.chunk : 1); ++chunk) {
+            for (int mult : {1, 2, 4}) {
+                mvf_tuning c{};
+                c.grad = grad;
+                c.chunk = grad == MVF_GRAD_FWD ? chunk : 0;
+                c.grid_blocks = mult * cu;
+                cand.push_back(c);
+            }
+        }
+    }
+    size_t max_ws = 0;
+    for (auto &c : cand) {
+        size_t b = 0;
+        if (mvf_batch_workspace(t, n_nodes, n_sub, mode, c.grad, &c, &b) == MVF_OK) max_ws = std::max(max_ws, b);
+    }
+    void *ws = nullptr;
+    double *red = nullptr;
+    int32_t *st = nullptr;
+    if (hipMalloc(&ws, max_ws) != hipSuccess || hipMalloc(&red, (size_t)n_nodes * t->C.roots.size() * 16) != hipSuccess ||
+        hipMalloc(&st, (size_t)n_nodes * 4) != hipSuccess) {
+        hipFree(ws);
+        hipFree(red);
+        hipFree(st);
+        return set_err(MVF_ENOMEM, "autotune workspace");
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    int best_i = -1;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        mvf_batch_args a{};
+        a.n_nodes = n_nodes;
+        a.max_nodes = n_nodes;
+        a.max_subdomains = n_sub;
+        a.boxes = boxes;
+        a.splits = splits;
+        a.mode = mode;
+        a.grad = cand[i].grad;
+        a.reduced = red;
+        a.status = st;
+        a.workspace = ws;
+        a.workspace_bytes = max_ws;
+        if (mvf_bound_batch(t, &a, &cand[i], stream) != MVF_OK) continue;     // warm-up; skips infeasible
+        hipEventRecord(e0, stream);
+        for (int rep = 0; rep < 2; ++rep) mvf_bound_batch(t, &a, &cand[i], stream);
+        hipEventRecord(e1, stream);
+        hipEventSynchronize(e1);
+        float ms = 0;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; best_i = (int)i; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipFree(ws);
+    hipFree(red);
+    hipFree(st);
+    if (best_i < 0) return set_err(MVF_ELIMIT, "no feasible tuning");
+    *out = cand[best_i];
+    out->best_ms = best / 2;
+    return MVF_OK;
+}
+
+}  // extern "C"

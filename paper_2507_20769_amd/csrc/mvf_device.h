@@ -16,8 +16,10 @@
 // the exact residual), which yields the correctly rounded-down result.
 //
 // Slot file.  VGPRs [SLOT_BASE, 256) hold the interpreter's register slots;
-// the compiler is restricted to VGPRs below SLOT_BASE.  A slot is read or
-// written with s_set_gpr_idx_on (index in M0) and v_mov_b64.
+// the compiler is restricted to VGPRs below SLOT_BASE (the kernels declare a
+// VGPR limit and a 5-waves-per-SIMD target, which also keeps SGPR-spill lanes
+// below the slot file; the build verifies the ISA).  A slot is read or written
+// with s_set_gpr_idx_on (index in M0) and v_mov_b64.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -224,8 +226,13 @@ __device__ __forceinline__ Iv ilog(Iv u) {
 #define MVF_SB 96
 static_assert(MVF_SB == mvf::SLOT_BASE, "slot base");
 
+// Slot indices are wave-uniform; readfirstlane pins them to an SGPR as the
+// index operand of s_set_gpr_idx_on requires.
+__device__ __forceinline__ uint32_t sidx(uint32_t idx) { return __builtin_amdgcn_readfirstlane(idx); }
+
 // read one interval at dword offset idx of the slot file
 __device__ __forceinline__ Iv slot_rd(uint32_t idx) {
+    idx = sidx(idx);
     Iv x;
     asm volatile("s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\t"
                  "v_mov_b64 %0, v[96:97]\n\t"
@@ -236,6 +243,7 @@ __device__ __forceinline__ Iv slot_rd(uint32_t idx) {
 }
 // read two consecutive intervals
 __device__ __forceinline__ void slot_rd2(uint32_t idx, Iv &x, Iv &y) {
+    idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\t"
                  "v_mov_b64 %0, v[96:97]\n\t"
                  "v_mov_b64 %1, v[98:99]\n\t"
@@ -245,6 +253,7 @@ __device__ __forceinline__ void slot_rd2(uint32_t idx, Iv &x, Iv &y) {
                  : "=v"(x.lo), "=v"(x.nh), "=v"(y.lo), "=v"(y.nh) : "s"(idx) : "m0");
 }
 __device__ __forceinline__ void slot_wr(uint32_t idx, Iv x) {
+    idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\t"
                  "v_mov_b64 v[96:97], %1\n\t"
                  "v_mov_b64 v[98:99], %2\n\t"
@@ -252,6 +261,7 @@ __device__ __forceinline__ void slot_wr(uint32_t idx, Iv x) {
                  :: "s"(idx), "v"(x.lo), "v"(x.nh) : "m0");
 }
 __device__ __forceinline__ void slot_wr2(uint32_t idx, Iv x, Iv y) {
+    idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\t"
                  "v_mov_b64 v[96:97], %1\n\t"
                  "v_mov_b64 v[98:99], %2\n\t"

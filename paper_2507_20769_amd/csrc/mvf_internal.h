@@ -25,7 +25,7 @@ enum : uint32_t {
 enum : uint32_t { K_SLOT = 0, K_VAR = 1, K_CONST = 2 };
 
 // 16-byte instruction, read from LDS by all lanes of a wave (broadcast):
-//   w0 = op | akind << 8 | bkind << 10 | a << 16
+//   w0 = op | akind << 8 | bkind << 10 | init_a << 12 | init_b << 13 | a << 16
 //   w1 = b | dst << 16
 //   k  = the constant operand (at most one operand is a constant)
 struct Instr {
@@ -42,11 +42,23 @@ inline Instr make_instr(uint32_t op, uint32_t ak, uint32_t a, uint32_t bk, uint3
     return I;
 }
 
+// Interval records one instruction leaves on the reverse-mode tape: the local
+// partials its adjoint rule needs (operand values of a product, 1/V and Z of a
+// quotient, 2U, 1/(2Z), Z, 1/U).  Variable and constant operands are not
+// recorded; they are known again in the reverse sweep.
+// Order within an instruction: U then V for a product, 1/V then Z for a quotient.
+constexpr uint32_t n_records(uint32_t op, uint32_t ak, uint32_t bk) {
+    return op == MVF_MUL ? (ak == K_SLOT && bk != K_CONST) + (bk == K_SLOT && ak != K_CONST)
+         : op == MVF_DIV ? 1u + (bk != K_CONST)
+         : (op >= MVF_SQR && op <= MVF_LOG) ? 1u : 0u;
+}
+
 // One compiled root program.
 struct RootProg {
     int32_t begin = 0, len = 0;      // range in the instruction array
     int32_t result_slot = 0;         // slot holding the root after the last instruction
     int32_t n_slots = 0;             // live-set size
+    int32_t n_rec = 0;               // reverse-mode records per subdomain
 };
 
 struct Compiled {
@@ -54,6 +66,7 @@ struct Compiled {
     std::vector<RootProg> roots;
     std::vector<Instr> instr;
     int32_t max_slots = 0;
+    int32_t max_rec = 0;             // largest record count of a root program
     int32_t chunk = 0;               // tangent components per forward pass
     int64_t ref_fwd = 0, ref_rev = 0;
 };

@@ -1,0 +1,90 @@
+// mvf_kernels.h -- launch arguments of the bounding kernels (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mvf.h"
+#include "mvf_internal.h"
+
+namespace mvf {
+
+constexpr int BLK = 256;            // lanes (subdomains) per workgroup
+
+// Per-tape arguments (wave-uniform).
+struct TapeArgs {
+    const Instr *prog;
+    int32_t n_instr, n_roots, n, mode;
+    int32_t root_begin[MVF_MAX_ROOTS], root_len[MVF_MAX_ROOTS], root_slot[MVF_MAX_ROOTS];
+    int32_t root_rec[MVF_MAX_ROOTS];
+};
+
+// One node box.
+struct BoxArgs {
+    int32_t splits[MVF_MAX_VARS];
+    int32_t tab_off[MVF_MAX_VARS + 1];
+    const double *box;       // device [n][2]
+    int64_t S;
+    double *per_sub;         // [m][2][S] or null
+    uint32_t *flags;         // [S] or null
+    double *reduced;         // [m][2]
+    int64_t *argmin;         // [1] or null
+    double *partial;         // [grid][m][2]
+    double *partial_lo0;     // [grid]
+    int64_t *partial_k;      // [grid]
+    double2 *rec;            // reverse-mode tape [max_rec][grid * BLK]
+    double2 *gacc;           // reverse-mode gradient accumulators [n][grid * BLK] when not in LDS
+};
+
+// Many node boxes in one persistent launch.
+struct BatchArgs {
+    const int32_t *n_nodes_dev;  // device node count (a captured graph changes it between replays) or null
+    int32_t n_nodes_val;         // node count when n_nodes_dev is null
+    int32_t n;
+    int32_t tab_cap;         // breakpoint-table capacity per node (entries)
+    const double *boxes;     // [N][n][2]
+    const int32_t *splits;   // [N][n]
+    double *reduced;         // [N][m][2]
+    int64_t *argmin;         // [N] or null
+    int32_t *status;         // [N]: 0 ok, 1 invalid node
+    int64_t *node_S;         // [N]
+    int64_t *item_off;       // [N + 1]
+    int64_t *counter;        // work-item counter
+    int64_t item_cap;        // capacity of the item partial arrays
+    double *partial;         // [items][m][2]
+    double *partial_lo0;     // [items]
+    int64_t *partial_k;      // [items]
+    double2 *rec;            // reverse-mode tape [max_rec][grid * BLK]
+    double2 *gacc;           // reverse-mode gradient accumulators [n][grid * BLK] when not in LDS
+};
+
+#ifdef __HIPCC__
+__device__ __forceinline__ int node_count(const BatchArgs &A) { return A.n_nodes_dev ? *A.n_nodes_dev : A.n_nodes_val; }
+#endif
+
+hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev, int grid, size_t lds,
+                        hipStream_t stream);
+hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool rev, int grid, size_t lds,
+                        int max_nodes, hipStream_t stream);
+
+constexpr size_t LDS_BUDGET = 160 * 1024;
+
+// LDS bytes of a workgroup (programs, table, gradient accumulators when in
+// LDS, reduction, ints, vrec).
+inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds) {
+    size_t b = (size_t)n_instr * 16 + (size_t)tab_cap * 32;
+    if (g_in_lds) b += (size_t)n * BLK * 16;
+    b += (size_t)(BLK / 64) * (2 * m + 2) * 8;
+    b += (2 * MVF_MAX_VARS + 8) * 4;
+    b = (b + 15) & ~(size_t)15;
+    b += (size_t)n * BLK * sizeof(uint16_t);
+    return b;
+}
+
+// Reverse mode keeps the gradient accumulators in LDS when a workgroup still
+// fits; otherwise they live in the workspace (coalesced [dim][lane]).
+inline bool grad_in_lds(int n_instr, int tab_cap, int n, int m) {
+    // two workgroups per compute unit
+    return lds_bytes(n_instr, tab_cap, n, m, true) <= LDS_BUDGET / 2;
+}
+
+}  // namespace mvf

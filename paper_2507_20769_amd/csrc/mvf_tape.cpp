@@ -144,13 +144,22 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
                 else if (b_const) { bk = K_CONST; b = 0; k = consts[nb->a]; }
                 else { bk = K_SLOT; b = (uint32_t)slot_of[nd.b]; }
             }
-            // release operands dying here, then allocate the result (it may reuse them)
-            if (tmp >= 0) busy[tmp] = 0;
-            if (!is_leaf(na.op) && last_use[nd.a] == (int32_t)p) busy[slot_of[nd.a]] = 0;
-            if (bin && !is_leaf(nb->op) && last_use[nd.b] == (int32_t)p) busy[slot_of[nd.b]] = 0;
+            // release operands dying here, then allocate the result (it may reuse them).
+            // A dying operand's adjoint receives its first contribution here in the
+            // reverse sweep: its slot is initialised instead of accumulated.
+            uint32_t init = 0;
+            if (tmp >= 0) { busy[tmp] = 0; init |= 1u; }
+            if (!is_leaf(na.op) && last_use[nd.a] == (int32_t)p) { busy[slot_of[nd.a]] = 0; init |= 1u; }
+            if (bin && !is_leaf(nb->op) && last_use[nd.b] == (int32_t)p) {
+                busy[slot_of[nd.b]] = 0;
+                if (nd.b != nd.a) init |= 2u;
+            }
             int32_t d = take();
             slot_of[i] = d;
-            C.instr.push_back(make_instr((uint32_t)nd.op, ak, a, bk, b, (uint32_t)d, k));
+            Instr ins = make_instr((uint32_t)nd.op, ak, a, bk, b, (uint32_t)d, k);
+            ins.w0 |= init << 12;
+            C.instr.push_back(ins);
+            P.n_rec += n_records((uint32_t)nd.op, ak, bk);
             int cv, ct, ca;
             ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
             sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
@@ -161,7 +170,10 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
         P.n_slots = (int32_t)busy.size();
         C.roots.push_back(P);
     }
-    for (auto &P : C.roots) C.max_slots = std::max(C.max_slots, P.n_slots);
+    for (auto &P : C.roots) {
+        C.max_slots = std::max(C.max_slots, P.n_slots);
+        C.max_rec = std::max(C.max_rec, P.n_rec);
+    }
 
     // tangent components per forward pass: the largest chunk whose slots fit
     const int avail = usable_dwords(n_roots);

@@ -38,8 +38,23 @@ class _Node(ctypes.Structure):
 
 class TapeStats(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("n_roots", ctypes.c_int32), ("n_instr", ctypes.c_int32),
-                ("max_slots", ctypes.c_int32), ("tangent_chunk", ctypes.c_int32),
+                ("max_slots", ctypes.c_int32), ("tangent_chunk", ctypes.c_int32), ("max_records", ctypes.c_int32),
                 ("ref_ops_fwd", ctypes.c_int64), ("ref_ops_rev", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("grad", ctypes.c_int32), ("chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
+                ("best_ms", ctypes.c_float)]
+
+    def __repr__(self):
+        return f"Tuning(grad={self.grad}, chunk={self.chunk}, grid_blocks={self.grid_blocks}, best_ms={self.best_ms:.3f})"
+
+
+class BatchArgs(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("max_nodes", ctypes.c_int32), ("max_subdomains", ctypes.c_int64),
+                ("boxes", ctypes.c_void_p), ("splits", ctypes.c_void_p), ("mode", ctypes.c_int32),
+                ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class BoundArgs(ctypes.Structure):
@@ -50,7 +65,9 @@ class BoundArgs(ctypes.Structure):
 
 
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
-           "mvf_bound_workspace", "mvf_bound", "mvf_strerror", "mvf_last_error"]
+           "mvf_bound_workspace", "mvf_bound", "mvf_adaptive_splits", "mvf_batch_workspace", "mvf_bound_batch",
+           "mvf_batch_graph_create", "mvf_batch_graph_staging", "mvf_batch_graph_launch", "mvf_batch_graph_result",
+           "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error"]
 
 
 def lib():
@@ -79,6 +96,29 @@ def lib():
             L.mvf_bound_workspace.argtypes = [P, P, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
             L.mvf_bound.restype = ctypes.c_int
             L.mvf_bound.argtypes = [P, ctypes.POINTER(BoundArgs), P]
+            i64 = ctypes.c_int64
+            L.mvf_adaptive_splits.restype = i64
+            L.mvf_adaptive_splits.argtypes = [i32, P, i64, P]
+            L.mvf_batch_workspace.restype = ctypes.c_int
+            L.mvf_batch_workspace.argtypes = [P, i32, i64, i32, i32, ctypes.POINTER(Tuning),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+            L.mvf_bound_batch.restype = ctypes.c_int
+            L.mvf_bound_batch.argtypes = [P, ctypes.POINTER(BatchArgs), ctypes.POINTER(Tuning), P]
+            L.mvf_batch_graph_create.restype = ctypes.c_int
+            L.mvf_batch_graph_create.argtypes = [P, i32, i64, i32, i32, ctypes.POINTER(Tuning), P, ctypes.POINTER(P)]
+            L.mvf_batch_graph_staging.restype = ctypes.c_int
+            L.mvf_batch_graph_staging.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+            L.mvf_batch_graph_launch.restype = ctypes.c_int
+            L.mvf_batch_graph_launch.argtypes = [P, i32, P]
+            L.mvf_batch_graph_result.restype = ctypes.c_int
+            L.mvf_batch_graph_result.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
+                                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)),
+                                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+            L.mvf_batch_graph_destroy.restype = ctypes.c_int
+            L.mvf_batch_graph_destroy.argtypes = [P]
+            L.mvf_autotune.restype = ctypes.c_int
+            L.mvf_autotune.argtypes = [P, i32, P, P, i64, i32, ctypes.POINTER(Tuning), P]
             _lib = L
     return _lib
 
@@ -194,4 +234,130 @@ def bound(tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str 
         out["per_sub"] = call.per_sub
     if flags:
         out["flags"] = call.flags
+    return out
+
+
+def adaptive_splits(widths, budget: int):
+    """Adaptive partitioning of Sec. 3.1.2 (host computation in the library)."""
+    w = np.ascontiguousarray(widths, dtype=np.float64)
+    out = np.zeros(len(w), dtype=np.int32)
+    count = lib().mvf_adaptive_splits(len(w), w.ctypes.data_as(ctypes.c_void_p), int(budget),
+                                      out.ctypes.data_as(ctypes.c_void_p))
+    if count < 0:
+        raise MVFError(int(count), "mvf_adaptive_splits")
+    return out, int(count)
+
+
+class BatchCall:
+    """Pre-marshalled batched bound of many nodes (device boxes [N, n, 2] f64, splits [N, n] i32)."""
+
+    def __init__(self, tape: Tape, boxes, splits, mode: str = "both", grad: str = "rev",
+                 tuning: Optional[Tuning] = None, max_subdomains: Optional[int] = None):
+        import torch
+        self.tape = tape
+        self.boxes = boxes.contiguous()
+        self.splits = splits.to(torch.int32).contiguous()
+        N = int(self.boxes.shape[0])
+        assert tuple(self.boxes.shape) == (N, tape.n_vars, 2) and self.boxes.dtype == torch.float64
+        assert tuple(self.splits.shape) == (N, tape.n_vars)
+        total = int(torch.prod(self.splits.to(torch.int64), dim=1).sum().item())
+        self.total = total
+        cap = max_subdomains if max_subdomains is not None else total
+        dev = self.boxes.device
+        m = tape.n_roots
+        self.tuning = tuning
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        ws = ctypes.c_size_t()
+        rc = lib().mvf_batch_workspace(tape.handle, N, max(cap, 1), MVF_MODE[mode], MVF_GRAD[grad], tp,
+                                       ctypes.byref(ws))
+        if rc != 0:
+            raise MVFError(rc, "mvf_batch_workspace")
+        self.workspace = torch.empty(max(int(ws.value), 8), dtype=torch.uint8, device=dev)
+        self.reduced = torch.empty((N, m, 2), dtype=torch.float64, device=dev)
+        self.argmin = torch.empty(N, dtype=torch.int64, device=dev)
+        self.status = torch.empty(N, dtype=torch.int32, device=dev)
+        self.args = BatchArgs(N, N, max(cap, 1), self.boxes.data_ptr(), self.splits.data_ptr(), MVF_MODE[mode],
+                              MVF_GRAD[grad], self.reduced.data_ptr(), self.argmin.data_ptr(), self.status.data_ptr(),
+                              self.workspace.data_ptr(), self.workspace.numel())
+
+    def launch(self, stream=None):
+        tp = ctypes.byref(self.tuning) if self.tuning is not None else None
+        rc = lib().mvf_bound_batch(self.tape.handle, ctypes.byref(self.args), tp, _stream_ptr(stream))
+        if rc != 0:
+            raise MVFError(rc, "mvf_bound_batch")
+        return self
+
+
+def bound_batch(tape: Tape, boxes, splits, mode: str = "both", grad: str = "rev", tuning=None, stream=None) -> dict:
+    call = BatchCall(tape, boxes, splits, mode, grad, tuning).launch(stream)
+    return {"reduced": call.reduced, "argmin": call.argmin, "status": call.status}
+
+
+class BatchGraph:
+    """A batched bound captured once in a HIP graph, replayed per call with new node data."""
+
+    def __init__(self, tape: Tape, max_nodes: int, max_subdomains: int, mode: str = "both", grad: str = "rev",
+                 tuning: Optional[Tuning] = None):
+        self.tape = tape
+        self.max_nodes = max_nodes
+        h = ctypes.c_void_p()
+        tp = ctypes.byref(tuning) if tuning is not None else None
+        rc = lib().mvf_batch_graph_create(tape.handle, max_nodes, max_subdomains, MVF_MODE[mode], MVF_GRAD[grad], tp,
+                                          None, ctypes.byref(h))
+        if rc != 0:
+            raise MVFError(rc, "mvf_batch_graph_create")
+        self.handle = h
+        bp = ctypes.POINTER(ctypes.c_double)()
+        sp = ctypes.POINTER(ctypes.c_int32)()
+        lib().mvf_batch_graph_staging(h, ctypes.byref(bp), ctypes.byref(sp))
+        n = tape.n_vars
+        self.h_boxes = np.ctypeslib.as_array(bp, shape=(max_nodes, n, 2))
+        self.h_splits = np.ctypeslib.as_array(sp, shape=(max_nodes, n))
+        rp = ctypes.POINTER(ctypes.c_double)()
+        ap = ctypes.POINTER(ctypes.c_int64)()
+        stp = ctypes.POINTER(ctypes.c_int32)()
+        lib().mvf_batch_graph_result(h, ctypes.byref(rp), ctypes.byref(ap), ctypes.byref(stp))
+        self.h_reduced = np.ctypeslib.as_array(rp, shape=(max_nodes, tape.n_roots, 2))
+        self.h_argmin = np.ctypeslib.as_array(ap, shape=(max_nodes,))
+        self.h_status = np.ctypeslib.as_array(stp, shape=(max_nodes,))
+
+    def launch(self, boxes: np.ndarray, splits: np.ndarray, stream=None):
+        """Stage node data (host arrays) into pinned memory and replay the graph."""
+        N = boxes.shape[0]
+        self.h_boxes[:N] = boxes
+        self.h_splits[:N] = splits
+        rc = lib().mvf_batch_graph_launch(self.handle, N, _stream_ptr(stream))
+        if rc != 0:
+            raise MVFError(rc, "mvf_batch_graph_launch")
+        self.n = N
+        return self
+
+    def result(self):
+        """Copies of (reduced [N, m, 2], argmin [N], status [N]); synchronise first."""
+        N = self.n
+        return self.h_reduced[:N].copy(), self.h_argmin[:N].copy(), self.h_status[:N].copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mvf_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(tape: Tape, boxes, splits, mode: str = "both", stream=None) -> Tuning:
+    import torch
+    boxes = boxes.contiguous()
+    splits = splits.to(torch.int32).contiguous()
+    N = int(boxes.shape[0])
+    total = int(torch.prod(splits.to(torch.int64), dim=1).sum().item())
+    out = Tuning()
+    rc = lib().mvf_autotune(tape.handle, N, boxes.data_ptr(), splits.data_ptr(), total, MVF_MODE[mode],
+                            ctypes.byref(out), _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_autotune")
     return out

@@ -1,0 +1,98 @@
+"""The C ABI on the host: the library loads, exports every entry point the
+header declares, and rejects malformed tapes and arguments with status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_20769_amd import inputs as I
+from paper_2507_20769_amd import mvf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mvf.h")).read()
+    return sorted(set(re.findall(r"\b(mvf_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mvf.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(mvf.EXPORTS) <= set(names)
+
+
+def _tape(nodes, consts, roots, n):
+    return I.Tape(np.array(nodes, dtype=I.NODE_DTYPE), np.array(consts, dtype=np.float64),
+                  np.array(roots, dtype=np.int32), n)
+
+
+@pytest.mark.parametrize("nodes,consts,roots,n,code", [
+    ([(I.VAR, 0, -1), (I.ADD, 0, 1)], [], [1], 1, -2),            # operand is not an earlier node
+    ([(I.VAR, 2, -1)], [], [0], 2, -2),                            # variable index out of range
+    ([(I.CONST, 3, -1)], [1.0], [0], 1, -2),                       # constant index out of range
+    ([(I.CONST, 0, -1)], [float("nan")], [0], 1, -2),              # non-finite constant
+    ([(I.VAR, 0, -1), (42, 0, 0)], [], [1], 1, -2),               # bad opcode
+    ([(I.VAR, 0, -1)], [], [5], 1, -2),                            # root is not a node
+    ([(I.VAR, 0, -1)], [], [0], 0, -3),                            # n_vars outside [1, 64]
+    ([(I.VAR, 0, -1)], [], [0], 65, -3),
+])
+def test_malformed_tapes_are_rejected(nodes, consts, roots, n, code):
+    with pytest.raises(mvf.MVFError) as e:
+        mvf.check(_tape(nodes, consts, roots, n))
+    assert e.value.code == code
+    assert mvf.lib().mvf_last_error().decode()
+
+
+def test_too_many_roots_and_nodes():
+    with pytest.raises(mvf.MVFError) as e:
+        mvf.check(_tape([(I.VAR, 0, -1)], [], [0] * 17, 1))
+    assert e.value.code == -3
+
+
+def test_valid_tapes_compile_and_report_costs():
+    for w in (I.tiny(1), I.mid(1)):
+        st = mvf.check(w.tape)
+        assert st.n_roots == w.tape.n_roots and st.n_vars == w.tape.n_vars
+        assert st.n_instr >= w.tape.n_ops()
+        assert st.ref_ops_fwd > st.ref_ops_rev > 0
+    assert mvf.check(I.mid(1).tape).tangent_chunk >= 1
+
+
+def test_leaf_roots_compile():
+    st = mvf.check(_tape([(I.VAR, 0, -1), (I.CONST, 0, -1)], [2.5], [0, 1], 1))
+    assert st.n_instr == 2
+
+
+def test_adaptive_splits_worked_example():
+    # Sec. 3.1.2: 5 dimensions, 2560 cores -> 5^4 * 4 = 2500
+    s, count = mvf.adaptive_splits(np.ones(5), 2560)
+    assert count == 2500 and sorted(s.tolist()) == [4, 5, 5, 5, 5]
+    s, count = mvf.adaptive_splits(np.array([1.0, 4.0]), 80)
+    assert count == 80 and s.tolist() == [8, 10]
+
+
+def test_library_agrees_with_oracle_adaptive_rule():
+    from oracle import oracle as O
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        n = int(rng.integers(1, 7))
+        w = rng.uniform(0.1, 5.0, n)
+        b = int(rng.integers(1, 100000))
+        s1, c1 = mvf.adaptive_splits(w, b)
+        s2, c2 = O.adaptive_splits(w, b)
+        assert c1 == c2 and s1.tolist() == s2.tolist()
+
+
+def test_bound_rejects_bad_arguments_without_device():
+    # argument checks run before any device call
+    L = mvf.lib()
+    assert L.mvf_bound(None, None, None) == -1
+    assert L.mvf_tape_destroy(None) == 0
+    assert L.mvf_bound_batch(None, None, None, None) == -1
+    assert L.mvf_batch_graph_launch(None, 0, None) == -1
