@@ -70,6 +70,32 @@ int check_device(int *n_cu) {
     return MVF_OK;
 }
 
+constexpr int BATCH_TAB_CAP = 512;
+
+// Tangent components per forward pass: the largest chunk whose slots fit the
+// register slot file, with the overflow in LDS spill slots, such that two
+// workgroups still share a compute unit (one, for the smallest chunk, if
+// that is the only way).
+void choose_chunk(Compiled &C) {
+    const int m = (int)C.roots.size(), n = C.n_vars, ni = (int)C.instr.size();
+    const int avail = usable_dwords(m);
+    C.chunk = 0;
+    C.spill = 0;
+    for (int c = MAX_CHUNK; c >= 1; --c) {
+        const int sp = std::max(0, C.max_slots - avail / (4 + 4 * c));
+        const size_t lds = lds_bytes(ni, BATCH_TAB_CAP, n, m, false, spill_bytes(sp, c));
+        if (lds <= LDS_BUDGET / 2 || (c == 1 && lds <= LDS_BUDGET - 1024)) {
+            C.chunk = c;
+            C.spill = sp;
+            return;
+        }
+    }
+}
+
+int spill_for(const Compiled &C, int chunk) {
+    return chunk > 0 ? std::max(0, C.max_slots - usable_dwords((int)C.roots.size()) / (4 + 4 * chunk)) : 0;
+}
+
 void fill_stats(const Compiled &C, mvf_tape_stats *st) {
     st->n_vars = C.n_vars;
     st->n_roots = (int32_t)C.roots.size();
@@ -81,7 +107,7 @@ void fill_stats(const Compiled &C, mvf_tape_stats *st) {
     st->ref_ops_rev = C.ref_rev;
 }
 
-TapeArgs tape_args(const mvf_tape *t, int mode) {
+TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {
     TapeArgs T;
     std::memset(&T, 0, sizeof T);
     T.prog = t->d_prog;
@@ -95,6 +121,8 @@ TapeArgs tape_args(const mvf_tape *t, int mode) {
         T.root_slot[r] = t->C.roots[r].result_slot;
         T.root_rec[r] = t->C.roots[r].n_rec;
     }
+    T.nreg = chunk > 0 ? usable_dwords(T.n_roots) / (4 + 4 * chunk) : usable_dwords(T.n_roots) / 4;
+    T.spill_slots = spill_for(t->C, chunk);
     return T;
 }
 
@@ -124,8 +152,6 @@ int batch_grid(const mvf_tape *t, const mvf_tuning *tu) {
     if (tu && tu->grid_blocks > 0) return tu->grid_blocks;
     return 2 * t->n_cu;
 }
-
-constexpr int BATCH_TAB_CAP = 512;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -238,6 +264,7 @@ int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
     std::string err;
     int rc = compile_tape(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, &C, &err);
     if (rc != MVF_OK) return set_err(rc, err);
+    choose_chunk(C);
     if (stats) fill_stats(C, stats);
     return MVF_OK;
 }
@@ -251,6 +278,7 @@ int mvf_tape_create(const mvf_node *nodes, int32_t n_nodes, const double *consts
     std::string err;
     int rc = compile_tape(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, &t->C, &err);
     if (rc != MVF_OK) { delete t; return set_err(rc, err); }
+    choose_chunk(t->C);
     rc = check_device(&t->n_cu);
     if (rc != MVF_OK) { delete t; return rc; }
     hipGetDevice(&t->device);
@@ -311,10 +339,10 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     const SingleLayout L = single_layout(t, grid, rev, tt);
     if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
-    const size_t lds = lds_bytes((int)t->C.instr.size(), tt, n, m, rev && L.g_lds);
+    const size_t lds = lds_bytes((int)t->C.instr.size(), tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
 
-    const TapeArgs T = tape_args(t, a->mode);
+    const TapeArgs T = tape_args(t, a->mode, chunk);
     BoxArgs B;
     std::memset(&B, 0, sizeof B);
     B.tab_off[0] = 0;
@@ -367,8 +395,10 @@ int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning
     if (rc != MVF_OK) return rc;
     if (a->n_nodes == 0) return MVF_OK;
     const int m = (int)t->C.roots.size();
-    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr);
-    hipError_t e = launch_batch(tape_args(t, a->mode), A, chunk, rev, grid, lds, a->n_nodes, stream);
+    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr,
+                                 spill_bytes(spill_for(t->C, chunk), chunk));
+    if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
+    hipError_t e = launch_batch(tape_args(t, a->mode, chunk), A, chunk, rev, grid, lds, a->n_nodes, stream);
     if (e != hipSuccess) return hip_err(e, "launch_batch");
     return MVF_OK;
 }
@@ -426,7 +456,9 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
                          g->d_argmin, g->d_status, g->d_ws, g->ws_bytes, grid, rev, &A);
     if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
-    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr);
+    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
+                                 spill_bytes(spill_for(t->C, chunk), chunk));
+    if (lds > LDS_BUDGET - 1024) { mvf_batch_graph_destroy(g); return set_err(MVF_ELIMIT, "LDS budget"); }
     (void)stream;
     hipStream_t cs = nullptr;                    // private capture stream, default priority
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MVF_EHIP, "hipStreamCreate");
@@ -439,7 +471,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
                   hipSuccess &&
               hipMemcpyAsync(g->d_splits, g->h_splits, (size_t)max_nodes * n * 4, hipMemcpyHostToDevice, cs) ==
                   hipSuccess;
-    ok = ok && launch_batch(tape_args(t, mode), A, chunk, rev, grid, lds, max_nodes, cs) == hipSuccess;
+    ok = ok && launch_batch(tape_args(t, mode, chunk), A, chunk, rev, grid, lds, max_nodes, cs) == hipSuccess;
     ok = ok && hipMemcpyAsync(g->h_reduced, g->d_reduced, (size_t)max_nodes * m * 2 * 8, hipMemcpyDeviceToHost, cs) ==
                    hipSuccess &&
          hipMemcpyAsync(g->h_argmin, g->d_argmin, (size_t)max_nodes * 8, hipMemcpyDeviceToHost, cs) == hipSuccess &&

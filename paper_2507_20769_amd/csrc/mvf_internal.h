@@ -67,7 +67,8 @@ struct Compiled {
     std::vector<Instr> instr;
     int32_t max_slots = 0;
     int32_t max_rec = 0;             // largest record count of a root program
-    int32_t chunk = 0;               // tangent components per forward pass
+    int32_t chunk = 0;               // tangent components per forward pass (set by the library)
+    int32_t spill = 0;               // LDS spill slots per lane at that chunk
     int64_t ref_fwd = 0, ref_rev = 0;
 };
 

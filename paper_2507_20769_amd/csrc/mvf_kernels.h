@@ -16,6 +16,8 @@ struct TapeArgs {
     int32_t n_instr, n_roots, n, mode;
     int32_t root_begin[MVF_MAX_ROOTS], root_len[MVF_MAX_ROOTS], root_slot[MVF_MAX_ROOTS];
     int32_t root_rec[MVF_MAX_ROOTS];
+    int32_t nreg;            // register slots of the launch's tangent chunk; higher slot ids live in LDS
+    int32_t spill_slots;     // LDS spill slots per lane (forward tangent passes)
 };
 
 // One node box.
@@ -69,10 +71,12 @@ hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool r
 constexpr size_t LDS_BUDGET = 160 * 1024;
 
 // LDS bytes of a workgroup (programs, table, gradient accumulators when in
-// LDS, reduction, ints, vrec).
-inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds) {
+// LDS, spill slots, reduction, ints, vrec).
+inline size_t spill_bytes(int spill_slots, int chunk) { return (size_t)spill_slots * (1 + chunk) * 16 * BLK; }
+inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds, size_t spill = 0) {
     size_t b = (size_t)n_instr * 16 + (size_t)tab_cap * 32;
     if (g_in_lds) b += (size_t)n * BLK * 16;
+    b += spill;
     b += (size_t)(BLK / 64) * (2 * m + 2) * 8;
     b += (2 * MVF_MAX_VARS + 8) * 4;
     b = (b + 15) & ~(size_t)15;

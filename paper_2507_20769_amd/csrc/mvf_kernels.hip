@@ -74,8 +74,30 @@ struct Ctx {
     int64_t gstride;
     double2 *rec;            // global reverse-mode tape of this lane ([record][lane])
     int64_t rec_stride;      // lanes sharing the tape (record stride, in records)
+    double2 *spill;          // LDS spill slots of this lane ([slot][component][lane])
+    uint32_t nreg;           // slot ids >= nreg are spilled (tangent passes)
     int tid, blk;
 };
+
+template <int C>
+__device__ __forceinline__ void spill_read(const Ctx &X, uint32_t a, Iv &val, Iv (&tan)[C > 0 ? C : 1]) {
+    const double2 *p = X.spill + (size_t)(a - X.nreg) * (1 + C) * X.blk;
+    const double2 v = p[0];
+    val = Iv{v.x, v.y};
+#pragma unroll
+    for (int t = 0; t < C; ++t) {
+        const double2 w = p[(size_t)(t + 1) * X.blk];
+        tan[t] = Iv{w.x, w.y};
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void spill_write(const Ctx &X, uint32_t a, const Iv &val, const Iv (&tan)[C > 0 ? C : 1]) {
+    double2 *p = X.spill + (size_t)(a - X.nreg) * (1 + C) * X.blk;
+    p[0] = make_double2(val.lo, val.nh);
+#pragma unroll
+    for (int t = 0; t < C; ++t) p[(size_t)(t + 1) * X.blk] = make_double2(tan[t].lo, tan[t].nh);
+}
 
 __device__ __forceinline__ double4 var_rec(const Ctx &X, uint32_t i) {
     return X.tab[X.vrec[i * X.blk + X.tid]];
@@ -87,7 +109,8 @@ __device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, d
                                       Iv (&tan)[C > 0 ? C : 1]) {
     constexpr uint32_t SD = 4 + 4 * C;
     if (kind == K_SLOT) {
-        slot_read<C>(a * SD, val, tan);
+        if (C > 0 && a >= X.nreg) spill_read<C>(X, a, val, tan);
+        else slot_read<C>(a * SD, val, tan);
     } else if (kind == K_VAR) {
         double4 r = var_rec(X, a);
         val = POINT ? Iv{r.z, r.w} : Iv{r.x, r.y};
@@ -214,7 +237,8 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
             for (int t = 0; t < C; ++t) dZ[t] = dU[t];
             break;
         }
-        slot_write<C>(I.d * SD, Z, dZ);
+        if (C > 0 && I.d >= X.nreg) spill_write<C>(X, I.d, Z, dZ);
+        else slot_write<C>(I.d * SD, Z, dZ);
         if constexpr (TAPE) {
             // records in the order of n_records(): U then V, 1/V then Z, or the single partial
             if (I.op == I_MUL) {
@@ -229,7 +253,8 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
         }
     }
     Iv val;
-    slot_read<C>((uint32_t)res_slot * SD, val, gout);
+    if (C > 0 && (uint32_t)res_slot >= X.nreg) spill_read<C>(X, (uint32_t)res_slot, val, gout);
+    else slot_read<C>((uint32_t)res_slot * SD, val, gout);
     return val;
 }
 
@@ -421,11 +446,12 @@ struct Smem {
     double4 *tab;
     uint16_t *vrec;
     double2 *G;
+    double2 *spill;
     double *wred;
     int32_t *ints;     // splits[MVF_MAX_VARS], tab_off[MVF_MAX_VARS + 1], scratch
 };
 
-__device__ __forceinline__ Smem carve(uint8_t *smem, const TapeArgs &T, int tab_cap, int blk, bool g_lds) {
+__device__ __forceinline__ Smem carve(uint8_t *smem, const TapeArgs &T, int tab_cap, int blk, bool g_lds, int chunk) {
     Smem s;
     uint8_t *p = smem;
     s.prog = reinterpret_cast<uint4 *>(p);
@@ -434,6 +460,8 @@ __device__ __forceinline__ Smem carve(uint8_t *smem, const TapeArgs &T, int tab_
     p += (size_t)tab_cap * 32;
     s.G = reinterpret_cast<double2 *>(p);
     if (g_lds) p += (size_t)T.n * blk * 16;
+    s.spill = reinterpret_cast<double2 *>(p);
+    p += (size_t)T.spill_slots * (1 + chunk) * 16 * blk;
     s.wred = reinterpret_cast<double *>(p);
     p += (size_t)(blk / 64) * (2 * T.n_roots + 2) * 8;
     s.ints = reinterpret_cast<int32_t *>(p);
@@ -524,7 +552,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = T.n_roots, n = T.n;
     const bool g_lds = B.gacc == nullptr;
-    Smem s = carve(smem, T, B.tab_off[n], BLK, REV && g_lds);
+    Smem s = carve(smem, T, B.tab_off[n], BLK, REV && g_lds, C);
     stage_program(T, s.prog, tid, BLK);
     if (tid <= n) s.ints[MVF_MAX_VARS + tid] = B.tab_off[tid];
     if (tid < n) s.ints[tid] = B.splits[tid];
@@ -543,6 +571,8 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     X.blk = BLK;
     X.rec_stride = (int64_t)gridDim.x * BLK;
     X.rec = B.rec + (int64_t)blockIdx.x * BLK + tid;
+    X.spill = s.spill + tid;
+    X.nreg = (uint32_t)T.nreg;
     for (int64_t base = (int64_t)blockIdx.x * BLK; base < B.S; base += (int64_t)gridDim.x * BLK) {
         const int64_t k = base + tid;
         const bool active = k < B.S;
@@ -672,7 +702,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     const int m = T.n_roots, n = T.n;
     const int N = node_count(A0);
     const bool g_lds = A0.gacc == nullptr;
-    Smem s = carve(smem, T, A0.tab_cap, BLK, REV && g_lds);
+    Smem s = carve(smem, T, A0.tab_cap, BLK, REV && g_lds, C);
     __shared__ int64_t sh_item;
     __shared__ int sh_node;
     stage_program(T, s.prog, tid, BLK);
@@ -687,6 +717,8 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     X.blk = BLK;
     X.rec_stride = (int64_t)gridDim.x * BLK;
     X.rec = A0.rec + (int64_t)blockIdx.x * BLK + tid;
+    X.spill = s.spill + tid;
+    X.nreg = (uint32_t)T.nreg;
     const int64_t total = A0.item_off[N];
     int cur = -1;
     for (;;) {

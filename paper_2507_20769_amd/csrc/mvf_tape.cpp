@@ -175,11 +175,8 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
         C.max_rec = std::max(C.max_rec, P.n_rec);
     }
 
-    // tangent components per forward pass: the largest chunk whose slots fit
+    // value passes keep every slot in registers
     const int avail = usable_dwords(n_roots);
-    C.chunk = 0;
-    for (int c = MAX_CHUNK; c >= 1; --c)
-        if (C.max_slots * (4 + 4 * c) <= avail) { C.chunk = c; break; }
     if (C.max_slots * 4 > avail)
         return fail(err, MVF_ELIMIT, "a root needs %ld live slots; the slot file holds %ld values", C.max_slots, avail / 4);
 

@@ -127,3 +127,25 @@ def test_gpu_bounds_enclose_samples():
         sl = 1e-12 * np.maximum(1, np.abs(v).max(axis=0))
         assert np.all(g["per_sub"][:, 0, k] - sl <= v.min(axis=0))
         assert np.all(v.max(axis=0) <= g["per_sub"][:, 1, k] + sl)
+
+
+@pytest.mark.parametrize("name", ["batch", "e2e"])
+def test_forward_with_lds_spill_slots(name):
+    # tapes whose live set exceeds the register slots at one tangent component: the
+    # highest slot ids live in LDS during tangent passes
+    from paper_2507_20769_amd import mvf
+    if name == "batch":
+        bw = I.batch(1, n_nodes=4)
+        tape, box, splits = bw.tape, bw.boxes[1], bw.splits[1]
+    else:
+        tape = I.e2e_tape(1)
+        box = np.array([[-3.0, 3.0]] * 10)
+        splits = np.array([2, 2, 2, 2, 2, 2, 2, 2, 1, 1])
+    st = mvf.check(tape)
+    assert st.tangent_chunk >= 1 and st.max_slots * (4 + 4 * st.tangent_chunk) > 160 - 4 * tape.n_roots
+    g = gpu_bound(tape, box, splits, mode="both", grad="fwd")
+    S = int(np.prod(splits))
+    ks = np.unique(np.concatenate([np.random.default_rng(2).choice(S, min(S, 120), replace=False), [0, S - 1]]))
+    o = O.bound(tape, box, splits, mode=O.MODE_BOTH, ks=ks, nthreads=8)
+    sc = scale_of(O.bound(tape, box, splits, mode=O.MODE_NIE, ks=ks, per_sub=False, nthreads=8)["reduced"])
+    assert_parity(g["per_sub"][:, :, ks], o["per_sub"], not has_transcendental(tape), sc, f"{name} fwd spill")
