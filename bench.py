@@ -1,15 +1,25 @@
 """Benchmark: MVF subdomain bounds per second on one MI355X.
 
-One step = one call of the whole bounding path on one node box of the mid
-workload (6 variables, a 200-op objective and three 80-op constraints,
-8^6 = 262,144 subdomains): subdomain generation, point pass, tangent passes,
-MVF intersected with the NIE, and the min/max reduction with argmin.  Inputs
-are resident in HBM before the timed region.
+Headline step = one call of the whole bounding path on one node box of the
+mid workload (6 variables, a 200-op objective and three 80-op constraints,
+8^6 = 262,144 subdomains) in the plain form: forward (tangent) mode, one
+launch per box -- subdomain generation, point pass, tangent passes, MVF
+intersected with the NIE, min/max reduction with argmin.  Inputs are resident
+in HBM before the timed region.
 
-Prints one JSON line.  ``value`` is subdomain-bounds/s (one subdomain-bound =
-the bounds of the objective and all constraints on one subdomain).
-``roofline`` relates the bounding kernel to the FP64 VALU issue peak of the
-chip; ``cpu_baseline`` times the CPU oracle on a bounded sample.
+The same JSON line carries the comparison of the two forms on the batch
+workload (512 B&B-like nodes of [-3,3]^8 with 2^10..2^18 subdomains each,
+a 400-op objective and two 150-op constraints):
+  * plain    -- forward mode, one launch per node, synchronised per node as a
+                branch-and-bound loop would;
+  * adjoint+batched -- reverse-mode adjoint, all nodes in one persistent
+                launch replayed from a HIP graph (staging H2D and result D2H
+                inside the graph),
+and the reverse-mode rate on the mid and 32-variable differentiation
+workloads.  ``value`` is subdomain-bounds/s (one subdomain-bound = the bounds
+of the objective and all constraints on one subdomain).  ``roofline`` relates
+the bounding kernel to the FP64 VALU issue rate; ``cpu_baseline`` times the
+CPU oracle on a bounded sample.
 """
 from __future__ import annotations
 
@@ -29,6 +39,7 @@ sys.path.insert(0, ROOT)
 # published 78.6 TFLOP/s counts an FMA as two operations.
 FP64_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9          # 39.3e12 op/s
 FP64_PUBLISHED_PEAK = 78.6e12
+METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 
 def parse():
@@ -36,10 +47,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="mid", choices=["mid", "tiny"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="headline only (used under the profiler)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device-to-device copy, the reference for HBM counters")
     return ap.parse_args()
 
 
@@ -58,7 +71,91 @@ def cpu_baseline(w, seconds: float) -> dict:
         k0 = k1
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "subdomain-bounds/s", "cores": threads, "kind": "oracle",
-            "sample": f"subdomains 0..{done - 1} of the {w.name} workload ({done} of {S}), {dt:.1f} s"}
+            "sample": f"subdomains 0..{done - 1} of the {w.name} workload ({done} of {S}), "
+                      f"forward-mode MVF, {dt:.1f} s"}
+
+
+def time_calls(launch, steps: int, warmup: int, stream) -> float:
+    """Average ms per call between HIP events on ``stream``."""
+    import torch
+    for _ in range(warmup):
+        launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def forms(seed: int) -> dict:
+    import torch
+
+    from paper_2507_20769_amd import inputs as I
+    from paper_2507_20769_amd import mvf
+    out = {}
+    stream = torch.cuda.current_stream()
+    # reverse mode on mid and on the 32-variable differentiation workload
+    for name, steps in (("mid", 20), ("diff", 4)):
+        w = getattr(I, name)(seed)
+        h = mvf.Tape(w.tape)
+        st = h.stats()
+        call = mvf.BoundCall(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both", grad="rev")
+        ms = time_calls(call.launch, steps, 1, stream)
+        out[f"{name}_adjoint"] = {"subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms, "subdomains": w.n_sub,
+                                  "ref_ops_per_subdomain": st.ref_ops_rev,
+                                  "issue_peak_frac": st.ref_ops_rev * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
+    # batch workload: plain forward per node vs adjoint + batched graph
+    bw = I.batch(seed)
+    h = mvf.Tape(bw.tape)
+    st = h.stats()
+    total = int(bw.n_sub.sum())
+    boxes = torch.tensor(bw.boxes, device="cuda")
+    calls = [mvf.BoundCall(h, boxes[i], bw.splits[i], mode="both", grad="fwd") for i in range(len(bw.boxes))]
+    red_plain = np.empty((len(calls), bw.tape.n_roots, 2))
+
+    def plain():
+        for i, c in enumerate(calls):
+            c.launch(stream)
+            stream.synchronize()                   # a B&B loop needs each node's bound before going on
+    plain()
+    t0 = time.perf_counter()
+    plain()
+    t_plain = time.perf_counter() - t0
+    for i, c in enumerate(calls):
+        red_plain[i] = c.reduced.cpu().numpy()
+    g = mvf.BatchGraph(h, len(bw.boxes), total, mode="both", grad="rev")
+    gs = torch.cuda.Stream()
+
+    def batched():
+        g.launch(bw.boxes, bw.splits, stream=gs)
+        gs.synchronize()
+    batched()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        batched()
+    t_batched = (time.perf_counter() - t0) / reps
+    red_b, _, status = g.result()
+    # same accuracy: both pass parity with their own oracle mode; report how the two
+    # gradient enclosures compare on the objective lower bound
+    d = red_b[:, 0, 0] - red_plain[:, 0, 0]
+    scale = np.maximum(1.0, np.abs(red_plain[:, 0, :]).max(axis=1))
+    out["batch"] = {
+        "nodes": len(bw.boxes), "subdomains": total,
+        "plain_forward_per_node": {"subdomain_bounds_per_s": total / t_plain, "s": t_plain,
+                                   "tangent_chunk": st.tangent_chunk},
+        "adjoint_batched_graph": {"subdomain_bounds_per_s": total / t_batched, "s": t_batched,
+                                  "status_ok": bool((status == 0).all())},
+        "speedup_adjoint_batched_vs_plain": t_plain / t_batched,
+        "objective_lb_adjoint_minus_forward": {"tighter_frac": float(np.mean(d > 0)),
+                                               "looser_frac": float(np.mean(d < 0)),
+                                               "mean_rel": float(np.mean(d / scale))},
+    }
+    g.close()
+    return out
 
 
 def main():
@@ -72,33 +169,28 @@ def main():
     from paper_2507_20769_amd import mvf
 
     torch.cuda.init()
-    w = getattr(I, args.workload)(args.seed)
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")     # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    w = I.mid(args.seed)
     tape = mvf.Tape(w.tape)
     st = tape.stats()
     box = torch.tensor(w.box, dtype=torch.float64, device="cuda")
     call = mvf.BoundCall(tape, box, w.splits, mode="both", grad="fwd")
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        call.launch(stream)
-    torch.cuda.synchronize()
-
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        call.launch(stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
+    ms = time_calls(lambda: call.launch(stream), args.steps, args.warmup, stream)
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
     S = w.n_sub
     value = S / (ms * 1e-3)
-    ops = st.ref_ops_fwd * S                      # algorithmic FP64 ops per launch
-    achieved = ops / (ms * 1e-3)
+    achieved = st.ref_ops_fwd * S / (ms * 1e-3)           # algorithmic FP64 ops per second
     reduced = call.reduced.cpu().numpy()
 
     out = {
-        "metric": "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain",
+        "metric": METRIC,
         "value": value,
         "unit": "subdomain-bounds/s",
         "n_gpus": 1,
@@ -110,17 +202,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": w.name, "form": "plain forward-mode, one launch per node box",
+        "config": {"workload": "mid", "form": "plain: forward-mode MVF, one launch per node box",
                    "n_vars": w.tape.n_vars, "tape_ops": w.tape.n_ops(), "roots": w.tape.n_roots,
                    "subdomains": S, "splits": [int(s) for s in w.splits], "seed": args.seed,
                    "tape_hash": w.tape.digest(), "tangent_chunk": st.tangent_chunk},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_ISSUE_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_ISSUE_PEAK, "traffic": None,
+                     "kernel": "bound_kernel<2,false> (+ its 1-block finish kernel inside the timed call)",
                      "ops_per_subdomain": st.ref_ops_fwd,
                      "frac_of_published_78.6": achieved / FP64_PUBLISHED_PEAK},
         "wall_s": wall,
         "objective_lower_bound": float(reduced[0, 0]),
     }
+    if not args.no_forms:
+        out["forms"] = forms(args.seed)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
