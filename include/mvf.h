@@ -113,6 +113,8 @@ typedef struct {
                                  made every bound of that subdomain [-inf, +inf] */
     void *workspace;          /* device scratch of mvf_bound_workspace() bytes */
     size_t workspace_bytes;
+    const struct mvf_tuning *tuning;   /* NULL, or a gradient mode and tangent chunk to use
+                                          (grid_blocks is ignored here) */
 } mvf_bound_args;
 
 /*
@@ -135,7 +137,7 @@ int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mod
 int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
 
 /* ---- tuning ----------------------------------------------------------- */
-typedef struct {
+typedef struct mvf_tuning {
     int32_t grad;             /* MVF_GRAD_FWD or MVF_GRAD_REV; other values: keep the call's choice */
     int32_t chunk;            /* tangent components per forward pass (1 .. tangent_chunk); 0: default */
     int32_t grid_blocks;      /* persistent workgroups of a batched launch; 0: two per compute unit */

@@ -21,12 +21,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["mvf_kernels.hip", "mvf_tape.cpp", "mvf_api.cpp"]
 DEVICE_SOURCES = ["mvf_kernels.hip"]
-SLOT_BASE = 96
+SLOT_BASE = 128
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17",
     "-ffp-contract=off",                                   # no contraction in round-to-nearest code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # loop-invariant code motion on machine code hoists constants (the exp/log
+    # coefficients) and argument values out of the interpreter loops and keeps
+    # them in SGPRs there; rematerialising them where used spills far less
+    "-mllvm", "-disable-machine-licm",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

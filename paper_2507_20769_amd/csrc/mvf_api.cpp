@@ -70,24 +70,28 @@ int check_device(int *n_cu) {
     return MVF_OK;
 }
 
-constexpr int BATCH_TAB_CAP = 512;
+constexpr int BATCH_TAB_CAP = 256;
 
-// Tangent components per forward pass: the largest chunk whose slots fit the
-// register slot file, with the overflow in LDS spill slots, such that two
-// workgroups still share a compute unit (one, for the smallest chunk, if
-// that is the only way).
+// Tangent components per forward pass: the fewest passes over the program
+// (then the fewest LDS spill slots, then the smallest chunk) among the chunks
+// whose spill slots still let two workgroups share a compute unit (one, for a
+// single component, if that is the only way).
 void choose_chunk(Compiled &C) {
     const int m = (int)C.roots.size(), n = C.n_vars, ni = (int)C.instr.size();
     const int avail = usable_dwords(m);
     C.chunk = 0;
     C.spill = 0;
-    for (int c = MAX_CHUNK; c >= 1; --c) {
+    int best_passes = 1 << 30, best_spill = 1 << 30;
+    for (int c = 1; c <= std::min(MAX_CHUNK, n); ++c) {
         const int sp = std::max(0, C.max_slots - avail / (4 + 4 * c));
         const size_t lds = lds_bytes(ni, BATCH_TAB_CAP, n, m, false, spill_bytes(sp, c));
-        if (lds <= LDS_BUDGET / 2 || (c == 1 && lds <= LDS_BUDGET - 1024)) {
+        if (!(lds <= LDS_BUDGET / 2 || (c == 1 && lds <= LDS_BUDGET - 1024))) continue;
+        const int passes = (n + c - 1) / c;
+        if (passes < best_passes || (passes == best_passes && sp < best_spill)) {
+            best_passes = passes;
+            best_spill = sp;
             C.chunk = c;
             C.spill = sp;
-            return;
         }
     }
 }
@@ -99,7 +103,7 @@ int spill_for(const Compiled &C, int chunk) {
 void fill_stats(const Compiled &C, mvf_tape_stats *st) {
     st->n_vars = C.n_vars;
     st->n_roots = (int32_t)C.roots.size();
-    st->n_instr = (int32_t)C.instr.size();
+    st->n_instr = C.n_prog;
     st->max_slots = C.max_slots;
     st->tangent_chunk = C.chunk;
     st->max_records = C.max_rec;
@@ -115,12 +119,7 @@ TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {
     T.n_roots = (int32_t)t->C.roots.size();
     T.n = t->C.n_vars;
     T.mode = mode;
-    for (int r = 0; r < T.n_roots; ++r) {
-        T.root_begin[r] = t->C.roots[r].begin;
-        T.root_len[r] = t->C.roots[r].len;
-        T.root_slot[r] = t->C.roots[r].result_slot;
-        T.root_rec[r] = t->C.roots[r].n_rec;
-    }
+    T.root_base = t->C.root_base;
     T.nreg = chunk > 0 ? usable_dwords(T.n_roots) / (4 + 4 * chunk) : usable_dwords(T.n_roots) / 4;
     T.spill_slots = spill_for(t->C, chunk);
     return T;
@@ -134,7 +133,8 @@ int resolve_grad(const mvf_tape *t, int mode, int grad, const mvf_tuning *tu, bo
     if (grad == MVF_GRAD_AUTO) grad = (t->C.chunk == 0 || t->C.ref_rev < t->C.ref_fwd) ? MVF_GRAD_REV : MVF_GRAD_FWD;
     *rev = grad == MVF_GRAD_REV;
     *chunk = *rev ? 0 : t->C.chunk;
-    if (tu && !*rev && tu->chunk >= 1 && tu->chunk <= t->C.chunk) *chunk = tu->chunk;
+    // a tuned chunk may exceed the default one; the launch checks that its spill slots fit in LDS
+    if (tu && !*rev && tu->chunk >= 1 && tu->chunk <= std::min(MAX_CHUNK, t->C.n_vars)) *chunk = tu->chunk;
     if (!*rev && *chunk == 0)
         return set_err(MVF_ELIMIT, "a root's live set is too large for tangent passes; use MVF_GRAD_REV");
     return MVF_OK;
@@ -333,7 +333,7 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     if (rc != MVF_OK) return rc;
     bool rev;
     int chunk;
-    rc = resolve_grad(t, a->mode, a->grad, nullptr, &rev, &chunk);
+    rc = resolve_grad(t, a->mode, a->grad, a->tuning, &rev, &chunk);
     if (rc != MVF_OK) return rc;
     const int grid = single_grid(t, S, rev);
     const SingleLayout L = single_layout(t, grid, rev, tt);

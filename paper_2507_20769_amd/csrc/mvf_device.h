@@ -65,6 +65,11 @@ __device__ __forceinline__ double fadd_ns(double a, double s) {       // RD(-a +
     asm volatile("v_add_f64 %0, -%1, %2" : "=v"(r) : "v"(a), "s"(s));
     return r;
 }
+__device__ __forceinline__ double fsub(double a, double b) {          // RD(a - b)
+    double r;
+    asm volatile("v_add_f64 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 __device__ __forceinline__ double fmul(double a, double b) {
     double r;
     asm volatile("v_mul_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
@@ -161,10 +166,21 @@ __device__ __forceinline__ Iv iadd(Iv u, Iv v) { return {fadd(u.lo, v.lo), fadd(
 __device__ __forceinline__ Iv isub(Iv u, Iv v) { return {fadd(u.lo, v.nh), fadd(u.nh, v.lo)}; }
 
 // hull of the four endpoint products; hi = -nh, so lo*hi = RD(lo * -nh) etc.
+// (volatile asm keeps source order: each minimum follows its two products, so
+// few temporaries are live at once)
 __device__ __forceinline__ Iv imul(Iv u, Iv v) {
-    double p0 = fmul(u.lo, v.lo), p1 = fmul_n(u.lo, v.nh), p2 = fmul_n(u.nh, v.lo), p3 = fmul(u.nh, v.nh);
-    double q0 = fmul_n(u.lo, v.lo), q1 = fmul(u.lo, v.nh), q2 = fmul(u.nh, v.lo), q3 = fmul_n(u.nh, v.nh);
-    return {fmin_(fmin_(p0, p1), fmin_(p2, p3)), fmin_(fmin_(q0, q1), fmin_(q2, q3))};
+    // the two endpoint chains interleaved: each operation's inputs were
+    // produced at least two instructions earlier
+    const double p0 = fmul(u.lo, v.lo), q0 = fmul_n(u.lo, v.lo);
+    const double p1 = fmul_n(u.lo, v.nh), q1 = fmul(u.lo, v.nh);
+    double lo = fmin_(p0, p1), nh = fmin_(q0, q1);
+    const double p2 = fmul_n(u.nh, v.lo), q2 = fmul(u.nh, v.lo);
+    lo = fmin_(lo, p2);
+    nh = fmin_(nh, q2);
+    const double p3 = fmul(u.nh, v.nh), q3 = fmul_n(u.nh, v.nh);
+    lo = fmin_(lo, p3);
+    nh = fmin_(nh, q3);
+    return {lo, nh};
 }
 
 __device__ __forceinline__ Iv isqr(Iv u) {
@@ -222,8 +238,33 @@ __device__ __forceinline__ Iv ilog(Iv u) {
     return {pred(pred(ll)), pred(pred(-lh))};
 }
 
+// ---- constant-operand forms ---------------------------------------------
+// Each equals the general operation with a point interval [k, k] (k != 0)
+// bit for bit, up to the sign of zero endpoints: the general hull's other
+// candidates are never smaller, by monotonicity of rounding.
+
+// -U = [-hi, -lo]: the two stored endpoints trade places (exact)
+__device__ __forceinline__ Iv ineg(Iv u) { return {u.nh, u.lo}; }
+
+// U * k for k > 0
+__device__ __forceinline__ Iv imulk(Iv u, double k) { return {fmul(u.lo, k), fmul(u.nh, k)}; }
+
+// U * R for an interval R > 0 (stored (r_lo, -r_hi)): each endpoint of the
+// result comes from one endpoint of U and either endpoint of R
+__device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
+    return {fmin_(fmul(u.lo, r.lo), fmul_n(u.lo, r.nh)), fmin_(fmul(u.nh, r.lo), fmul_n(u.nh, r.nh))};
+}
+
+// U / k for k > 0
+__device__ __forceinline__ Iv idivk(Iv u, double k) { return {div_rd(u.lo, k), div_rd(u.nh, k)}; }
+
 // ---- slot file (GPR index mode) -------------------------------------------
-#define MVF_SB 96
+#define MVF_SB 128
+// the first four register pairs of the slot file (GPR-index base operands)
+#define MVF_P0 "v[128:129]"
+#define MVF_P1 "v[130:131]"
+#define MVF_P2 "v[132:133]"
+#define MVF_P3 "v[134:135]"
 static_assert(MVF_SB == mvf::SLOT_BASE, "slot base");
 
 // Slot indices are wave-uniform; readfirstlane pins them to an SGPR as the
@@ -235,8 +276,8 @@ __device__ __forceinline__ Iv slot_rd(uint32_t idx) {
     idx = sidx(idx);
     Iv x;
     asm volatile("s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\t"
-                 "v_mov_b64 %0, v[96:97]\n\t"
-                 "v_mov_b64 %1, v[98:99]\n\t"
+                 "v_mov_b64 %0, " MVF_P0 "\n\t"
+                 "v_mov_b64 %1, " MVF_P1 "\n\t"
                  "s_set_gpr_idx_off"
                  : "=v"(x.lo), "=v"(x.nh) : "s"(idx) : "m0");
     return x;
@@ -245,31 +286,119 @@ __device__ __forceinline__ Iv slot_rd(uint32_t idx) {
 __device__ __forceinline__ void slot_rd2(uint32_t idx, Iv &x, Iv &y) {
     idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\t"
-                 "v_mov_b64 %0, v[96:97]\n\t"
-                 "v_mov_b64 %1, v[98:99]\n\t"
-                 "v_mov_b64 %2, v[100:101]\n\t"
-                 "v_mov_b64 %3, v[102:103]\n\t"
+                 "v_mov_b64 %0, " MVF_P0 "\n\t"
+                 "v_mov_b64 %1, " MVF_P1 "\n\t"
+                 "v_mov_b64 %2, " MVF_P2 "\n\t"
+                 "v_mov_b64 %3, " MVF_P3 "\n\t"
                  "s_set_gpr_idx_off"
                  : "=v"(x.lo), "=v"(x.nh), "=v"(y.lo), "=v"(y.nh) : "s"(idx) : "m0");
 }
 __device__ __forceinline__ void slot_wr(uint32_t idx, Iv x) {
     idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\t"
-                 "v_mov_b64 v[96:97], %1\n\t"
-                 "v_mov_b64 v[98:99], %2\n\t"
+                 "v_mov_b64 " MVF_P0 ", %1\n\t"
+                 "v_mov_b64 " MVF_P1 ", %2\n\t"
                  "s_set_gpr_idx_off"
                  :: "s"(idx), "v"(x.lo), "v"(x.nh) : "m0");
 }
 __device__ __forceinline__ void slot_wr2(uint32_t idx, Iv x, Iv y) {
     idx = sidx(idx);
     asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\t"
-                 "v_mov_b64 v[96:97], %1\n\t"
-                 "v_mov_b64 v[98:99], %2\n\t"
-                 "v_mov_b64 v[100:101], %3\n\t"
-                 "v_mov_b64 v[102:103], %4\n\t"
+                 "v_mov_b64 " MVF_P0 ", %1\n\t"
+                 "v_mov_b64 " MVF_P1 ", %2\n\t"
+                 "v_mov_b64 " MVF_P2 ", %3\n\t"
+                 "v_mov_b64 " MVF_P3 ", %4\n\t"
                  "s_set_gpr_idx_off"
                  :: "s"(idx), "v"(x.lo), "v"(x.nh), "v"(y.lo), "v"(y.nh) : "m0");
 }
+// n consecutive intervals (a slot's value then its tangent components) at
+// dword offset idx, in one GPR-index session
+#define MVF_Q0 "v[128:129]"
+#define MVF_Q1 "v[130:131]"
+#define MVF_Q2 "v[132:133]"
+#define MVF_Q3 "v[134:135]"
+#define MVF_Q4 "v[136:137]"
+#define MVF_Q5 "v[138:139]"
+#define MVF_Q6 "v[140:141]"
+#define MVF_Q7 "v[142:143]"
+#define MVF_Q8 "v[144:145]"
+#define MVF_Q9 "v[146:147]"
+static_assert(MVF_SB == 128, "register names of the slot-file sessions");
+
+template <int N>
+__device__ __forceinline__ void slot_rd_n(uint32_t idx, Iv (&x)[N]) {
+    idx = sidx(idx);
+    static_assert(N >= 1 && N <= 5, "1 to 5 intervals");
+    if constexpr (N == 1) {
+        asm volatile("s_set_gpr_idx_on %2, gpr_idx(SRC0)\n\tv_mov_b64 %0, " MVF_Q0 "\n\tv_mov_b64 %1, " MVF_Q1
+                     "\n\ts_set_gpr_idx_off"
+                     : "=v"(x[0].lo), "=v"(x[0].nh) : "s"(idx) : "m0");
+    } else if constexpr (N == 2) {
+        asm volatile("s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\tv_mov_b64 %0, " MVF_Q0 "\n\tv_mov_b64 %1, " MVF_Q1
+                     "\n\tv_mov_b64 %2, " MVF_Q2 "\n\tv_mov_b64 %3, " MVF_Q3 "\n\ts_set_gpr_idx_off"
+                     : "=v"(x[0].lo), "=v"(x[0].nh), "=v"(x[1].lo), "=v"(x[1].nh) : "s"(idx) : "m0");
+    } else if constexpr (N == 3) {
+        asm volatile("s_set_gpr_idx_on %6, gpr_idx(SRC0)\n\tv_mov_b64 %0, " MVF_Q0 "\n\tv_mov_b64 %1, " MVF_Q1
+                     "\n\tv_mov_b64 %2, " MVF_Q2 "\n\tv_mov_b64 %3, " MVF_Q3 "\n\tv_mov_b64 %4, " MVF_Q4
+                     "\n\tv_mov_b64 %5, " MVF_Q5 "\n\ts_set_gpr_idx_off"
+                     : "=v"(x[0].lo), "=v"(x[0].nh), "=v"(x[1].lo), "=v"(x[1].nh), "=v"(x[2].lo), "=v"(x[2].nh)
+                     : "s"(idx) : "m0");
+    } else if constexpr (N == 4) {
+        asm volatile("s_set_gpr_idx_on %8, gpr_idx(SRC0)\n\tv_mov_b64 %0, " MVF_Q0 "\n\tv_mov_b64 %1, " MVF_Q1
+                     "\n\tv_mov_b64 %2, " MVF_Q2 "\n\tv_mov_b64 %3, " MVF_Q3 "\n\tv_mov_b64 %4, " MVF_Q4
+                     "\n\tv_mov_b64 %5, " MVF_Q5 "\n\tv_mov_b64 %6, " MVF_Q6 "\n\tv_mov_b64 %7, " MVF_Q7
+                     "\n\ts_set_gpr_idx_off"
+                     : "=v"(x[0].lo), "=v"(x[0].nh), "=v"(x[1].lo), "=v"(x[1].nh), "=v"(x[2].lo), "=v"(x[2].nh),
+                       "=v"(x[3].lo), "=v"(x[3].nh)
+                     : "s"(idx) : "m0");
+    } else {
+        asm volatile("s_set_gpr_idx_on %10, gpr_idx(SRC0)\n\tv_mov_b64 %0, " MVF_Q0 "\n\tv_mov_b64 %1, " MVF_Q1
+                     "\n\tv_mov_b64 %2, " MVF_Q2 "\n\tv_mov_b64 %3, " MVF_Q3 "\n\tv_mov_b64 %4, " MVF_Q4
+                     "\n\tv_mov_b64 %5, " MVF_Q5 "\n\tv_mov_b64 %6, " MVF_Q6 "\n\tv_mov_b64 %7, " MVF_Q7
+                     "\n\tv_mov_b64 %8, " MVF_Q8 "\n\tv_mov_b64 %9, " MVF_Q9 "\n\ts_set_gpr_idx_off"
+                     : "=v"(x[0].lo), "=v"(x[0].nh), "=v"(x[1].lo), "=v"(x[1].nh), "=v"(x[2].lo), "=v"(x[2].nh),
+                       "=v"(x[3].lo), "=v"(x[3].nh), "=v"(x[4].lo), "=v"(x[4].nh)
+                     : "s"(idx) : "m0");
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void slot_wr_n(uint32_t idx, const Iv (&x)[N]) {
+    idx = sidx(idx);
+    static_assert(N >= 1 && N <= 5, "1 to 5 intervals");
+    if constexpr (N == 1) {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\tv_mov_b64 " MVF_Q0 ", %1\n\tv_mov_b64 " MVF_Q1
+                     ", %2\n\ts_set_gpr_idx_off"
+                     :: "s"(idx), "v"(x[0].lo), "v"(x[0].nh) : "m0");
+    } else if constexpr (N == 2) {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\tv_mov_b64 " MVF_Q0 ", %1\n\tv_mov_b64 " MVF_Q1
+                     ", %2\n\tv_mov_b64 " MVF_Q2 ", %3\n\tv_mov_b64 " MVF_Q3 ", %4\n\ts_set_gpr_idx_off"
+                     :: "s"(idx), "v"(x[0].lo), "v"(x[0].nh), "v"(x[1].lo), "v"(x[1].nh) : "m0");
+    } else if constexpr (N == 3) {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\tv_mov_b64 " MVF_Q0 ", %1\n\tv_mov_b64 " MVF_Q1
+                     ", %2\n\tv_mov_b64 " MVF_Q2 ", %3\n\tv_mov_b64 " MVF_Q3 ", %4\n\tv_mov_b64 " MVF_Q4
+                     ", %5\n\tv_mov_b64 " MVF_Q5 ", %6\n\ts_set_gpr_idx_off"
+                     :: "s"(idx), "v"(x[0].lo), "v"(x[0].nh), "v"(x[1].lo), "v"(x[1].nh), "v"(x[2].lo), "v"(x[2].nh)
+                     : "m0");
+    } else if constexpr (N == 4) {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\tv_mov_b64 " MVF_Q0 ", %1\n\tv_mov_b64 " MVF_Q1
+                     ", %2\n\tv_mov_b64 " MVF_Q2 ", %3\n\tv_mov_b64 " MVF_Q3 ", %4\n\tv_mov_b64 " MVF_Q4
+                     ", %5\n\tv_mov_b64 " MVF_Q5 ", %6\n\tv_mov_b64 " MVF_Q6 ", %7\n\tv_mov_b64 " MVF_Q7
+                     ", %8\n\ts_set_gpr_idx_off"
+                     :: "s"(idx), "v"(x[0].lo), "v"(x[0].nh), "v"(x[1].lo), "v"(x[1].nh), "v"(x[2].lo), "v"(x[2].nh),
+                        "v"(x[3].lo), "v"(x[3].nh)
+                     : "m0");
+    } else {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(DST)\n\tv_mov_b64 " MVF_Q0 ", %1\n\tv_mov_b64 " MVF_Q1
+                     ", %2\n\tv_mov_b64 " MVF_Q2 ", %3\n\tv_mov_b64 " MVF_Q3 ", %4\n\tv_mov_b64 " MVF_Q4
+                     ", %5\n\tv_mov_b64 " MVF_Q5 ", %6\n\tv_mov_b64 " MVF_Q6 ", %7\n\tv_mov_b64 " MVF_Q7
+                     ", %8\n\tv_mov_b64 " MVF_Q8 ", %9\n\tv_mov_b64 " MVF_Q9 ", %10\n\ts_set_gpr_idx_off"
+                     :: "s"(idx), "v"(x[0].lo), "v"(x[0].nh), "v"(x[1].lo), "v"(x[1].nh), "v"(x[2].lo), "v"(x[2].nh),
+                        "v"(x[3].lo), "v"(x[3].nh), "v"(x[4].lo), "v"(x[4].nh)
+                     : "m0");
+    }
+}
+
 // make the slot file part of the kernel's register allocation
 __device__ __forceinline__ void claim_slot_file() { asm volatile("" ::: "v255"); }
 

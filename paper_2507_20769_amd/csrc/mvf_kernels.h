@@ -14,8 +14,7 @@ constexpr int BLK = 256;            // lanes (subdomains) per workgroup
 struct TapeArgs {
     const Instr *prog;
     int32_t n_instr, n_roots, n, mode;
-    int32_t root_begin[MVF_MAX_ROOTS], root_len[MVF_MAX_ROOTS], root_slot[MVF_MAX_ROOTS];
-    int32_t root_rec[MVF_MAX_ROOTS];
+    int32_t root_base;       // program record index of root 0's {begin, len, result slot, records}
     int32_t nreg;            // register slots of the launch's tangent chunk; higher slot ids live in LDS
     int32_t spill_slots;     // LDS spill slots per lane (forward tangent passes)
 };
@@ -59,8 +58,19 @@ struct BatchArgs {
     double2 *gacc;           // reverse-mode gradient accumulators [n][grid * BLK] when not in LDS
 };
 
+// The bounding kernels take one argument struct each (at kernarg offset 0).
+struct BoundKArgs {
+    TapeArgs T;
+    BoxArgs B;
+};
+struct BatchKArgs {
+    TapeArgs T;
+    BatchArgs A;
+};
+
 #ifdef __HIPCC__
-__device__ __forceinline__ int node_count(const BatchArgs &A) { return A.n_nodes_dev ? *A.n_nodes_dev : A.n_nodes_val; }
+template <typename BA>     // BatchArgs in any address space
+__device__ __forceinline__ int node_count(const BA &A) { return A.n_nodes_dev ? *A.n_nodes_dev : A.n_nodes_val; }
 #endif
 
 hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev, int grid, size_t lds,
@@ -77,7 +87,7 @@ inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds, s
     size_t b = (size_t)n_instr * 16 + (size_t)tab_cap * 32;
     if (g_in_lds) b += (size_t)n * BLK * 16;
     b += spill;
-    b += (size_t)(BLK / 64) * (2 * m + 2) * 8;
+    b += ((size_t)(BLK / 64) * (2 * m + 3) * 8 + 15) & ~(size_t)15;   // per-wave reduction records
     b += (2 * MVF_MAX_VARS + 8) * 4;
     b = (b + 15) & ~(size_t)15;
     b += (size_t)n * BLK * sizeof(uint16_t);

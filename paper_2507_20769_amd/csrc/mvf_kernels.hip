@@ -52,21 +52,23 @@ __device__ __forceinline__ double breakpoint(double lo, double hi, int s, int j)
     return r < hi ? r : hi;
 }
 
-// Hide a pointer from the optimiser: loads through it are re-issued where they
-// are used (scalar-cache hits) instead of being hoisted into SGPRs that stay
-// live across the interpreter loop; SGPR pressure there spills into VGPR lanes.
-template <typename P>
-__device__ __forceinline__ const P *opaque(const P *p) {
-    const uint64_t v = reinterpret_cast<uint64_t>(p);
+// Kernel arguments are read through a pointer to the kernarg segment that the
+// optimiser cannot see through: every use re-issues a scalar load (a
+// scalar-cache hit) instead of keeping the loaded values in SGPRs across the
+// interpreter loops.
+template <typename K>
+using KPtr = const __attribute__((address_space(4))) K *;
+
+template <typename K>
+__device__ __forceinline__ KPtr<K> kargs() {
+    const uint64_t v = reinterpret_cast<uint64_t>(__builtin_amdgcn_kernarg_segment_ptr());
     uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
     asm volatile("" : "+s"(lo), "+s"(hi));
-    lo = __builtin_amdgcn_readfirstlane(lo);          // keeps the pointer wave-uniform
-    hi = __builtin_amdgcn_readfirstlane(hi);
-    return reinterpret_cast<const P *>((uint64_t)hi << 32 | lo);
+    return reinterpret_cast<KPtr<K>>((uint64_t)hi << 32 | lo);
 }
 
 struct Ctx {
-    const uint4 *prog;       // LDS program
+    const uint4 *prog;       // LDS program (root programs, then auxiliary records)
     const double4 *tab;      // LDS: {lo, nh, c, -c} per (dim, j)
     const uint16_t *vrec;    // LDS: [dim][BLK] table index of the lane's subdomain
     double2 *G;              // reverse-mode gradient accumulators of this lane ([dim] with stride gstride),
@@ -79,184 +81,284 @@ struct Ctx {
     int tid, blk;
 };
 
-template <int C>
-__device__ __forceinline__ void spill_read(const Ctx &X, uint32_t a, Iv &val, Iv (&tan)[C > 0 ? C : 1]) {
-    const double2 *p = X.spill + (size_t)(a - X.nreg) * (1 + C) * X.blk;
-    const double2 v = p[0];
-    val = Iv{v.x, v.y};
-#pragma unroll
-    for (int t = 0; t < C; ++t) {
-        const double2 w = p[(size_t)(t + 1) * X.blk];
-        tan[t] = Iv{w.x, w.y};
-    }
-}
-
-template <int C>
-__device__ __forceinline__ void spill_write(const Ctx &X, uint32_t a, const Iv &val, const Iv (&tan)[C > 0 ? C : 1]) {
-    double2 *p = X.spill + (size_t)(a - X.nreg) * (1 + C) * X.blk;
-    p[0] = make_double2(val.lo, val.nh);
-#pragma unroll
-    for (int t = 0; t < C; ++t) p[(size_t)(t + 1) * X.blk] = make_double2(tan[t].lo, tan[t].nh);
-}
-
 __device__ __forceinline__ double4 var_rec(const Ctx &X, uint32_t i) {
     return X.tab[X.vrec[i * X.blk + X.tid]];
 }
 
-// fetch operand (kind, a): value and C tangent components [c0, c0 + C)
-template <int C, bool POINT>
-__device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, double k, int c0, Iv &val,
-                                      Iv (&tan)[C > 0 ? C : 1]) {
-    constexpr uint32_t SD = 4 + 4 * C;
-    if (kind == K_SLOT) {
-        if (C > 0 && a >= X.nreg) spill_read<C>(X, a, val, tan);
-        else slot_read<C>(a * SD, val, tan);
-    } else if (kind == K_VAR) {
-        double4 r = var_rec(X, a);
-        val = POINT ? Iv{r.z, r.w} : Iv{r.x, r.y};
+__device__ __forceinline__ Iv aux_rec(const Ctx &X, uint32_t i) {
+    const uint4 r = X.prog[i];
+    return Iv{__hiloint2double((int)r.y, (int)r.x), __hiloint2double((int)r.w, (int)r.z)};
+}
+
+constexpr Iv kZero = {0.0, 0.0};
+constexpr Iv kOne = {1.0, -1.0};
+
+// Slot access for a pass carrying C tangent components: a slot holds the value
+// then the components, 4 dwords each, and is moved as a whole (one GPR-index
+// session); ids >= nreg live in LDS (tangent passes).
+template <int C>
+__device__ __forceinline__ void load_slot(const Ctx &X, uint32_t s, Iv (&A)[1 + C]) {
+    if (C > 0 && s >= X.nreg) {
+        const double2 *p = X.spill + (size_t)(s - X.nreg) * (1 + C) * X.blk;
 #pragma unroll
-        for (int t = 0; t < C; ++t) {
-            const bool hit = (int)a == c0 + t;
-            tan[t] = Iv{hit ? 1.0 : 0.0, hit ? -1.0 : 0.0};
+        for (int i = 0; i <= C; ++i) {
+            const double2 v = p[(size_t)i * X.blk];
+            A[i] = Iv{v.x, v.y};
         }
-    } else {
-        val = Iv{k, -k};
+        return;
+    }
+    slot_rd_n<1 + C>(s * (4 + 4 * C), A);
+}
+template <int C>
+__device__ __forceinline__ void store_slot(const Ctx &X, uint32_t s, const Iv (&Z)[1 + C]) {
+    if (C > 0 && s >= X.nreg) {
+        double2 *p = X.spill + (size_t)(s - X.nreg) * (1 + C) * X.blk;
 #pragma unroll
-        for (int t = 0; t < C; ++t) tan[t] = Iv{0.0, 0.0};
+        for (int i = 0; i <= C; ++i) p[(size_t)i * X.blk] = make_double2(Z[i].lo, Z[i].nh);
+        return;
+    }
+    slot_wr_n<1 + C>(s * (4 + 4 * C), Z);
+}
+
+// Operand (kind, a): value in A[0]; for a slot or the previous result the C
+// tangent components in A[1..C] (dense); for a variable, hit = its component
+// index within [c0, c0 + C) (its tangent is one there and zero elsewhere), -1
+// otherwise; constants have zero tangents.
+template <int C, bool POINT>
+__device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, double k, int c0,
+                                      const Iv (&P)[1 + C], Iv (&A)[1 + C], bool &dense, int &hit) {
+    dense = false;
+    hit = -1;
+    if (kind == K_SLOT) {
+        dense = true;
+        load_slot<C>(X, a, A);
+    } else if (kind == K_PREV) {
+        dense = true;
+#pragma unroll
+        for (int i = 0; i <= C; ++i) A[i] = P[i];
+    } else if (kind == K_VAR) {
+        const double4 r = var_rec(X, a);
+        A[0] = POINT ? Iv{r.z, r.w} : Iv{r.x, r.y};
+        const int h = (int)a - c0;
+        hit = h >= 0 && h < C ? h : -1;
+    } else {
+        A[0] = Iv{k, -k};
     }
 }
 
-struct Decoded {
-    uint32_t op, ak, bk, ia, ib, a, b, d;
+struct Dec {
+    uint32_t w0, op, ak, bk, a, b, d;
     double k;
 };
 
-__device__ __forceinline__ Decoded decode(const uint4 *P, int pc) {
-    uint4 raw = P[pc];
-    const uint32_t w0 = __builtin_amdgcn_readfirstlane(raw.x);
+__device__ __forceinline__ Dec decode(uint4 raw) {
+    Dec D;
+    D.w0 = __builtin_amdgcn_readfirstlane(raw.x);
     const uint32_t w1 = __builtin_amdgcn_readfirstlane(raw.y);
-    Decoded D;
     D.k = __hiloint2double((int)raw.w, (int)raw.z);
-    D.op = w0 & 0xffu;
-    D.ak = (w0 >> 8) & 3u;
-    D.bk = (w0 >> 10) & 3u;
-    D.ia = (w0 >> 12) & 1u;
-    D.ib = (w0 >> 13) & 1u;
-    D.a = w0 >> 16;
+    D.op = D.w0 & 31u;
+    D.ak = (D.w0 >> 5) & 3u;
+    D.bk = (D.w0 >> 7) & 3u;
+    D.a = D.w0 >> 16;
     D.b = w1 & 0xffffu;
     D.d = w1 >> 16;
     return D;
 }
 
+// Z[1 + h] = f(Z[1 + h]) for the hit component h of a variable operand
+#define MVF_AT_HIT(h, EXPR)                                 \
+    do {                                                    \
+        _Pragma("unroll") for (int t_ = 0; t_ < C; ++t_) {  \
+            if (t_ == (h)) { Iv &z = Z[1 + t_]; z = (EXPR); } \
+        }                                                   \
+    } while (0)
+
 // Run one root program forward; returns the root's value interval and (C > 0)
-// its tangent components [c0, c0 + C).  With TAPE, also writes the reverse-mode
-// records of every instruction.
+// its tangent components [c0, c0 + C).  Each instruction moves its operands
+// and its result as whole slots (value and components); a result consumed
+// only by the next instruction stays in registers (P).  With TAPE, writes the
+// reverse-mode records.
 template <int C, bool POINT, bool TAPE>
 __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0, Iv (&gout)[C > 0 ? C : 1],
                           uint32_t &bad) {
-    constexpr uint32_t SD = 4 + 4 * C;
+    constexpr int N = 1 + C;
+    Iv P[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) P[i] = kZero;
     int64_t rp = 0;                                    // record position
-    for (int pc = begin; pc < begin + len; ++pc) {
-        const Decoded I = decode(X.prog, pc);
-        Iv U, V, Z;
-        Iv dU[C > 0 ? C : 1], dV[C > 0 ? C : 1], dZ[C > 0 ? C : 1];
-        fetch<C, POINT>(X, I.ak, I.a, I.k, c0, U, dU);
-        if (I.op >= I_ADD && I.op <= I_DIV) fetch<C, POINT>(X, I.bk, I.b, I.k, c0, V, dV);
-        Iv r0, r1;                                     // records of this instruction
+    const int end = begin + len;
+    uint4 nxt = X.prog[begin];
+    for (int pc = begin; pc < end; ++pc) {
+        const Dec I = decode(nxt);
+        Iv A[N], B[N], Z[N];
+        bool ad, bd = false;
+        int ha, hb = -1;
+        fetch<C, POINT>(X, I.ak, I.a, I.k, c0, P, A, ad, ha);
+        if (I.op <= I_DIV) fetch<C, POINT>(X, I.bk, I.b, I.k, c0, P, B, bd, hb);
+        nxt = X.prog[pc + 1 < end ? pc + 1 : pc];      // prefetch the next instruction
+        const Iv U = A[0], V = B[0];
+#pragma unroll
+        for (int t = 1; t < N; ++t) Z[t] = kZero;
         switch (I.op) {
         case I_ADD:
-            Z = iadd(U, V);
+            Z[0] = iadd(U, V);
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-            for (int t = 0; t < C; ++t) dZ[t] = iadd(dU[t], dV[t]);
+                    for (int t = 1; t < N; ++t) Z[t] = A[t];
+                }
+                if (bd) {
+#pragma unroll
+                    for (int t = 1; t < N; ++t) Z[t] = iadd(Z[t], B[t]);     // exact when Z[t] is zero
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, iadd(z, kOne));
+                if (hb >= 0) MVF_AT_HIT(hb, iadd(z, kOne));
+            }
             break;
         case I_SUB:
-            Z = isub(U, V);
+            Z[0] = isub(U, V);
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-            for (int t = 0; t < C; ++t) dZ[t] = isub(dU[t], dV[t]);
+                    for (int t = 1; t < N; ++t) Z[t] = A[t];
+                }
+                if (bd) {
+#pragma unroll
+                    for (int t = 1; t < N; ++t) Z[t] = isub(Z[t], B[t]);     // exact negation when Z[t] is zero
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, iadd(z, kOne));
+                if (hb >= 0) MVF_AT_HIT(hb, isub(z, kOne));
+            }
             break;
         case I_MUL:
-            Z = imul(U, V);
+            Z[0] = imul(U, V);
+            if constexpr (TAPE) {
+                if (is_reg_kind(I.ak) && I.bk != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(U.lo, U.nh);
+                if (is_reg_kind(I.bk) && I.ak != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(V.lo, V.nh);
+            }
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-            for (int t = 0; t < C; ++t) dZ[t] = iadd(imul(V, dU[t]), imul(U, dV[t]));
-            r0 = U;
-            r1 = V;
+                    for (int t = 1; t < N; ++t) Z[t] = imul(V, A[t]);
+                }
+                if (bd) {
+#pragma unroll
+                    for (int t = 1; t < N; ++t) Z[t] = iadd(Z[t], imul(U, B[t]));   // exact when Z[t] is zero
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, iadd(z, V));
+                if (hb >= 0) MVF_AT_HIT(hb, iadd(z, U));
+            }
             break;
         case I_DIV: {
             bad |= (V.lo <= 0.0 && V.nh <= 0.0) ? 1u : 0u;
-            Z = idiv(U, V);
+            Z[0] = idiv(U, V);
             if constexpr (C > 0 || TAPE) {
-                Iv R = irecip(V);
+                const Iv R = irecip(V);
+                if constexpr (TAPE) {
+                    X.rec[(rp++) * X.rec_stride] = make_double2(R.lo, R.nh);
+                    if (I.bk != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(Z[0].lo, Z[0].nh);
+                }
+                if constexpr (C > 0) {
+                    // q = dU - Z dV, then dZ = q / V (times the enclosure of 1/V)
+                    if (ad) {
 #pragma unroll
-                for (int t = 0; t < C; ++t) dZ[t] = imul(isub(dU[t], imul(Z, dV[t])), R);
-                r0 = R;
-                r1 = Z;
+                        for (int t = 1; t < N; ++t) Z[t] = A[t];
+                    }
+                    if (bd) {
+#pragma unroll
+                        for (int t = 1; t < N; ++t) Z[t] = isub(Z[t], imul(Z[0], B[t]));
+                    }
+                    if (ha >= 0) MVF_AT_HIT(ha, iadd(z, kOne));
+                    if (hb >= 0) MVF_AT_HIT(hb, isub(z, Z[0]));
+                    if (ad || bd || ha >= 0 || hb >= 0) {
+#pragma unroll
+                        for (int t = 1; t < N; ++t) Z[t] = imul(Z[t], R);
+                    }
+                }
             }
             break;
         }
-        case I_SQR: {
-            Z = isqr(U);
-            if constexpr (C > 0 || TAPE) {
-                Iv T = itwice(U);
+        case I_SQR: case I_SQRT: case I_EXP: case I_LOG: {
+            Iv D = kZero;                               // local derivative
+            if (I.op == I_SQR) {
+                Z[0] = isqr(U);
+                if constexpr (C > 0 || TAPE) D = itwice(U);
+            } else if (I.op == I_SQRT) {
+                bad |= U.lo < 0.0 ? 1u : 0u;
+                Z[0] = isqrt(U);
+                if constexpr (C > 0 || TAPE) D = isqrt_deriv(Z[0]);
+            } else if (I.op == I_EXP) {
+                Z[0] = iexp(U);
+                D = Z[0];
+            } else {
+                bad |= U.lo <= 0.0 ? 1u : 0u;
+                Z[0] = ilog(U);
+                if constexpr (C > 0 || TAPE) D = irecip(U);
+            }
+            if constexpr (TAPE) {
+                if (I.ak != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(D.lo, D.nh);
+            }
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-                for (int t = 0; t < C; ++t) dZ[t] = imul(T, dU[t]);
-                r0 = T;
+                    for (int t = 1; t < N; ++t) Z[t] = imul(D, A[t]);
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, D);
             }
             break;
         }
-        case I_SQRT: {
-            bad |= U.lo < 0.0 ? 1u : 0u;
-            Z = isqrt(U);
-            if constexpr (C > 0 || TAPE) {
-                Iv R = isqrt_deriv(Z);
+        case I_ADDK: case I_KSUB: case I_LOAD: {
+            const bool ks = I.op == I_KSUB;
+            Z[0] = I.op == I_ADDK ? Iv{fadd(U.lo, I.k), fsub(U.nh, I.k)} : ks ? Iv{fadd(I.k, U.nh), fsub(U.lo, I.k)} : U;
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-                for (int t = 0; t < C; ++t) dZ[t] = imul(dU[t], R);
-                r0 = R;
+                    for (int t = 1; t < N; ++t) Z[t] = ks ? ineg(A[t]) : A[t];
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, ks ? ineg(kOne) : kOne);
             }
             break;
         }
-        case I_EXP:
-            Z = iexp(U);
+        case I_MULK: case I_MULKN: {
+            const bool ng = I.op == I_MULKN;
+            Z[0] = imulk(ng ? ineg(U) : U, I.k);
+            if constexpr (C > 0) {
+                if (ad) {
 #pragma unroll
-            for (int t = 0; t < C; ++t) dZ[t] = imul(Z, dU[t]);
-            r0 = Z;
-            break;
-        case I_LOG: {
-            bad |= U.lo <= 0.0 ? 1u : 0u;
-            Z = ilog(U);
-            if constexpr (C > 0 || TAPE) {
-                Iv R = irecip(U);
-#pragma unroll
-                for (int t = 0; t < C; ++t) dZ[t] = imul(dU[t], R);
-                r0 = R;
+                    for (int t = 1; t < N; ++t) Z[t] = imulk(ng ? ineg(A[t]) : A[t], I.k);
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, imulk(ng ? ineg(kOne) : kOne, I.k));
             }
             break;
         }
-        default:   // I_LOAD
-            Z = U;
+        default: {   // I_DIVK, I_DIVKN
+            const bool ng = I.op == I_DIVKN;
+            Z[0] = idivk(ng ? ineg(U) : U, I.k);
+            if constexpr (C > 0) {
+                const Iv R = aux_rec(X, I.b);
+                if (ad) {
 #pragma unroll
-            for (int t = 0; t < C; ++t) dZ[t] = dU[t];
+                    for (int t = 1; t < N; ++t) Z[t] = imul_pos(ng ? ineg(A[t]) : A[t], R);
+                }
+                if (ha >= 0) MVF_AT_HIT(ha, imul_pos(ng ? ineg(kOne) : kOne, R));
+            }
             break;
         }
-        if (C > 0 && I.d >= X.nreg) spill_write<C>(X, I.d, Z, dZ);
-        else slot_write<C>(I.d * SD, Z, dZ);
-        if constexpr (TAPE) {
-            // records in the order of n_records(): U then V, 1/V then Z, or the single partial
-            if (I.op == I_MUL) {
-                if (I.ak == K_SLOT && I.bk != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(r0.lo, r0.nh);
-                if (I.bk == K_SLOT && I.ak != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(r1.lo, r1.nh);
-            } else if (I.op == I_DIV) {
-                X.rec[(rp++) * X.rec_stride] = make_double2(r0.lo, r0.nh);
-                if (I.bk != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(r1.lo, r1.nh);
-            } else if (I.op >= I_SQR && I.op <= I_LOG) {
-                X.rec[(rp++) * X.rec_stride] = make_double2(r0.lo, r0.nh);
-            }
+        }
+        if (I.w0 & W0_NOWRITE) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) P[i] = Z[i];
+        } else {
+            store_slot<C>(X, I.d, Z);
         }
     }
-    Iv val;
-    if (C > 0 && (uint32_t)res_slot >= X.nreg) spill_read<C>(X, (uint32_t)res_slot, val, gout);
-    else slot_read<C>((uint32_t)res_slot * SD, val, gout);
-    return val;
+    Iv R[N];
+    load_slot<C>(X, (uint32_t)res_slot, R);
+#pragma unroll
+    for (int t = 0; t < C; ++t) gout[t] = R[1 + t];
+    return R[0];
 }
+#undef MVF_AT_HIT
 
 __device__ __forceinline__ Iv ld_rec(const Ctx &X, int64_t rp) {
     const double2 v = X.rec[rp * X.rec_stride];
@@ -264,12 +366,16 @@ __device__ __forceinline__ Iv ld_rec(const Ctx &X, int64_t rp) {
 }
 
 // adjoint contribution c to operand (kind, a); init: first contribution
-// (the slot is written, not accumulated); neg: subtract instead of add
-__device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t a, uint32_t init, bool neg, Iv c) {
-    if (kind == K_SLOT) {
+// (written, not accumulated); neg: subtract instead of add; pa is the adjoint
+// of the previous instruction's register-held result
+__device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t a, bool init, bool neg, Iv c,
+                                           Iv &pa) {
+    if (kind == K_PREV) {
+        pa = init ? (neg ? ineg(c) : c) : (neg ? isub(pa, c) : iadd(pa, c));   // 0 - [lo, hi] = [-hi, -lo]
+    } else if (kind == K_SLOT) {
         const uint32_t idx = a * 4;
         if (init) {
-            slot_wr(idx, neg ? Iv{c.nh, c.lo} : c);    // 0 - [lo, hi] = [-hi, -lo]
+            slot_wr(idx, neg ? ineg(c) : c);
         } else {
             const Iv s = slot_rd(idx);
             slot_wr(idx, neg ? isub(s, c) : iadd(s, c));
@@ -284,53 +390,61 @@ __device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t
 
 // Reverse sweep over one root program; the adjoint of the root is [1, 1].
 __device__ void reverse_sweep(const Ctx &X, int begin, int len, int res_slot, int64_t n_rec) {
-    slot_wr((uint32_t)res_slot * 4, Iv{1.0, -1.0});
+    slot_wr((uint32_t)res_slot * 4, kOne);
+    Iv pa = kZero;
     int64_t rp = n_rec;
+    uint4 nxt = X.prog[begin + len - 1];
     for (int pc = begin + len - 1; pc >= begin; --pc) {
-        const Decoded I = decode(X.prog, pc);
-        const Iv zb = slot_rd(I.d * 4);
+        const uint4 raw = nxt;
+        nxt = X.prog[pc > begin ? pc - 1 : pc];        // prefetch the next instruction
+        const Dec I = decode(raw);
+        const bool ia = (I.w0 & W0_INIT_A) != 0, ib = (I.w0 & W0_INIT_B) != 0;
+        const Iv zb = (I.w0 & W0_NOWRITE) ? pa : slot_rd(I.d * 4);
         switch (I.op) {
-        case I_ADD:
-            contribute(X, I.ak, I.a, I.ia, false, zb);
-            contribute(X, I.bk, I.b, I.ib, false, zb);
-            break;
-        case I_SUB:
-            contribute(X, I.ak, I.a, I.ia, false, zb);
-            contribute(X, I.bk, I.b, I.ib, true, zb);
+        case I_ADD: case I_SUB:
+            contribute(X, I.ak, I.a, ia, false, zb, pa);
+            contribute(X, I.bk, I.b, ib, I.op == I_SUB, zb, pa);
             break;
         case I_MUL: {
-            const bool hv = I.bk == K_SLOT && I.ak != K_CONST, hu = I.ak == K_SLOT && I.bk != K_CONST;
-            Iv V = {0.0, 0.0}, U = {0.0, 0.0};
+            const bool hv = is_reg_kind(I.bk) && I.ak != K_CONST, hu = is_reg_kind(I.ak) && I.bk != K_CONST;
+            Iv V = kZero, U = kZero;
             if (hv) V = ld_rec(X, --rp);
             if (hu) U = ld_rec(X, --rp);
             if (I.ak != K_CONST) {
                 if (I.bk == K_VAR) { const double4 r = var_rec(X, I.b); V = Iv{r.x, r.y}; }
                 else if (I.bk == K_CONST) V = Iv{I.k, -I.k};
-                contribute(X, I.ak, I.a, I.ia, false, imul(zb, V));
+                contribute(X, I.ak, I.a, ia, false, imul(zb, V), pa);
             }
             if (I.bk != K_CONST) {
                 if (I.ak == K_VAR) { const double4 r = var_rec(X, I.a); U = Iv{r.x, r.y}; }
                 else if (I.ak == K_CONST) U = Iv{I.k, -I.k};
-                contribute(X, I.bk, I.b, I.ib, false, imul(zb, U));
+                contribute(X, I.bk, I.b, ib, false, imul(zb, U), pa);
             }
             break;
         }
         case I_DIV: {
-            Iv Z = {0.0, 0.0};
+            Iv Z = kZero;
             if (I.bk != K_CONST) Z = ld_rec(X, --rp);
             const Iv R = ld_rec(X, --rp);
             const Iv T = imul(zb, R);
-            contribute(X, I.ak, I.a, I.ia, false, T);
-            if (I.bk != K_CONST) contribute(X, I.bk, I.b, I.ib, true, imul(T, Z));
+            contribute(X, I.ak, I.a, ia, false, T, pa);
+            if (I.bk != K_CONST) contribute(X, I.bk, I.b, ib, true, imul(T, Z), pa);
             break;
         }
-        case I_SQR: case I_SQRT: case I_EXP: case I_LOG: {
-            const Iv R = ld_rec(X, --rp);
-            contribute(X, I.ak, I.a, I.ia, false, imul(zb, R));
+        case I_SQR: case I_SQRT: case I_EXP: case I_LOG:
+            if (I.ak != K_CONST) {
+                const Iv R = ld_rec(X, --rp);
+                contribute(X, I.ak, I.a, ia, false, imul(zb, R), pa);
+            }
             break;
-        }
-        default:   // I_LOAD
-            contribute(X, I.ak, I.a, I.ia, false, zb);
+        case I_ADDK: case I_KSUB: case I_LOAD:
+            contribute(X, I.ak, I.a, ia, I.op == I_KSUB, zb, pa);
+            break;
+        case I_MULK: case I_MULKN:
+            contribute(X, I.ak, I.a, ia, false, imulk(I.op == I_MULKN ? ineg(zb) : zb, I.k), pa);
+            break;
+        default:     // I_DIVK, I_DIVKN
+            contribute(X, I.ak, I.a, ia, false, imul_pos(I.op == I_DIVKN ? ineg(zb) : zb, aux_rec(X, I.b)), pa);
             break;
         }
     }
@@ -353,27 +467,103 @@ __device__ __forceinline__ void wave_argmin(double &v, int64_t &k) {
     }
 }
 
-// Bounds of every root on the lane's subdomain, written to the result slots.
-// Returns the domain flag (violation or NaN).
+// Where a lane's results go: the optional per-subdomain output and the wave's
+// running reduction record in LDS.  The record holds, for each root r, the
+// minimum lower endpoint and the minimum of -upper at [2r], [2r + 1]; the
+// objective's argmin (value, subdomain) at [2m], [2m + 1]; and the smallest
+// flagged subdomain at [2m + 2].
+struct LaneOut {
+    double *per_sub;     // [m][2][S] or null
+    int64_t S, k;
+    double *w;           // the wave's record
+    int lane;
+    bool active;
+};
+
+constexpr int wred_len(int m) { return 2 * m + 3; }
+
+__device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const int64_t u = __shfl_xor(v, o, 64);
+        v = u < v ? u : v;
+    }
+    return v;
+}
+
+// Fold root r's bound on this lane's subdomain into the wave record.  A lane
+// whose subdomain is flagged later is fixed up by finish_lane.
+__device__ __forceinline__ void reduce_root(int r, int m, Iv B, const LaneOut &o) {
+    if (o.active && o.per_sub) {
+        o.per_sub[(int64_t)(2 * r) * o.S + o.k] = B.lo;
+        o.per_sub[(int64_t)(2 * r + 1) * o.S + o.k] = -B.nh;
+    }
+    const double lo = o.active && B.lo == B.lo ? B.lo : __builtin_inf();
+    const double nh = o.active && B.nh == B.nh ? B.nh : __builtin_inf();
+    const double wl = wave_min(lo), wn = wave_min(nh);
+    if (r == 0) {
+        double v = lo;
+        int64_t kk = o.active ? o.k : INT64_MAX;
+        wave_argmin(v, kk);
+        if (o.lane == 0) {
+            const double pv = o.w[2 * m];
+            const int64_t pk = reinterpret_cast<int64_t *>(o.w)[2 * m + 1];
+            if (v < pv || (v == pv && kk < pk)) {
+                o.w[2 * m] = v;
+                reinterpret_cast<int64_t *>(o.w)[2 * m + 1] = kk;
+            }
+        }
+    }
+    if (o.lane == 0) {
+        o.w[2 * r] = fmin(o.w[2 * r], wl);
+        o.w[2 * r + 1] = fmin(o.w[2 * r + 1], wn);
+    }
+}
+
+// After all roots: the domain flag, the per-subdomain bounds of a flagged
+// subdomain ([-inf, +inf] for every root), and the wave's smallest flagged
+// subdomain.
+__device__ __forceinline__ void finish_lane(int m, uint32_t bad, const LaneOut &o, uint32_t *flags) {
+    if (o.active && flags) flags[o.k] = bad;
+    if (o.active && bad && o.per_sub) {
+        for (int r = 0; r < m; ++r) {
+            o.per_sub[(int64_t)(2 * r) * o.S + o.k] = -__builtin_inf();
+            o.per_sub[(int64_t)(2 * r + 1) * o.S + o.k] = __builtin_inf();
+        }
+    }
+    const int64_t kb = wave_min_i64(o.active && bad ? o.k : INT64_MAX);
+    if (o.lane == 0) {
+        int64_t *wk = reinterpret_cast<int64_t *>(o.w);
+        wk[2 * m + 2] = kb < wk[2 * m + 2] ? kb : wk[2 * m + 2];
+    }
+}
+
+__device__ __forceinline__ void reset_wred(double *w, int m) {
+    for (int r = 0; r < 2 * m + 1; ++r) w[r] = __builtin_inf();
+    reinterpret_cast<int64_t *>(w)[2 * m + 1] = INT64_MAX;
+    reinterpret_cast<int64_t *>(w)[2 * m + 2] = INT64_MAX;
+}
+
+// Bounds of every root on the lane's subdomain, each folded into the wave's
+// reduction record as soon as it is known.  Returns the domain flag
+// (violation or NaN).
 template <int C, bool REV>
-__device__ uint32_t bound_lane(const TapeArgs &T0, const Ctx &X) {
-    const int m = opaque(&T0)->n_roots;
-    const uint32_t res_base = (uint32_t)usable_dwords(m);
+__device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx &X, const LaneOut &o) {
     mode_round_down();
     uint32_t bad = 0;
     for (int r = 0; r < m; ++r) {
-        const TapeArgs &T = *opaque(&T0);
-        const int n = T.n;
-        const int pb = T.root_begin[r], pl = T.root_len[r], rs = T.root_slot[r];
+        const uint4 ri = X.prog[root_base + r];
+        const int pb = (int)__builtin_amdgcn_readfirstlane(ri.x), pl = (int)__builtin_amdgcn_readfirstlane(ri.y);
+        const int rs = (int)__builtin_amdgcn_readfirstlane(ri.z);
         Iv B;
         Iv g0[1];
-        if (T.mode == MVF_MODE_NIE) {
+        if (mode == MVF_MODE_NIE) {
             B = run_program<0, false, false>(X, pb, pl, rs, 0, g0, bad);
         } else if constexpr (REV) {
             const Iv FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
             const Iv nie = run_program<0, false, true>(X, pb, pl, rs, 0, g0, bad);
             for (int i = 0; i < n; ++i) X.G[i * X.gstride] = make_double2(0.0, 0.0);
-            reverse_sweep(X, pb, pl, rs, T.root_rec[r]);
+            reverse_sweep(X, pb, pl, rs, (int64_t)__builtin_amdgcn_readfirstlane(ri.w));
             Iv acc = FC;
             for (int i = 0; i < n; ++i) {
                 const double4 rec = var_rec(X, (uint32_t)i);
@@ -381,11 +571,11 @@ __device__ uint32_t bound_lane(const TapeArgs &T0, const Ctx &X) {
                 const double2 g = X.G[i * X.gstride];
                 acc = iadd(acc, imul(Iv{g.x, g.y}, D));
             }
-            B = T.mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};
-        } else {
-            Iv G[C > 0 ? C : 1];
+            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};
+        } else if constexpr (C > 0) {
+            Iv G[C];
             const Iv FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
-            Iv acc = FC, nie = {0.0, 0.0};
+            Iv acc = FC, nie = kZero;
             for (int c0 = 0; c0 < n; c0 += C) {
                 Iv v = run_program<C, false, false>(X, pb, pl, rs, c0, G, bad);
                 if (c0 == 0) nie = v;
@@ -398,20 +588,20 @@ __device__ uint32_t bound_lane(const TapeArgs &T0, const Ctx &X) {
                     }
                 }
             }
-            B = T.mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};
+            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};
+        } else {
+            B = kZero;   // not launched: a forward gradient needs tangent components
         }
-        slot_wr(res_base + 4 * r, B);
+        if (B.lo != B.lo || B.nh != B.nh) bad = 1;
+        reduce_root(r, m, B, o);
     }
     mode_round_nearest();
-    for (int r = 0; r < m; ++r) {
-        Iv B = slot_rd(res_base + 4 * r);
-        if (B.lo != B.lo || B.nh != B.nh) bad = 1;
-    }
     return bad;
 }
 
 // stage the programs into LDS (whole workgroup)
-__device__ __forceinline__ void stage_program(const TapeArgs &T, uint4 *lprog, int tid, int blk) {
+template <typename TA>
+__device__ __forceinline__ void stage_program(const TA &T, uint4 *lprog, int tid, int blk) {
     const uint4 *src = reinterpret_cast<const uint4 *>(T.prog);
     for (int i = tid; i < T.n_instr; i += blk) lprog[i] = src[i];
 }
@@ -451,7 +641,8 @@ struct Smem {
     int32_t *ints;     // splits[MVF_MAX_VARS], tab_off[MVF_MAX_VARS + 1], scratch
 };
 
-__device__ __forceinline__ Smem carve(uint8_t *smem, const TapeArgs &T, int tab_cap, int blk, bool g_lds, int chunk) {
+template <typename TA>     // TapeArgs in any address space
+__device__ __forceinline__ Smem carve(uint8_t *smem, const TA &T, int tab_cap, int blk, bool g_lds, int chunk) {
     Smem s;
     uint8_t *p = smem;
     s.prog = reinterpret_cast<uint4 *>(p);
@@ -463,65 +654,24 @@ __device__ __forceinline__ Smem carve(uint8_t *smem, const TapeArgs &T, int tab_
     s.spill = reinterpret_cast<double2 *>(p);
     p += (size_t)T.spill_slots * (1 + chunk) * 16 * blk;
     s.wred = reinterpret_cast<double *>(p);
-    p += (size_t)(blk / 64) * (2 * T.n_roots + 2) * 8;
+    p += (size_t)(blk / 64) * wred_len(T.n_roots) * 8;       // 32 (2m + 3) bytes: 16-byte aligned
     s.ints = reinterpret_cast<int32_t *>(p);
-    p += (2 * MVF_MAX_VARS + 8) * 4;
-    p = reinterpret_cast<uint8_t *>((reinterpret_cast<uintptr_t>(p) + 15) & ~uintptr_t(15));
+    p += (2 * MVF_MAX_VARS + 8) * 4;       // every region above is a multiple of 16 bytes
     s.vrec = reinterpret_cast<uint16_t *>(p);
     return s;
 }
 
-// Per-wave reduction of the lanes' result slots into the wave's LDS record
-// (running min over calls); per_sub/flags written for active lanes.
-__device__ __forceinline__ void reduce_lane(const TapeArgs &T, double *w, bool active, int64_t k, uint32_t bad,
-                                            double *per_sub, int64_t S, uint32_t *flags, int lane) {
-    const int m = T.n_roots;
-    const uint32_t res_base = (uint32_t)usable_dwords(m);
-    for (int r = 0; r < m; ++r) {
-        Iv B = slot_rd(res_base + 4 * r);
-        if (bad) B = Iv{-__builtin_inf(), -__builtin_inf()};
-        if (active && per_sub) {
-            per_sub[(int64_t)(2 * r) * S + k] = B.lo;
-            per_sub[(int64_t)(2 * r + 1) * S + k] = -B.nh;
-        }
-        const double lo = active ? B.lo : __builtin_inf();
-        const double nh = active ? B.nh : __builtin_inf();
-        const double wl = wave_min(lo), wn = wave_min(nh);
-        if (r == 0) {
-            double v = lo;
-            int64_t kk = active ? k : INT64_MAX;
-            wave_argmin(v, kk);
-            if (lane == 0) {
-                const double pv = w[2 * m];
-                const int64_t pk = reinterpret_cast<int64_t *>(w)[2 * m + 1];
-                if (v < pv || (v == pv && kk < pk)) {
-                    w[2 * m] = v;
-                    reinterpret_cast<int64_t *>(w)[2 * m + 1] = kk;
-                }
-            }
-        }
-        if (lane == 0) {
-            w[2 * r] = fmin(w[2 * r], wl);
-            w[2 * r + 1] = fmin(w[2 * r + 1], wn);
-        }
-    }
-    if (active && flags) flags[k] = bad;
-}
-
-__device__ __forceinline__ void reset_wred(double *w, int m) {
-    for (int r = 0; r < 2 * m + 1; ++r) w[r] = __builtin_inf();
-    reinterpret_cast<int64_t *>(w)[2 * m + 1] = INT64_MAX;
-}
-
-// combine the waves' records into one partial (thread 0)
+// Combine the waves' records into one partial (thread 0).  Any flagged
+// subdomain makes every root's hull [-inf, +inf]; the objective's argmin is
+// then the smallest subdomain whose lower bound is -inf.
 __device__ __forceinline__ void write_partial(const double *wred, int waves, int m, double *part, double *plo0,
                                               int64_t *pk) {
     double best = __builtin_inf();
-    int64_t bk = INT64_MAX;
+    int64_t bk = INT64_MAX, kb = INT64_MAX;
     for (int r = 0; r < m; ++r) {
         double l = __builtin_inf(), h = __builtin_inf();
         for (int w = 0; w < waves; ++w) {
-            const double *wr = wred + w * (2 * m + 2);
+            const double *wr = wred + w * wred_len(m);
             l = fmin(l, wr[2 * r]);
             h = fmin(h, wr[2 * r + 1]);
         }
@@ -529,10 +679,17 @@ __device__ __forceinline__ void write_partial(const double *wred, int waves, int
         part[2 * r + 1] = h;
     }
     for (int w = 0; w < waves; ++w) {
-        const double *wr = wred + w * (2 * m + 2);
+        const double *wr = wred + w * wred_len(m);
         const double v = wr[2 * m];
         const int64_t kk = reinterpret_cast<const int64_t *>(wr)[2 * m + 1];
         if (v < best || (v == best && kk < bk)) { best = v; bk = kk; }
+        const int64_t f = reinterpret_cast<const int64_t *>(wr)[2 * m + 2];
+        kb = f < kb ? f : kb;
+    }
+    if (kb != INT64_MAX) {
+        for (int r = 0; r < 2 * m; ++r) part[r] = -__builtin_inf();
+        bk = best == -__builtin_inf() && bk < kb ? bk : kb;
+        best = -__builtin_inf();
     }
     *plo0 = best;
     *pk = bk;
@@ -544,46 +701,66 @@ __device__ __forceinline__ void write_partial(const double *wred, int waves, int
 // single box
 // ---------------------------------------------------------------------------
 template <int C, bool REV>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amdgpu_waves_per_eu(5, 5))) void bound_kernel(TapeArgs T,
-                                                                                               BoxArgs B) {
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amdgpu_waves_per_eu(4, 4))) void bound_kernel(
+    BoundKArgs /* read through kargs() */) {
     using namespace dev;
     extern __shared__ __align__(16) uint8_t smem[];
     claim_slot_file();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = T.n_roots, n = T.n;
-    const bool g_lds = B.gacc == nullptr;
-    Smem s = carve(smem, T, B.tab_off[n], BLK, REV && g_lds, C);
-    stage_program(T, s.prog, tid, BLK);
-    if (tid <= n) s.ints[MVF_MAX_VARS + tid] = B.tab_off[tid];
-    if (tid < n) s.ints[tid] = B.splits[tid];
-    __syncthreads();
-    build_table(n, B.box, s.ints, s.ints + MVF_MAX_VARS, s.tab, tid, BLK);
-    if (lane == 0) reset_wred(s.wred + wave * (2 * m + 2), m);
-    __syncthreads();
-
+    Smem s;
     Ctx X;
+    int m, n;
+    {
+        const auto K = kargs<BoundKArgs>();
+        m = K->T.n_roots;
+        n = K->T.n;
+        const bool g_lds = K->B.gacc == nullptr;
+        s = carve(smem, K->T, K->B.tab_off[n], BLK, REV && g_lds, C);
+        stage_program(K->T, s.prog, tid, BLK);
+        if (tid <= n) s.ints[MVF_MAX_VARS + tid] = K->B.tab_off[tid];
+        if (tid < n) s.ints[tid] = K->B.splits[tid];
+        __syncthreads();
+        build_table(n, K->B.box, s.ints, s.ints + MVF_MAX_VARS, s.tab, tid, BLK);
+        if (lane == 0) reset_wred(s.wred + wave * wred_len(m), m);
+        X.G = g_lds ? s.G + tid : K->B.gacc + (int64_t)blockIdx.x * BLK + tid;
+        X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
+        X.rec = K->B.rec + (int64_t)blockIdx.x * BLK + tid;
+        X.nreg = (uint32_t)K->T.nreg;
+    }
+    __syncthreads();
     X.prog = s.prog;
     X.tab = s.tab;
     X.vrec = s.vrec;
-    X.G = g_lds ? s.G + tid : B.gacc + (int64_t)blockIdx.x * BLK + tid;
-    X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
     X.tid = tid;
     X.blk = BLK;
     X.rec_stride = (int64_t)gridDim.x * BLK;
-    X.rec = B.rec + (int64_t)blockIdx.x * BLK + tid;
     X.spill = s.spill + tid;
-    X.nreg = (uint32_t)T.nreg;
-    for (int64_t base = (int64_t)blockIdx.x * BLK; base < B.S; base += (int64_t)gridDim.x * BLK) {
+    for (int64_t base = (int64_t)blockIdx.x * BLK;; base += (int64_t)gridDim.x * BLK) {
+        const int64_t S = kargs<BoundKArgs>()->B.S;
+        if (base >= S) break;
         const int64_t k = base + tid;
-        const bool active = k < B.S;
-        decode_subdomain(n, active ? k : B.S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
-        const uint32_t bad = bound_lane<C, REV>(T, X);
-        reduce_lane(T, s.wred + wave * (2 * m + 2), active, k, bad, B.per_sub, B.S, B.flags, lane);
+        const bool active = k < S;
+        decode_subdomain(n, active ? k : S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
+        LaneOut o;
+        uint32_t bad;
+        {
+            const auto K = kargs<BoundKArgs>();
+            o.per_sub = K->B.per_sub;
+            o.S = S;
+            o.k = k;
+            o.w = s.wred + wave * wred_len(m);
+            o.lane = lane;
+            o.active = active;
+            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o);
+        }
+        finish_lane(m, bad, o, kargs<BoundKArgs>()->B.flags);
     }
     __syncthreads();
-    if (tid == 0)
-        write_partial(s.wred, BLK / 64, m, B.partial + (size_t)blockIdx.x * m * 2, B.partial_lo0 + blockIdx.x,
-                      B.partial_k + blockIdx.x);
+    if (tid == 0) {
+        const auto K = kargs<BoundKArgs>();
+        write_partial(s.wred, BLK / 64, m, K->B.partial + (size_t)blockIdx.x * m * 2, K->B.partial_lo0 + blockIdx.x,
+                      K->B.partial_k + blockIdx.x);
+    }
 }
 
 // Reduce per-block partials [nblocks][m][2] into reduced[m][2] (lo, hi) and argmin.
@@ -693,53 +870,64 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs A) {
 }
 
 template <int C, bool REV>
-__global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amdgpu_waves_per_eu(5, 5))) void batch_kernel(TapeArgs T,
-                                                                                               BatchArgs A0) {
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amdgpu_waves_per_eu(4, 4))) void batch_kernel(
+    BatchKArgs /* read through kargs() */) {
     using namespace dev;
     extern __shared__ __align__(16) uint8_t smem[];
     claim_slot_file();
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = T.n_roots, n = T.n;
-    const int N = node_count(A0);
-    const bool g_lds = A0.gacc == nullptr;
-    Smem s = carve(smem, T, A0.tab_cap, BLK, REV && g_lds, C);
     __shared__ int64_t sh_item;
     __shared__ int sh_node;
-    stage_program(T, s.prog, tid, BLK);
-
+    Smem s;
     Ctx X;
+    int m, n;
+    {
+        const auto K = kargs<BatchKArgs>();
+        m = K->T.n_roots;
+        n = K->T.n;
+        const bool g_lds = K->A.gacc == nullptr;
+        s = carve(smem, K->T, K->A.tab_cap, BLK, REV && g_lds, C);
+        stage_program(K->T, s.prog, tid, BLK);
+        X.G = g_lds ? s.G + tid : K->A.gacc + (int64_t)blockIdx.x * BLK + tid;
+        X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
+        X.rec = K->A.rec + (int64_t)blockIdx.x * BLK + tid;
+        X.nreg = (uint32_t)K->T.nreg;
+    }
     X.prog = s.prog;
     X.tab = s.tab;
     X.vrec = s.vrec;
-    X.G = g_lds ? s.G + tid : A0.gacc + (int64_t)blockIdx.x * BLK + tid;
-    X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
     X.tid = tid;
     X.blk = BLK;
     X.rec_stride = (int64_t)gridDim.x * BLK;
-    X.rec = A0.rec + (int64_t)blockIdx.x * BLK + tid;
     X.spill = s.spill + tid;
-    X.nreg = (uint32_t)T.nreg;
-    const int64_t total = A0.item_off[N];
     int cur = -1;
     for (;;) {
-        const BatchArgs &A = *opaque(&A0);
-        if (tid == 0) sh_item = atomicAdd(reinterpret_cast<unsigned long long *>(A.counter), 1ull);
+        {
+            const auto K = kargs<BatchKArgs>();
+            if (tid == 0) sh_item = atomicAdd(reinterpret_cast<unsigned long long *>(K->A.counter), 1ull);
+        }
         __syncthreads();
         const int64_t item = sh_item;
-        if (item >= total) break;                       // uniform exit: every wave reaches it
-        if (tid == 0) {                                 // node owning the item: last node with item_off <= item
-            int lo = 0, hi = N - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (A.item_off[mid] <= item) lo = mid; else hi = mid - 1;
+        int N;
+        {
+            const auto K = kargs<BatchKArgs>();
+            N = node_count(K->A);
+            if (item >= K->A.item_off[N]) break;           // uniform exit: every wave reaches it
+            if (tid == 0) {                                 // node owning the item: last node with item_off <= item
+                int lo = 0, hi = N - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (K->A.item_off[mid] <= item) lo = mid; else hi = mid - 1;
+                }
+                while (lo < N - 1 && K->A.item_off[lo + 1] <= item) ++lo;   // skip nodes without items
+                sh_node = lo;
             }
-            while (lo < N - 1 && A.item_off[lo + 1] <= item) ++lo;   // skip nodes without items
-            sh_node = lo;
         }
         __syncthreads();
         const int node = sh_node;
         if (node != cur) {                              // new node: splits, offsets, breakpoint table
-            if (tid < n) s.ints[tid] = A.splits[(int64_t)node * n + tid];
+            const auto K = kargs<BatchKArgs>();
+            if (tid < n) s.ints[tid] = K->A.splits[(int64_t)node * n + tid];
             __syncthreads();
             if (tid == 0) {
                 int acc = 0;
@@ -747,21 +935,38 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
                 s.ints[MVF_MAX_VARS + n] = acc;
             }
             __syncthreads();
-            build_table(n, A.boxes + (int64_t)node * n * 2, s.ints, s.ints + MVF_MAX_VARS, s.tab, tid, BLK);
+            build_table(n, K->A.boxes + (int64_t)node * n * 2, s.ints, s.ints + MVF_MAX_VARS, s.tab, tid, BLK);
             cur = node;
         }
-        if (lane == 0) reset_wred(s.wred + wave * (2 * m + 2), m);
+        if (lane == 0) reset_wred(s.wred + wave * wred_len(m), m);
         __syncthreads();
-        const int64_t S = A.node_S[node];
-        const int64_t k = (item - A.item_off[node]) * BLK + tid;
+        int64_t S, k;
+        {
+            const auto K = kargs<BatchKArgs>();
+            S = K->A.node_S[node];
+            k = (item - K->A.item_off[node]) * BLK + tid;
+        }
         const bool active = k < S;
         decode_subdomain(n, active ? k : S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
-        const uint32_t bad = bound_lane<C, REV>(T, X);
-        reduce_lane(T, s.wred + wave * (2 * m + 2), active, k, bad, nullptr, S, nullptr, lane);
+        LaneOut o;
+        o.per_sub = nullptr;
+        o.S = S;
+        o.k = k;
+        o.w = s.wred + wave * wred_len(m);
+        o.lane = lane;
+        o.active = active;
+        uint32_t bad;
+        {
+            const auto K = kargs<BatchKArgs>();
+            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o);
+        }
+        finish_lane(m, bad, o, nullptr);
         __syncthreads();
-        if (tid == 0)
-            write_partial(s.wred, BLK / 64, m, A.partial + (size_t)item * m * 2, A.partial_lo0 + item,
-                          A.partial_k + item);
+        if (tid == 0) {
+            const auto K = kargs<BatchKArgs>();
+            write_partial(s.wred, BLK / 64, m, K->A.partial + (size_t)item * m * 2, K->A.partial_lo0 + item,
+                          K->A.partial_k + item);
+        }
     }
 }
 
@@ -821,33 +1026,39 @@ static hipError_t allow_lds(K kernel) {
                                (int)(LDS_BUDGET - 1024));
 }
 
-#define MVF_DISPATCH(C_, REV_, CALL)                       \
-    do {                                                   \
-        if (REV_) {                                        \
-            constexpr int Cx = 0; constexpr bool Rx = true; \
-            CALL;                                          \
-        } else if ((C_) == 0) {                            \
-            constexpr int Cx = 0; constexpr bool Rx = false; \
-            CALL;                                          \
-        } else if ((C_) == 1) {                            \
-            constexpr int Cx = 1; constexpr bool Rx = false; \
-            CALL;                                          \
-        } else {                                           \
-            constexpr int Cx = 2; constexpr bool Rx = false; \
-            CALL;                                          \
-        }                                                  \
+#define MVF_DISPATCH(C_, REV_, CALL)                            \
+    do {                                                        \
+        if (REV_) {                                             \
+            constexpr int Cx = 0; constexpr bool Rx = true;     \
+            CALL;                                               \
+        } else if ((C_) == 0) {                                 \
+            constexpr int Cx = 0; constexpr bool Rx = false;    \
+            CALL;                                               \
+        } else if ((C_) == 1) {                                 \
+            constexpr int Cx = 1; constexpr bool Rx = false;    \
+            CALL;                                               \
+        } else if ((C_) == 2) {                                 \
+            constexpr int Cx = 2; constexpr bool Rx = false;    \
+            CALL;                                               \
+        } else if ((C_) == 3) {                                 \
+            constexpr int Cx = 3; constexpr bool Rx = false;    \
+            CALL;                                               \
+        } else {                                                \
+            constexpr int Cx = 4; constexpr bool Rx = false;    \
+            CALL;                                               \
+        }                                                       \
     } while (0)
 
 hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev, int grid, size_t lds,
                         hipStream_t stream) {
-    static_assert(MAX_CHUNK == 2, "one kernel instance per chunk size");
+    static_assert(MAX_CHUNK == 4, "one kernel instance per chunk size");
     hipError_t e = hipSuccess;
     MVF_DISPATCH(chunk, rev, {
         static std::once_flag once;
         static hipError_t ae = hipSuccess;
         std::call_once(once, [] { ae = allow_lds(bound_kernel<Cx, Rx>); });
         if (ae != hipSuccess) return ae;
-        hipLaunchKernelGGL((bound_kernel<Cx, Rx>), dim3(grid), dim3(BLK), lds, stream, T, B);
+        hipLaunchKernelGGL((bound_kernel<Cx, Rx>), dim3(grid), dim3(BLK), lds, stream, BoundKArgs{T, B});
     });
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -866,7 +1077,7 @@ hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool r
         static hipError_t ae = hipSuccess;
         std::call_once(once, [] { ae = allow_lds(batch_kernel<Cx, Rx>); });
         if (ae != hipSuccess) return ae;
-        hipLaunchKernelGGL((batch_kernel<Cx, Rx>), dim3(grid), dim3(BLK), lds, stream, T, A);
+        hipLaunchKernelGGL((batch_kernel<Cx, Rx>), dim3(grid), dim3(BLK), lds, stream, BatchKArgs{T, A});
     });
     e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -9,7 +9,9 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
+#include <cstring>
 
 #include "mvf_internal.h"
 
@@ -40,6 +42,17 @@ void ref_cost(int op, bool a_const, bool b_const, int *val, int *tan, int *adj) 
     case MVF_EXP: case MVF_LOG: *val = 2; *tan = 14; *adj = 16; return;
     default: *val = 0; *tan = 0; *adj = 0;
     }
+}
+
+// Enclosure [RD(1/k), RU(1/k)] of 1/k for k > 0: the round-to-nearest quotient
+// and its neighbour on the side of the exact value.  fma is correctly rounded,
+// so the sign of fma(q, k, -1) is the sign of the exact residual q*k - 1.
+void recip_enclosure(double k, double *lo, double *hi) {
+    const double q = 1.0 / k;
+    const double r = std::fma(q, k, -1.0);
+    if (r == 0.0) { *lo = q; *hi = q; }
+    else if (r > 0.0) { *lo = std::nextafter(q, -INFINITY); *hi = q; }
+    else { *lo = q; *hi = std::nextafter(q, INFINITY); }
 }
 
 int fail(std::string *err, int code, const char *fmt, long a = 0, long b = 0) {
@@ -79,8 +92,9 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
 
     Compiled C;
     C.n_vars = n_vars;
-    std::vector<uint8_t> in_cone(n_nodes);
-    std::vector<int32_t> slot_of(n_nodes, -1), last_use(n_nodes, -1);
+    std::vector<uint8_t> in_cone(n_nodes), in_regs(n_nodes);
+    std::vector<int32_t> slot_of(n_nodes, -1), last_use(n_nodes, -1), uses(n_nodes, 0);
+    std::vector<double> aux;            // reciprocal enclosures of constant divisors, (lo, -hi) pairs
     int64_t sum_val = 0, sum_tan = 0, sum_adj = 0, n_ops = 0;
 
     for (int r = 0; r < n_roots; ++r) {
@@ -102,18 +116,20 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             C.roots.push_back(P);
             continue;
         }
-        // program position of each arithmetic node, then last uses
+        // program order of the arithmetic nodes, their uses and last uses
         std::vector<int32_t> order;
         for (int i = 0; i <= roots[r]; ++i)
             if (in_cone[i] && !is_leaf(nodes[i].op)) order.push_back(i);
-        std::vector<int32_t> pos(n_nodes, -1);
-        for (size_t p = 0; p < order.size(); ++p) pos[order[p]] = (int32_t)p;
-        for (int i : order) last_use[i] = -1;
+        for (int i : order) { last_use[i] = -1; uses[i] = 0; in_regs[i] = 0; }
         for (size_t p = 0; p < order.size(); ++p) {
             const mvf_node &nd = nodes[order[p]];
-            if (!is_leaf(nodes[nd.a].op)) last_use[nd.a] = (int32_t)p;
-            if (is_binary(nd.op) && !is_leaf(nodes[nd.b].op)) last_use[nd.b] = (int32_t)p;
+            if (!is_leaf(nodes[nd.a].op)) { last_use[nd.a] = (int32_t)p; ++uses[nd.a]; }
+            if (is_binary(nd.op) && !is_leaf(nodes[nd.b].op)) { last_use[nd.b] = (int32_t)p; ++uses[nd.b]; }
         }
+        auto refs = [&](int j, int i) {          // operand references of node j to node i
+            const mvf_node &nd = nodes[j];
+            return (nd.a == i ? 1 : 0) + (is_binary(nd.op) && nd.b == i ? 1 : 0);
+        };
         // linear scan over a pool of slots (lowest free id first)
         std::vector<uint8_t> busy;
         auto take = [&]() {
@@ -122,44 +138,86 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             busy.push_back(1);
             return (int32_t)busy.size() - 1;
         };
+        auto operand = [&](int node, uint32_t *kind, uint32_t *idx, double *k) {
+            const mvf_node &nd = nodes[node];
+            if (nd.op == MVF_VAR) { *kind = K_VAR; *idx = (uint32_t)nd.a; }
+            else if (nd.op == MVF_CONST) { *kind = K_CONST; *idx = 0; *k = consts[nd.a]; }
+            else if (in_regs[node]) { *kind = K_PREV; *idx = 0; }
+            else { *kind = K_SLOT; *idx = (uint32_t)slot_of[node]; }
+        };
         for (size_t p = 0; p < order.size(); ++p) {
-            int i = order[p];
+            const int i = order[p];
             const mvf_node &nd = nodes[i];
             const bool bin = is_binary(nd.op);
-            const mvf_node &na = nodes[nd.a];
-            const mvf_node *nb = bin ? &nodes[nd.b] : nullptr;
-            uint32_t ak, a, bk = K_SLOT, b = 0;
-            double k = 0.0;
-            bool a_const = na.op == MVF_CONST, b_const = bin && nb->op == MVF_CONST;
-            int32_t tmp = -1;
-            if (a_const && b_const) {        // materialise operand a so at most one constant remains
-                tmp = take();
-                C.instr.push_back(make_instr(I_LOAD, K_CONST, 0, K_SLOT, 0, (uint32_t)tmp, consts[na.a]));
-                ak = K_SLOT; a = (uint32_t)tmp;
-            } else if (na.op == MVF_VAR) { ak = K_VAR; a = (uint32_t)na.a; }
-            else if (a_const) { ak = K_CONST; a = 0; k = consts[na.a]; }
-            else { ak = K_SLOT; a = (uint32_t)slot_of[nd.a]; }
-            if (bin) {
-                if (nb->op == MVF_VAR) { bk = K_VAR; b = (uint32_t)nb->a; }
-                else if (b_const) { bk = K_CONST; b = 0; k = consts[nb->a]; }
-                else { bk = K_SLOT; b = (uint32_t)slot_of[nd.b]; }
+            const bool a_const = nodes[nd.a].op == MVF_CONST, b_const = bin && nodes[nd.b].op == MVF_CONST;
+            uint32_t ak, a, bk = K_SLOT, b = 0, init = 0;
+            double ka = 0.0, kb = 0.0;
+            if (a_const && b_const) {
+                // materialise operand a: a load whose only consumer is this instruction
+                C.instr.push_back(make_instr(I_LOAD, K_CONST, 0, K_SLOT, 0, 0, consts[nodes[nd.a].a]));
+                C.instr.back().w0 |= W0_NOWRITE;
+                ak = K_PREV; a = 0;
+                init |= 1u;
+            } else {
+                operand(nd.a, &ak, &a, &ka);
             }
-            // release operands dying here, then allocate the result (it may reuse them).
-            // A dying operand's adjoint receives its first contribution here in the
-            // reverse sweep: its slot is initialised instead of accumulated.
-            uint32_t init = 0;
-            if (tmp >= 0) { busy[tmp] = 0; init |= 1u; }
-            if (!is_leaf(na.op) && last_use[nd.a] == (int32_t)p) { busy[slot_of[nd.a]] = 0; init |= 1u; }
-            if (bin && !is_leaf(nb->op) && last_use[nd.b] == (int32_t)p) {
-                busy[slot_of[nd.b]] = 0;
+            if (bin) operand(nd.b, &bk, &b, &kb);
+            // release operands dying here; a dying operand's adjoint receives its first
+            // contribution here in the reverse sweep (written instead of accumulated)
+            if (!is_leaf(nodes[nd.a].op) && last_use[nd.a] == (int32_t)p) {
+                if (!in_regs[nd.a]) busy[slot_of[nd.a]] = 0;
+                init |= 1u;
+            }
+            if (bin && !is_leaf(nodes[nd.b].op) && last_use[nd.b] == (int32_t)p) {
+                if (!in_regs[nd.b] && nd.b != nd.a) busy[slot_of[nd.b]] = 0;
                 if (nd.b != nd.a) init |= 2u;
             }
-            int32_t d = take();
-            slot_of[i] = d;
-            Instr ins = make_instr((uint32_t)nd.op, ak, a, bk, b, (uint32_t)d, k);
-            ins.w0 |= init << 12;
+            // the result stays in registers when the next node is its only consumer
+            const bool nowrite = i != roots[r] && p + 1 < order.size() && uses[i] == refs(order[p + 1], i) &&
+                                 uses[i] > 0;
+            int32_t d = 0;
+            if (nowrite) in_regs[i] = 1;
+            else { d = take(); slot_of[i] = d; }
+
+            // constant-operand forms: the other operand moves to position a
+            uint32_t op = (uint32_t)nd.op;
+            double k = a_const && !b_const ? ka : kb;
+            const bool one_const = bin && (a_const != b_const);
+            if (one_const) {
+                const uint32_t xk = a_const ? bk : ak, xi = a_const ? b : a;
+                const uint32_t xinit = a_const ? (init >> 1) & 1u : init & 1u;
+                bool special = true;
+                switch (nd.op) {
+                case MVF_ADD: op = I_ADDK; break;
+                case MVF_SUB: op = a_const ? I_KSUB : I_ADDK; if (!a_const) k = -k; break;
+                case MVF_MUL:
+                    if (k == 0.0) special = false;
+                    else { op = std::signbit(k) ? I_MULKN : I_MULK; k = std::fabs(k); }
+                    break;
+                case MVF_DIV:
+                    if (a_const || k == 0.0) { special = false; break; }
+                    op = std::signbit(k) ? I_DIVKN : I_DIVK;
+                    k = std::fabs(k);
+                    b = (uint32_t)(aux.size() / 2);       // aux record index, relocated below
+                    {
+                        double lo, hi;
+                        recip_enclosure(k, &lo, &hi);
+                        aux.push_back(lo);
+                        aux.push_back(-hi);
+                    }
+                    break;
+                default: special = false;
+                }
+                if (special) {
+                    if (op != I_DIVK && op != I_DIVKN) b = 0;
+                    ak = xk; a = xi; bk = K_CONST;
+                    init = xinit;
+                }
+            }
+            Instr ins = make_instr(op, ak, a, bk, b, (uint32_t)d, k);
+            ins.w0 |= (init & 1u ? W0_INIT_A : 0u) | (init & 2u ? W0_INIT_B : 0u) | (nowrite ? W0_NOWRITE : 0u);
             C.instr.push_back(ins);
-            P.n_rec += n_records((uint32_t)nd.op, ak, bk);
+            P.n_rec += n_records(op, ak, bk);
             int cv, ct, ca;
             ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
             sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
@@ -170,9 +228,30 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
         P.n_slots = (int32_t)busy.size();
         C.roots.push_back(P);
     }
+    // auxiliary records after the programs; relocate the constant-divisor references
+    C.n_prog = (int32_t)C.instr.size();
+    if (C.n_prog + aux.size() / 2 > 65536)
+        return fail(err, MVF_ELIMIT, "program of %ld instructions exceeds 65536 records", (long)(C.n_prog + aux.size() / 2));
+    for (auto &ins : C.instr) {
+        const uint32_t op = ins.w0 & 31u;
+        if (op == I_DIVK || op == I_DIVKN) ins.w1 = (ins.w1 & 0xffff0000u) | ((ins.w1 & 0xffffu) + (uint32_t)C.n_prog);
+    }
+    for (size_t j = 0; j < aux.size(); j += 2) {
+        Instr rec;
+        std::memcpy(&rec, &aux[j], 16);
+        C.instr.push_back(rec);
+    }
     for (auto &P : C.roots) {
         C.max_slots = std::max(C.max_slots, P.n_slots);
         C.max_rec = std::max(C.max_rec, P.n_rec);
+    }
+    // one record per root: program begin, length, result slot, reverse-mode record count
+    C.root_base = (int32_t)C.instr.size();
+    for (auto &P : C.roots) {
+        const uint32_t w[4] = {(uint32_t)P.begin, (uint32_t)P.len, (uint32_t)P.result_slot, (uint32_t)P.n_rec};
+        Instr rec;
+        std::memcpy(&rec, w, 16);
+        C.instr.push_back(rec);
     }
 
     // value passes keep every slot in registers

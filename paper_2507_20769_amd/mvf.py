@@ -61,7 +61,7 @@ class BoundArgs(ctypes.Structure):
     _fields_ = [("box", ctypes.c_void_p), ("splits", ctypes.c_void_p), ("mode", ctypes.c_int32),
                 ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
                 ("per_sub", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p)]
 
 
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
@@ -188,9 +188,10 @@ class BoundCall:
     so repeated launches only enqueue kernels)."""
 
     def __init__(self, tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str = "fwd",
-                 per_sub: bool = False, flags: bool = False):
+                 per_sub: bool = False, flags: bool = False, tuning: "Tuning | None" = None):
         import torch
         self.tape = tape
+        self.tuning = tuning
         dev = box.device
         assert box.dtype == torch.float64 and box.is_cuda and tuple(box.shape) == (tape.n_vars, 2)
         self.box = box.contiguous()
@@ -212,7 +213,8 @@ class BoundCall:
                               self.reduced.data_ptr(), self.argmin.data_ptr(),
                               self.per_sub.data_ptr() if per_sub else None,
                               self.flags.data_ptr() if flags else None,
-                              self.workspace.data_ptr(), self.workspace.numel())
+                              self.workspace.data_ptr(), self.workspace.numel(),
+                              ctypes.addressof(tuning) if tuning is not None else None)
 
     def launch(self, stream=None):
         rc = lib().mvf_bound(self.tape.handle, ctypes.byref(self.args), _stream_ptr(stream))
@@ -278,7 +280,8 @@ class BatchCall:
         self.status = torch.empty(N, dtype=torch.int32, device=dev)
         self.args = BatchArgs(N, N, max(cap, 1), self.boxes.data_ptr(), self.splits.data_ptr(), MVF_MODE[mode],
                               MVF_GRAD[grad], self.reduced.data_ptr(), self.argmin.data_ptr(), self.status.data_ptr(),
-                              self.workspace.data_ptr(), self.workspace.numel())
+                              self.workspace.data_ptr(), self.workspace.numel(),
+                              ctypes.addressof(tuning) if tuning is not None else None)
 
     def launch(self, stream=None):
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
