@@ -207,6 +207,46 @@ int mvf_batch_graph_destroy(mvf_batch_graph *g);
 int mvf_autotune(const mvf_tape *tape, int32_t n_nodes, const double *boxes, const int32_t *splits,
                  int64_t n_subdomains, int32_t mode, mvf_tuning *out, hipStream_t stream);
 
+/* ---- points and boxes (differentiation) -------------------------------
+ * One lane per point or box, evaluated with the same register programs and
+ * outward-rounded operations as the bounding kernels.  A point x is the
+ * degenerate box [x, x] (Sec. 2.2, interval arithmetic: a point interval
+ * encloses the real value f(x)).  Every output is an interval [lo, hi]
+ * stored as two doubles; where an operation leaves its domain (a divisor
+ * containing 0, sqrt of a negative, log of a non-positive value) the row is
+ * [-inf, +inf] and flags[b] (nullable) is 1.  Arrays are device memory owned
+ * by the caller; the workspace is caller-provided device scratch of
+ * mvf_points_workspace() bytes (0 for MVF_POINTS_EVAL and
+ * MVF_BOXES_GRAD_FWD; pass NULL then).  Asynchronous on the stream.
+ */
+enum { MVF_POINTS_EVAL = 0, MVF_POINTS_VJP = 1, MVF_BOXES_GRAD_FWD = 2, MVF_BOXES_GRAD_REV = 3 };
+int mvf_points_workspace(const mvf_tape *tape, int32_t op, int64_t n_items, size_t *bytes);
+
+/* f [B][m][2]: enclosure of every root at each point x [B][n] (row major). */
+int mvf_eval_points(const mvf_tape *tape, int64_t B, const double *x, double *f, uint32_t *flags,
+                    void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * gx [B][n][2]: enclosure of sum_r gout[b][r] * grad f_r(x_b), from one
+ * reverse sweep over the union of the root cones seeded with [gout, gout]
+ * at the roots (the adjoint of a node collects every root's contribution
+ * before it is propagated).  The paper computes gradients in tangent mode
+ * (Sec. 3.2, operator overloading); this reverse sweep is the adjoint
+ * counterpart of the same local derivative rules.
+ */
+int mvf_vjp_points(const mvf_tape *tape, int64_t B, const double *x, const double *gout, double *gx,
+                   uint32_t *flags, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * G [B][n][2]: interval gradient enclosure of root `root` on each box
+ * boxes [B][n][2] (Sec. 2.2, the gradient enclosure in the mean value form),
+ * in tangent mode (MVF_GRAD_FWD) or by the reverse-mode adjoint
+ * (MVF_GRAD_REV).  flags[b] reports a domain violation anywhere in the
+ * union of the root cones.
+ */
+int mvf_gradient_boxes(const mvf_tape *tape, int64_t B, const double *boxes, int32_t root, int32_t grad,
+                       double *G, uint32_t *flags, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- diagnostics ----------------------------------------------------- */
 const char *mvf_strerror(int code);
 const char *mvf_last_error(void);

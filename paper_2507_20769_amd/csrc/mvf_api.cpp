@@ -77,7 +77,7 @@ constexpr int BATCH_TAB_CAP = 256;
 // whose spill slots still let two workgroups share a compute unit (one, for a
 // single component, if that is the only way).
 void choose_chunk(Compiled &C) {
-    const int m = (int)C.roots.size(), n = C.n_vars, ni = (int)C.instr.size();
+    const int m = (int)C.roots.size(), n = C.n_vars, ni = C.n_bound;
     const int avail = usable_dwords(m);
     C.chunk = 0;
     C.spill = 0;
@@ -115,7 +115,7 @@ TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {
     TapeArgs T;
     std::memset(&T, 0, sizeof T);
     T.prog = t->d_prog;
-    T.n_instr = (int32_t)t->C.instr.size();
+    T.n_instr = t->C.n_bound;
     T.n_roots = (int32_t)t->C.roots.size();
     T.n = t->C.n_vars;
     T.mode = mode;
@@ -163,7 +163,7 @@ struct SingleLayout {
 SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total) {
     const size_t m = t->C.roots.size();
     SingleLayout L;
-    L.g_lds = grad_in_lds((int)t->C.instr.size(), tab_total, t->C.n_vars, (int)m);
+    L.g_lds = grad_in_lds(t->C.n_bound, tab_total, t->C.n_vars, (int)m);
     L.partial = 0;
     L.lo0 = align_up(L.partial + (size_t)grid * m * 2 * 8);
     L.k = align_up(L.lo0 + (size_t)grid * 8);
@@ -189,10 +189,72 @@ BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int 
     L.lo0 = align_up(L.partial + items * m * 2 * 8);
     L.k = align_up(L.lo0 + items * 8);
     L.rec = align_up(L.k + items * 8);
-    L.g_lds = grad_in_lds((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, (int)m);
+    L.g_lds = grad_in_lds(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, (int)m);
     L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
+}
+
+// Point and box entry points: grid, LDS placement of the gradient accumulators,
+// workspace (reverse-mode records, then accumulators when not in LDS).
+struct PointsLayout {
+    int grid = 1, chunk = 0, spill = 0;
+    bool g_lds = true;
+    size_t rec = 0, gacc = 0, total = 0, lds = 0;
+};
+
+int points_layout(const mvf_tape *t, int op, int64_t B, PointsLayout *L) {
+    const Compiled &C = t->C;
+    const bool rev = op == PT_VJP || op == PT_GRAD_REV;
+    if (!C.union_ok) return set_err(MVF_ELIMIT, "the union of the root cones needs more slots than the slot file holds");
+    if (op == PT_GRAD_FWD) {
+        if (C.chunk == 0) return set_err(MVF_ELIMIT, "a root's live set is too large for tangent passes; use MVF_GRAD_REV");
+        L->chunk = C.chunk;
+        L->spill = C.spill;
+    }
+    const int64_t need = std::max<int64_t>(1, (B + BLK - 1) / BLK);
+    L->grid = (int)std::min<int64_t>(need, rev ? 2 * t->n_cu : MAX_GRID);
+    const size_t spill = spill_bytes(L->spill, L->chunk);
+    L->g_lds = points_lds_bytes((int)C.instr.size(), C.n_vars, true, spill) <= LDS_BUDGET / 2;
+    L->lds = points_lds_bytes((int)C.instr.size(), C.n_vars, rev && L->g_lds, spill);
+    if (L->lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "programs exceed the LDS budget of the point kernels");
+    const int recs = op == PT_VJP ? C.uprog.n_rec : C.max_rec;
+    L->rec = 0;
+    L->gacc = align_up(rev ? (size_t)recs * L->grid * BLK * 16 : 0);
+    L->total = L->gacc + (rev && !L->g_lds ? (size_t)C.n_vars * L->grid * BLK * 16 : 0);
+    return MVF_OK;
+}
+
+int launch_points_op(const mvf_tape *t, int op, int64_t B, const double *x, const double *gout, int32_t root,
+                     double *out, uint32_t *flags, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (B < 0 || B > (INT64_C(1) << 40)) return set_err(MVF_EINVAL, "point count outside [0, 2^40]");
+    if (B == 0) return MVF_OK;
+    PointsLayout L;
+    int rc = points_layout(t, op, B, &L);
+    if (rc != MVF_OK) return rc;
+    if (L.total > 0 && (!ws || ws_bytes < L.total)) return set_err(MVF_EINVAL, "workspace too small");
+    PointsArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.prog = t->d_prog;
+    A.n_records = (int32_t)t->C.instr.size();
+    A.n_roots = (int32_t)t->C.roots.size();
+    A.n = t->C.n_vars;
+    A.root_base = t->C.root_base;
+    A.union_base = t->C.union_base;
+    A.nreg = L.chunk > 0 ? usable_dwords(A.n_roots) / (4 + 4 * L.chunk) : usable_dwords(A.n_roots) / 4;
+    A.spill_slots = L.spill;
+    A.root = root;
+    A.B = B;
+    A.x = x;
+    A.gout = gout;
+    A.out = out;
+    A.flags = flags;
+    uint8_t *w = static_cast<uint8_t *>(ws);
+    A.rec = L.total > 0 ? reinterpret_cast<double2 *>(w + L.rec) : nullptr;
+    A.gacc = (op == PT_VJP || op == PT_GRAD_REV) && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
+    hipError_t e = launch_points(A, op, L.chunk, L.grid, L.lds, stream);
+    if (e != hipSuccess) return hip_err(e, "launch_points");
+    return MVF_OK;
 }
 
 int check_splits(const mvf_tape *t, const int32_t *splits, int64_t *S, int *tab_total) {
@@ -243,6 +305,37 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
 
 extern "C" {
 
+int mvf_points_workspace(const mvf_tape *t, int32_t op, int64_t B, size_t *bytes) {
+    if (!t || !bytes) return set_err(MVF_EINVAL, "null argument");
+    if (op < MVF_POINTS_EVAL || op > MVF_BOXES_GRAD_REV) return set_err(MVF_EINVAL, "bad op");
+    PointsLayout L;
+    const int rc = points_layout(t, op, std::max<int64_t>(B, 1), &L);
+    if (rc != MVF_OK) return rc;
+    *bytes = L.total;
+    return MVF_OK;
+}
+
+int mvf_eval_points(const mvf_tape *t, int64_t B, const double *x, double *f, uint32_t *flags, void *workspace,
+                    size_t workspace_bytes, hipStream_t stream) {
+    if (!t || (B > 0 && (!x || !f))) return set_err(MVF_EINVAL, "null argument");
+    return launch_points_op(t, PT_EVAL, B, x, nullptr, 0, f, flags, workspace, workspace_bytes, stream);
+}
+
+int mvf_vjp_points(const mvf_tape *t, int64_t B, const double *x, const double *gout, double *gx, uint32_t *flags,
+                   void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!t || (B > 0 && (!x || !gout || !gx))) return set_err(MVF_EINVAL, "null argument");
+    return launch_points_op(t, PT_VJP, B, x, gout, 0, gx, flags, workspace, workspace_bytes, stream);
+}
+
+int mvf_gradient_boxes(const mvf_tape *t, int64_t B, const double *boxes, int32_t root, int32_t grad, double *G,
+                       uint32_t *flags, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!t || (B > 0 && (!boxes || !G))) return set_err(MVF_EINVAL, "null argument");
+    if (root < 0 || root >= (int32_t)t->C.roots.size()) return set_err(MVF_EINVAL, "root out of range");
+    if (grad != MVF_GRAD_FWD && grad != MVF_GRAD_REV) return set_err(MVF_EINVAL, "grad must be MVF_GRAD_FWD or MVF_GRAD_REV");
+    return launch_points_op(t, grad == MVF_GRAD_FWD ? PT_GRAD_FWD : PT_GRAD_REV, B, boxes, nullptr, root, G, flags,
+                            workspace, workspace_bytes, stream);
+}
+
 const char *mvf_strerror(int code) {
     switch (code) {
     case MVF_OK: return "ok";
@@ -282,7 +375,7 @@ int mvf_tape_create(const mvf_node *nodes, int32_t n_nodes, const double *consts
     rc = check_device(&t->n_cu);
     if (rc != MVF_OK) { delete t; return rc; }
     hipGetDevice(&t->device);
-    if (lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, n_roots, false) > LDS_BUDGET - 1024) {
+    if (lds_bytes(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, n_roots, false) > LDS_BUDGET - 1024) {
         delete t;
         return set_err(MVF_ELIMIT, "programs and tables exceed the 160 KiB LDS budget");
     }
@@ -339,7 +432,7 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     const SingleLayout L = single_layout(t, grid, rev, tt);
     if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
-    const size_t lds = lds_bytes((int)t->C.instr.size(), tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
+    const size_t lds = lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
 
     const TapeArgs T = tape_args(t, a->mode, chunk);
@@ -395,7 +488,7 @@ int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning
     if (rc != MVF_OK) return rc;
     if (a->n_nodes == 0) return MVF_OK;
     const int m = (int)t->C.roots.size();
-    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr,
+    const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr,
                                  spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
     hipError_t e = launch_batch(tape_args(t, a->mode, chunk), A, chunk, rev, grid, lds, a->n_nodes, stream);
@@ -456,7 +549,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
                          g->d_argmin, g->d_status, g->d_ws, g->ws_bytes, grid, rev, &A);
     if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
-    const size_t lds = lds_bytes((int)t->C.instr.size(), BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
+    const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
                                  spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) { mvf_batch_graph_destroy(g); return set_err(MVF_ELIMIT, "LDS budget"); }
     (void)stream;

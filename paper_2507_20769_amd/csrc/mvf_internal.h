@@ -85,7 +85,13 @@ struct RootProg {
 struct Compiled {
     int32_t n_vars = 0;
     int32_t n_prog = 0;              // instructions of the root programs (auxiliary records follow)
-    int32_t root_base = 0;           // index of the per-root records {begin, len, result slot, records}
+    int32_t root_base = 0;           // index of the per-root records {begin, len, result slot, records},
+                                     // followed by the union program's record and its root slots
+    RootProg uprog;                  // union of all root cones, every root live to its end
+    std::vector<int32_t> union_slots;  // slot of each root at the end of the union program
+    bool union_ok = false;           // the union program's live set fits the slot file
+    int32_t n_bound = 0;             // records the bounding kernels stage (programs, aux, root records)
+    int32_t union_base = 0;          // index of the union record
     std::vector<RootProg> roots;
     std::vector<Instr> instr;
     int32_t max_slots = 0;

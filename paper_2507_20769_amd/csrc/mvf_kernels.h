@@ -68,6 +68,27 @@ struct BatchKArgs {
     BatchArgs A;
 };
 
+// Point and box entry points (one lane per point or box).
+enum : int { PT_EVAL = 0, PT_VJP = 1, PT_GRAD_FWD = 2, PT_GRAD_REV = 3 };
+struct PointsArgs {
+    const Instr *prog;
+    int32_t n_records;       // every program record (all are staged)
+    int32_t n_roots, n, root_base, union_base;
+    int32_t nreg, spill_slots;   // tangent passes of a forward gradient
+    int32_t root;            // the root whose gradient is taken
+    int64_t B;
+    const double *x;         // points [B][n], or boxes [B][n][2] for gradients
+    const double *gout;      // [B][m] cotangents (vector-Jacobian product)
+    double *out;             // values [B][m][2], or gradients [B][n][2]
+    uint32_t *flags;         // [B] or null: domain violation
+    double2 *rec;            // reverse-mode records [records][grid * BLK]
+    double2 *gacc;           // gradient accumulators [n][grid * BLK] when not in LDS
+};
+struct PointsKArgs {
+    PointsArgs P;
+};
+hipError_t launch_points(const PointsArgs &A, int op, int chunk, int grid, size_t lds, hipStream_t stream);
+
 #ifdef __HIPCC__
 template <typename BA>     // BatchArgs in any address space
 __device__ __forceinline__ int node_count(const BA &A) { return A.n_nodes_dev ? *A.n_nodes_dev : A.n_nodes_val; }
@@ -92,6 +113,10 @@ inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds, s
     b = (b + 15) & ~(size_t)15;
     b += (size_t)n * BLK * sizeof(uint16_t);
     return b;
+}
+
+inline size_t points_lds_bytes(int n_records, int n, bool g_in_lds, size_t spill) {
+    return (size_t)n_records * 16 + (g_in_lds ? (size_t)n * BLK * 16 : 0) + spill;
 }
 
 // Reverse mode keeps the gradient accumulators in LDS when a workgroup still

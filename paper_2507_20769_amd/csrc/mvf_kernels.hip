@@ -77,12 +77,30 @@ struct Ctx {
     double2 *rec;            // global reverse-mode tape of this lane ([record][lane])
     int64_t rec_stride;      // lanes sharing the tape (record stride, in records)
     double2 *spill;          // LDS spill slots of this lane ([slot][component][lane])
+    const double *vsrc;      // this lane's point [n] or box [n][2] (point and box entry points)
     uint32_t nreg;           // slot ids >= nreg are spilled (tangent passes)
     int tid, blk;
 };
 
 __device__ __forceinline__ double4 var_rec(const Ctx &X, uint32_t i) {
     return X.tab[X.vrec[i * X.blk + X.tid]];
+}
+
+// Where variable values come from: the breakpoint table of the lane's
+// subdomain, the lane's point [x_i, x_i], or the lane's box.
+enum : int { VS_TABLE = 0, VS_POINT = 1, VS_BOX = 2 };
+
+template <int VS, bool POINT>
+__device__ __forceinline__ Iv var_val(const Ctx &X, uint32_t i) {
+    if constexpr (VS == VS_TABLE) {
+        const double4 r = var_rec(X, i);
+        return POINT ? Iv{r.z, r.w} : Iv{r.x, r.y};
+    } else if constexpr (VS == VS_POINT) {
+        const double x = X.vsrc[i];
+        return Iv{x, -x};
+    } else {
+        return Iv{X.vsrc[2 * i], -X.vsrc[2 * i + 1]};
+    }
 }
 
 __device__ __forceinline__ Iv aux_rec(const Ctx &X, uint32_t i) {
@@ -124,7 +142,7 @@ __device__ __forceinline__ void store_slot(const Ctx &X, uint32_t s, const Iv (&
 // tangent components in A[1..C] (dense); for a variable, hit = its component
 // index within [c0, c0 + C) (its tangent is one there and zero elsewhere), -1
 // otherwise; constants have zero tangents.
-template <int C, bool POINT>
+template <int C, bool POINT, int VS>
 __device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, double k, int c0,
                                       const Iv (&P)[1 + C], Iv (&A)[1 + C], bool &dense, int &hit) {
     dense = false;
@@ -137,8 +155,7 @@ __device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, d
 #pragma unroll
         for (int i = 0; i <= C; ++i) A[i] = P[i];
     } else if (kind == K_VAR) {
-        const double4 r = var_rec(X, a);
-        A[0] = POINT ? Iv{r.z, r.w} : Iv{r.x, r.y};
+        A[0] = var_val<VS, POINT>(X, a);
         const int h = (int)a - c0;
         hit = h >= 0 && h < C ? h : -1;
     } else {
@@ -178,7 +195,7 @@ __device__ __forceinline__ Dec decode(uint4 raw) {
 // and its result as whole slots (value and components); a result consumed
 // only by the next instruction stays in registers (P).  With TAPE, writes the
 // reverse-mode records.
-template <int C, bool POINT, bool TAPE>
+template <int C, bool POINT, bool TAPE, int VS = VS_TABLE>
 __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0, Iv (&gout)[C > 0 ? C : 1],
                           uint32_t &bad) {
     constexpr int N = 1 + C;
@@ -193,8 +210,8 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
         Iv A[N], B[N], Z[N];
         bool ad, bd = false;
         int ha, hb = -1;
-        fetch<C, POINT>(X, I.ak, I.a, I.k, c0, P, A, ad, ha);
-        if (I.op <= I_DIV) fetch<C, POINT>(X, I.bk, I.b, I.k, c0, P, B, bd, hb);
+        fetch<C, POINT, VS>(X, I.ak, I.a, I.k, c0, P, A, ad, ha);
+        if (I.op <= I_DIV) fetch<C, POINT, VS>(X, I.bk, I.b, I.k, c0, P, B, bd, hb);
         nxt = X.prog[pc + 1 < end ? pc + 1 : pc];      // prefetch the next instruction
         const Iv U = A[0], V = B[0];
 #pragma unroll
@@ -352,6 +369,7 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
             store_slot<C>(X, I.d, Z);
         }
     }
+    if (res_slot < 0) return kZero;                    // the union program: roots are read by the caller
     Iv R[N];
     load_slot<C>(X, (uint32_t)res_slot, R);
 #pragma unroll
@@ -388,9 +406,10 @@ __device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t
     }
 }
 
-// Reverse sweep over one root program; the adjoint of the root is [1, 1].
-__device__ void reverse_sweep(const Ctx &X, int begin, int len, int res_slot, int64_t n_rec) {
-    slot_wr((uint32_t)res_slot * 4, kOne);
+// Reverse sweep over one program.  The caller seeds the adjoints of the
+// program's results (for a root program: [1, 1] in its result slot).
+template <int VS = VS_TABLE>
+__device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
     Iv pa = kZero;
     int64_t rp = n_rec;
     uint4 nxt = X.prog[begin + len - 1];
@@ -411,12 +430,12 @@ __device__ void reverse_sweep(const Ctx &X, int begin, int len, int res_slot, in
             if (hv) V = ld_rec(X, --rp);
             if (hu) U = ld_rec(X, --rp);
             if (I.ak != K_CONST) {
-                if (I.bk == K_VAR) { const double4 r = var_rec(X, I.b); V = Iv{r.x, r.y}; }
+                if (I.bk == K_VAR) V = var_val<VS, false>(X, I.b);
                 else if (I.bk == K_CONST) V = Iv{I.k, -I.k};
                 contribute(X, I.ak, I.a, ia, false, imul(zb, V), pa);
             }
             if (I.bk != K_CONST) {
-                if (I.ak == K_VAR) { const double4 r = var_rec(X, I.a); U = Iv{r.x, r.y}; }
+                if (I.ak == K_VAR) U = var_val<VS, false>(X, I.a);
                 else if (I.ak == K_CONST) U = Iv{I.k, -I.k};
                 contribute(X, I.bk, I.b, ib, false, imul(zb, U), pa);
             }
@@ -563,7 +582,8 @@ __device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx 
             const Iv FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
             const Iv nie = run_program<0, false, true>(X, pb, pl, rs, 0, g0, bad);
             for (int i = 0; i < n; ++i) X.G[i * X.gstride] = make_double2(0.0, 0.0);
-            reverse_sweep(X, pb, pl, rs, (int64_t)__builtin_amdgcn_readfirstlane(ri.w));
+            slot_wr((uint32_t)rs * 4, kOne);
+            reverse_sweep(X, pb, pl, (int64_t)__builtin_amdgcn_readfirstlane(ri.w));
             Iv acc = FC;
             for (int i = 0; i < n; ++i) {
                 const double4 rec = var_rec(X, (uint32_t)i);
@@ -1016,6 +1036,138 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs A, int m) {
 }
 
 // ---------------------------------------------------------------------------
+// points and boxes: values and vector-Jacobian products at points, interval
+// gradients on boxes (one lane per point or box, grid-stride)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t u4_at(uint4 q, int j) { return j == 0 ? q.x : j == 1 ? q.y : j == 2 ? q.z : q.w; }
+
+template <int OP, int C>
+__global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amdgpu_waves_per_eu(4, 4))) void points_kernel(
+    PointsKArgs /* read through kargs() */) {
+    using namespace dev;
+    extern __shared__ __align__(16) uint8_t smem[];
+    claim_slot_file();
+    const int tid = threadIdx.x;
+    uint4 *lprog = reinterpret_cast<uint4 *>(smem);
+    Ctx X;
+    int m, n;
+    {
+        const auto K = kargs<PointsKArgs>();
+        m = K->P.n_roots;
+        n = K->P.n;
+        const int nr = K->P.n_records;
+        const uint4 *src = reinterpret_cast<const uint4 *>(K->P.prog);
+        for (int i = tid; i < nr; i += BLK) lprog[i] = src[i];
+        uint8_t *p = smem + (size_t)nr * 16;
+        const bool g_lds = K->P.gacc == nullptr;
+        X.G = g_lds ? reinterpret_cast<double2 *>(p) + tid : K->P.gacc + (int64_t)blockIdx.x * BLK + tid;
+        X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
+        if (g_lds) p += (size_t)n * BLK * 16;
+        X.spill = reinterpret_cast<double2 *>(p) + tid;
+        X.rec = K->P.rec + (int64_t)blockIdx.x * BLK + tid;
+        X.nreg = (uint32_t)K->P.nreg;
+    }
+    __syncthreads();
+    X.prog = lprog;
+    X.tab = nullptr;
+    X.vrec = nullptr;
+    X.tid = tid;
+    X.blk = BLK;
+    X.rec_stride = (int64_t)gridDim.x * BLK;
+    constexpr int VS = OP >= PT_GRAD_FWD ? VS_BOX : VS_POINT;
+    for (int64_t base = (int64_t)blockIdx.x * BLK;; base += (int64_t)gridDim.x * BLK) {
+        int64_t B, k, kk;
+        int ub, ul, urec, root_rec;
+        {
+            const auto K = kargs<PointsKArgs>();
+            B = K->P.B;
+            if (base >= B) break;
+            k = base + tid;
+            kk = k < B ? k : B - 1;                  // lanes past the end repeat the last item; nothing is stored
+            X.vsrc = K->P.x + kk * n * (VS == VS_BOX ? 2 : 1);
+            const uint4 ur = X.prog[K->P.union_base];
+            ub = (int)__builtin_amdgcn_readfirstlane(ur.x);
+            ul = (int)__builtin_amdgcn_readfirstlane(ur.y);
+            urec = (int)__builtin_amdgcn_readfirstlane(ur.z);
+            root_rec = K->P.root_base + K->P.root;
+        }
+        const bool active = k < B;
+        const int ubase = kargs<PointsKArgs>()->P.union_base;
+        mode_round_down();
+        uint32_t bad = 0;
+        Iv g0[1];
+        if constexpr (OP == PT_EVAL) {
+            run_program<0, true, false, VS>(X, ub, ul, -1, 0, g0, bad);
+            double *f = kargs<PointsKArgs>()->P.out;
+            for (int r = 0; r < m; ++r) {
+                const uint4 q = X.prog[ubase + 1 + r / 4];
+                const uint32_t sl = __builtin_amdgcn_readfirstlane(u4_at(q, r & 3));
+                const Iv v = slot_rd(sl * 4);
+                if (active) {
+                    f[(kk * m + r) * 2] = bad ? -__builtin_inf() : v.lo;
+                    f[(kk * m + r) * 2 + 1] = bad ? __builtin_inf() : -v.nh;
+                }
+            }
+        } else if constexpr (OP == PT_VJP) {
+            run_program<0, true, true, VS>(X, ub, ul, -1, 0, g0, bad);
+            for (int i = 0; i < n; ++i) X.G[i * X.gstride] = make_double2(0.0, 0.0);
+            const double *gout = kargs<PointsKArgs>()->P.gout;
+            for (int r = 0; r < m; ++r) {                // seeds, roots in order; a repeated root accumulates
+                const uint4 q = X.prog[ubase + 1 + r / 4];
+                const uint32_t sl = __builtin_amdgcn_readfirstlane(u4_at(q, r & 3));
+                bool seen = false;
+                for (int r2 = 0; r2 < r; ++r2) {
+                    const uint4 q2 = X.prog[ubase + 1 + r2 / 4];
+                    seen |= __builtin_amdgcn_readfirstlane(u4_at(q2, r2 & 3)) == sl;
+                }
+                const double g = gout[kk * m + r];
+                const Iv seed = {g, -g};
+                slot_wr(sl * 4, seen ? iadd(slot_rd(sl * 4), seed) : seed);
+            }
+            reverse_sweep<VS>(X, ub, ul, urec);
+        } else {
+            run_program<0, false, false, VS>(X, ub, ul, -1, 0, g0, bad);   // domain of every live node
+            const uint4 ri = X.prog[root_rec];
+            const int pb = (int)__builtin_amdgcn_readfirstlane(ri.x), pl = (int)__builtin_amdgcn_readfirstlane(ri.y);
+            const int rs = (int)__builtin_amdgcn_readfirstlane(ri.z);
+            uint32_t bad2 = 0;
+            double *Gout = kargs<PointsKArgs>()->P.out;
+            if constexpr (OP == PT_GRAD_REV) {
+                run_program<0, false, true, VS>(X, pb, pl, rs, 0, g0, bad2);
+                for (int i = 0; i < n; ++i) X.G[i * X.gstride] = make_double2(0.0, 0.0);
+                slot_wr((uint32_t)rs * 4, kOne);
+                reverse_sweep<VS>(X, pb, pl, (int64_t)__builtin_amdgcn_readfirstlane(ri.w));
+            } else {
+                for (int c0 = 0; c0 < n; c0 += C) {
+                    Iv G[C];
+                    run_program<C, false, false, VS>(X, pb, pl, rs, c0, G, bad2);
+#pragma unroll
+                    for (int t = 0; t < C; ++t) {
+                        if (active && c0 + t < n) {
+                            Gout[(kk * n + c0 + t) * 2] = bad ? -__builtin_inf() : G[t].lo;
+                            Gout[(kk * n + c0 + t) * 2 + 1] = bad ? __builtin_inf() : -G[t].nh;
+                        }
+                    }
+                }
+            }
+        }
+        mode_round_nearest();
+        if constexpr (OP == PT_VJP || OP == PT_GRAD_REV) {
+            double *o = kargs<PointsKArgs>()->P.out;
+            for (int i = 0; i < n; ++i) {
+                const double2 g = X.G[i * X.gstride];
+                if (active) {
+                    o[(kk * n + i) * 2] = bad ? -__builtin_inf() : g.x;
+                    o[(kk * n + i) * 2 + 1] = bad ? __builtin_inf() : -g.y;
+                }
+            }
+        }
+        uint32_t *flags = kargs<PointsKArgs>()->P.flags;
+        if (active && flags) flags[kk] = bad;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launch helpers (host)
 // ---------------------------------------------------------------------------
 
@@ -1083,6 +1235,29 @@ hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool r
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(batch_finish_kernel, dim3(max_nodes), dim3(256), 0, stream, A, T.n_roots);
     return hipGetLastError();
+}
+
+hipError_t launch_points(const PointsArgs &A, int op, int chunk, int grid, size_t lds, hipStream_t stream) {
+    static_assert(MAX_CHUNK == 4, "one kernel instance per chunk size");
+    auto go = [&](auto kernel) -> hipError_t {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS_BUDGET - 1024));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kernel, dim3(grid), dim3(BLK), lds, stream, PointsKArgs{A});
+        return hipGetLastError();
+    };
+    switch (op) {
+    case PT_EVAL: return go(points_kernel<PT_EVAL, 0>);
+    case PT_VJP: return go(points_kernel<PT_VJP, 0>);
+    case PT_GRAD_REV: return go(points_kernel<PT_GRAD_REV, 0>);
+    default:
+        switch (chunk) {
+        case 1: return go(points_kernel<PT_GRAD_FWD, 1>);
+        case 2: return go(points_kernel<PT_GRAD_FWD, 2>);
+        case 3: return go(points_kernel<PT_GRAD_FWD, 3>);
+        default: return go(points_kernel<PT_GRAD_FWD, 4>);
+        }
+    }
 }
 
 }  // namespace mvf

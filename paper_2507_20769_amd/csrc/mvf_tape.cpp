@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 
 #include "mvf_internal.h"
@@ -97,18 +98,29 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
     std::vector<double> aux;            // reciprocal enclosures of constant divisors, (lo, -hi) pairs
     int64_t sum_val = 0, sum_tan = 0, sum_adj = 0, n_ops = 0;
 
-    for (int r = 0; r < n_roots; ++r) {
+    // Programs 0 .. m-1 compute one root each (bounding, gradients of one root);
+    // program m is the union of all root cones with every root kept live to
+    // its end (point values of all roots and their vector-Jacobian product).
+    std::vector<uint8_t> is_root(n_nodes);
+    for (int pi = 0; pi <= n_roots; ++pi) {
+        const bool uni = pi == n_roots;
         RootProg P;
         P.begin = (int32_t)C.instr.size();
         std::fill(in_cone.begin(), in_cone.end(), 0);
-        in_cone[roots[r]] = 1;
-        for (int i = roots[r]; i >= 0; --i) {
+        std::fill(is_root.begin(), is_root.end(), 0);
+        int top = 0;
+        for (int r = uni ? 0 : pi; r < (uni ? n_roots : pi + 1); ++r) {
+            in_cone[roots[r]] = 1;
+            is_root[roots[r]] = 1;
+            top = std::max(top, (int)roots[r]);
+        }
+        for (int i = top; i >= 0; --i) {
             if (!in_cone[i]) continue;
             if (is_binary(nodes[i].op) || is_unary(nodes[i].op)) in_cone[nodes[i].a] = 1;
             if (is_binary(nodes[i].op)) in_cone[nodes[i].b] = 1;
         }
-        const mvf_node &rn = nodes[roots[r]];
-        if (is_leaf(rn.op)) {
+        if (!uni && is_leaf(nodes[roots[pi]].op)) {
+            const mvf_node &rn = nodes[roots[pi]];
             uint32_t ak = rn.op == MVF_VAR ? K_VAR : K_CONST;
             double k = rn.op == MVF_CONST ? consts[rn.a] : 0.0;
             C.instr.push_back(make_instr(I_LOAD, ak, rn.op == MVF_VAR ? (uint32_t)rn.a : 0, K_SLOT, 0, 0, k));
@@ -118,7 +130,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
         }
         // program order of the arithmetic nodes, their uses and last uses
         std::vector<int32_t> order;
-        for (int i = 0; i <= roots[r]; ++i)
+        for (int i = 0; i <= top; ++i)
             if (in_cone[i] && !is_leaf(nodes[i].op)) order.push_back(i);
         for (int i : order) { last_use[i] = -1; uses[i] = 0; in_regs[i] = 0; }
         for (size_t p = 0; p < order.size(); ++p) {
@@ -126,6 +138,8 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             if (!is_leaf(nodes[nd.a].op)) { last_use[nd.a] = (int32_t)p; ++uses[nd.a]; }
             if (is_binary(nd.op) && !is_leaf(nodes[nd.b].op)) { last_use[nd.b] = (int32_t)p; ++uses[nd.b]; }
         }
+        for (int i : order)
+            if (is_root[i]) last_use[i] = INT32_MAX;        // roots stay live to the end of the program
         auto refs = [&](int j, int i) {          // operand references of node j to node i
             const mvf_node &nd = nodes[j];
             return (nd.a == i ? 1 : 0) + (is_binary(nd.op) && nd.b == i ? 1 : 0);
@@ -173,7 +187,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
                 if (nd.b != nd.a) init |= 2u;
             }
             // the result stays in registers when the next node is its only consumer
-            const bool nowrite = i != roots[r] && p + 1 < order.size() && uses[i] == refs(order[p + 1], i) &&
+            const bool nowrite = !is_root[i] && p + 1 < order.size() && uses[i] == refs(order[p + 1], i) &&
                                  uses[i] > 0;
             int32_t d = 0;
             if (nowrite) in_regs[i] = 1;
@@ -218,24 +232,48 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             ins.w0 |= (init & 1u ? W0_INIT_A : 0u) | (init & 2u ? W0_INIT_B : 0u) | (nowrite ? W0_NOWRITE : 0u);
             C.instr.push_back(ins);
             P.n_rec += n_records(op, ak, bk);
-            int cv, ct, ca;
-            ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
-            sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
-            if (nd.op == MVF_SQR || nd.op == MVF_SQRT) sum_val += 2;   // 2U or 1/(2Z), once per op
+            if (!uni) {
+                int cv, ct, ca;
+                ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
+                sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
+                if (nd.op == MVF_SQR || nd.op == MVF_SQRT) sum_val += 2;   // 2U or 1/(2Z), once per op
+            }
+        }
+        if (!uni) {
+            P.len = (int32_t)C.instr.size() - P.begin;
+            P.result_slot = slot_of[roots[pi]];
+            P.n_slots = (int32_t)busy.size();
+            C.roots.push_back(P);
+            continue;
+        }
+        // union program: variable and constant roots are loaded at its end (in the
+        // reverse sweep their seeds reach the gradient before any other contribution)
+        for (int r = 0; r < n_roots; ++r) {
+            const mvf_node &rn = nodes[roots[r]];
+            if (!is_leaf(rn.op)) { C.union_slots.push_back(slot_of[roots[r]]); continue; }
+            const int32_t d = take();
+            C.instr.push_back(make_instr(I_LOAD, rn.op == MVF_VAR ? K_VAR : K_CONST, rn.op == MVF_VAR ? (uint32_t)rn.a : 0,
+                                         K_SLOT, 0, (uint32_t)d, rn.op == MVF_CONST ? consts[rn.a] : 0.0));
+            C.union_slots.push_back(d);
         }
         P.len = (int32_t)C.instr.size() - P.begin;
-        P.result_slot = slot_of[roots[r]];
+        P.result_slot = -1;
         P.n_slots = (int32_t)busy.size();
-        C.roots.push_back(P);
+        C.uprog = P;
     }
-    // auxiliary records after the programs; relocate the constant-divisor references
+    // Layout: [root programs][auxiliary records][root records] -- what the bounding
+    // kernels stage -- then [union program][union record][union root slots].
+    std::vector<Instr> uni(C.instr.begin() + C.uprog.begin, C.instr.end());
+    C.instr.resize(C.uprog.begin);
     C.n_prog = (int32_t)C.instr.size();
     if (C.n_prog + aux.size() / 2 > 65536)
         return fail(err, MVF_ELIMIT, "program of %ld instructions exceeds 65536 records", (long)(C.n_prog + aux.size() / 2));
-    for (auto &ins : C.instr) {
+    auto relocate = [&](Instr &ins) {
         const uint32_t op = ins.w0 & 31u;
         if (op == I_DIVK || op == I_DIVKN) ins.w1 = (ins.w1 & 0xffff0000u) | ((ins.w1 & 0xffffu) + (uint32_t)C.n_prog);
-    }
+    };
+    for (auto &ins : C.instr) relocate(ins);
+    for (auto &ins : uni) relocate(ins);
     for (size_t j = 0; j < aux.size(); j += 2) {
         Instr rec;
         std::memcpy(&rec, &aux[j], 16);
@@ -253,9 +291,30 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
         std::memcpy(&rec, w, 16);
         C.instr.push_back(rec);
     }
+    C.n_bound = (int32_t)C.instr.size();
+    C.uprog.begin = (int32_t)C.instr.size();
+    C.instr.insert(C.instr.end(), uni.begin(), uni.end());
+    // the union record {begin, length, records, roots}, then the root slots, four per record
+    C.union_base = (int32_t)C.instr.size();
+    {
+        const uint32_t w[4] = {(uint32_t)C.uprog.begin, (uint32_t)C.uprog.len, (uint32_t)C.uprog.n_rec,
+                               (uint32_t)n_roots};
+        Instr rec;
+        std::memcpy(&rec, w, 16);
+        C.instr.push_back(rec);
+        for (int r = 0; r < n_roots; r += 4) {
+            uint32_t q[4] = {0, 0, 0, 0};
+            for (int j = 0; j < 4 && r + j < n_roots; ++j) q[j] = (uint32_t)C.union_slots[r + j];
+            std::memcpy(&rec, q, 16);
+            C.instr.push_back(rec);
+        }
+    }
+    if (C.instr.size() > 65536)
+        return fail(err, MVF_ELIMIT, "program of %ld records exceeds 65536", (long)C.instr.size());
 
     // value passes keep every slot in registers
     const int avail = usable_dwords(n_roots);
+    C.union_ok = C.uprog.n_slots * 4 <= avail;
     if (C.max_slots * 4 > avail)
         return fail(err, MVF_ELIMIT, "a root needs %ld live slots; the slot file holds %ld values", C.max_slots, avail / 4);
 

@@ -67,7 +67,8 @@ class BoundArgs(ctypes.Structure):
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
            "mvf_bound_workspace", "mvf_bound", "mvf_adaptive_splits", "mvf_batch_workspace", "mvf_bound_batch",
            "mvf_batch_graph_create", "mvf_batch_graph_staging", "mvf_batch_graph_launch", "mvf_batch_graph_result",
-           "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error"]
+           "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
+           "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes"]
 
 
 def lib():
@@ -119,6 +120,14 @@ def lib():
             L.mvf_batch_graph_destroy.argtypes = [P]
             L.mvf_autotune.restype = ctypes.c_int
             L.mvf_autotune.argtypes = [P, i32, P, P, i64, i32, ctypes.POINTER(Tuning), P]
+            L.mvf_points_workspace.restype = ctypes.c_int
+            L.mvf_points_workspace.argtypes = [P, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
+            L.mvf_eval_points.restype = ctypes.c_int
+            L.mvf_eval_points.argtypes = [P, i64, P, P, P, P, ctypes.c_size_t, P]
+            L.mvf_vjp_points.restype = ctypes.c_int
+            L.mvf_vjp_points.argtypes = [P, i64, P, P, P, P, P, ctypes.c_size_t, P]
+            L.mvf_gradient_boxes.restype = ctypes.c_int
+            L.mvf_gradient_boxes.argtypes = [P, i64, P, i32, i32, P, P, P, ctypes.c_size_t, P]
             _lib = L
     return _lib
 
@@ -364,3 +373,124 @@ def autotune(tape: Tape, boxes, splits, mode: str = "both", stream=None) -> Tuni
     if rc != 0:
         raise MVFError(rc, "mvf_autotune")
     return out
+
+
+# ---------------------------------------------------------------------------
+# points and boxes
+# ---------------------------------------------------------------------------
+_PT = {"eval": 0, "vjp": 1, "grad_fwd": 2, "grad_rev": 3}
+
+
+def _points_ws(tape: Tape, op: str, B: int, device):
+    import torch
+    nb = ctypes.c_size_t()
+    rc = lib().mvf_points_workspace(tape.handle, _PT[op], int(B), ctypes.byref(nb))
+    if rc != 0:
+        raise MVFError(rc, "mvf_points_workspace")
+    return torch.empty(max(int(nb.value), 8), dtype=torch.uint8, device=device), int(nb.value)
+
+
+def _check_points(tape: Tape, x, width: int):
+    import torch
+    assert x.dtype == torch.float64 and x.is_cuda, "device float64 tensor expected"
+    assert x.dim() == (2 if width == 1 else 3) and x.shape[1] == tape.n_vars
+    return x.contiguous()
+
+
+def eval_points(tape: Tape, x, flags: bool = False, stream=None):
+    """Enclosures [B, m, 2] of every root at the points x [B, n] (device float64)."""
+    import torch
+    x = _check_points(tape, x, 1)
+    B = x.shape[0]
+    f = torch.empty((B, tape.n_roots, 2), dtype=torch.float64, device=x.device)
+    fl = torch.empty(max(B, 1), dtype=torch.int32, device=x.device) if flags else None
+    ws, nb = _points_ws(tape, "eval", B, x.device)
+    rc = lib().mvf_eval_points(tape.handle, B, x.data_ptr(), f.data_ptr(), fl.data_ptr() if flags else None,
+                               ws.data_ptr() if nb else None, nb, _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_eval_points")
+    return (f, fl[:B]) if flags else f
+
+
+def vjp_points(tape: Tape, x, gout, flags: bool = False, stream=None):
+    """Enclosures [B, n, 2] of sum_r gout[:, r] * grad f_r at the points x [B, n]."""
+    import torch
+    x = _check_points(tape, x, 1)
+    B = x.shape[0]
+    assert gout.dtype == torch.float64 and tuple(gout.shape) == (B, tape.n_roots)
+    gout = gout.contiguous()
+    gx = torch.empty((B, tape.n_vars, 2), dtype=torch.float64, device=x.device)
+    fl = torch.empty(max(B, 1), dtype=torch.int32, device=x.device) if flags else None
+    ws, nb = _points_ws(tape, "vjp", B, x.device)
+    rc = lib().mvf_vjp_points(tape.handle, B, x.data_ptr(), gout.data_ptr(), gx.data_ptr(),
+                              fl.data_ptr() if flags else None, ws.data_ptr() if nb else None, nb,
+                              _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_vjp_points")
+    return (gx, fl[:B]) if flags else gx
+
+
+def gradient_boxes(tape: Tape, boxes, root: int = 0, grad: str = "rev", flags: bool = False, stream=None):
+    """Interval gradient [B, n, 2] of one root on boxes [B, n, 2], tangent or adjoint mode."""
+    import torch
+    boxes = _check_points(tape, boxes, 2)
+    B = boxes.shape[0]
+    G = torch.empty((B, tape.n_vars, 2), dtype=torch.float64, device=boxes.device)
+    fl = torch.empty(max(B, 1), dtype=torch.int32, device=boxes.device) if flags else None
+    op = "grad_fwd" if grad == "fwd" else "grad_rev"
+    ws, nb = _points_ws(tape, op, B, boxes.device)
+    rc = lib().mvf_gradient_boxes(tape.handle, B, boxes.data_ptr(), int(root), MVF_GRAD[grad], G.data_ptr(),
+                                  fl.data_ptr() if flags else None, ws.data_ptr() if nb else None, nb,
+                                  _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_gradient_boxes")
+    return (G, fl[:B]) if flags else G
+
+
+def _midpoint(iv):
+    """Midpoint of intervals stored as [..., 2] (lo, hi)."""
+    return 0.5 * iv[..., 0] + 0.5 * iv[..., 1]
+
+
+def _make_point_function():
+    import torch
+
+    class MVFPoint(torch.autograd.Function):
+        """f(x) for a batch of points, differentiable through the library.
+
+        forward:  x [B, n] (device float64) -> midpoints of the root enclosures [B, m]
+        backward: grad [B, m] -> midpoints of the vector-Jacobian enclosures [B, n],
+                  one reverse sweep per point (mvf_vjp_points).
+        Both enclosures are a few ulps wide at points, so the midpoints carry
+        the floating-point values of f and of its gradient.
+        """
+
+        @staticmethod
+        def forward(ctx, x, tape):
+            ctx.tape = tape
+            ctx.save_for_backward(x)
+            return _midpoint(eval_points(tape, x))
+
+        @staticmethod
+        def backward(ctx, grad):
+            (x,) = ctx.saved_tensors
+            gx = vjp_points(ctx.tape, x.detach(), grad.to(torch.float64).contiguous())
+            return _midpoint(gx), None
+
+    return MVFPoint
+
+
+_MVFPoint = None
+
+
+def MVFPoint():
+    """The torch.autograd.Function class (built on first use so importing this module needs no torch)."""
+    global _MVFPoint
+    if _MVFPoint is None:
+        _MVFPoint = _make_point_function()
+    return _MVFPoint
+
+
+def point_function(tape: Tape, x):
+    """Differentiable f(x): MVFPoint().apply(x, tape)."""
+    return MVFPoint().apply(x, tape)

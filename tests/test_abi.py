@@ -96,3 +96,12 @@ def test_bound_rejects_bad_arguments_without_device():
     assert L.mvf_tape_destroy(None) == 0
     assert L.mvf_bound_batch(None, None, None, None) == -1
     assert L.mvf_batch_graph_launch(None, 0, None) == -1
+
+
+def test_points_entry_points_reject_bad_arguments_without_device():
+    L = mvf.lib()
+    nb = ctypes.c_size_t()
+    assert L.mvf_points_workspace(None, 0, 1, ctypes.byref(nb)) == -1
+    assert L.mvf_eval_points(None, 1, None, None, None, None, 0, None) == -1
+    assert L.mvf_vjp_points(None, 1, None, None, None, None, None, 0, None) == -1
+    assert L.mvf_gradient_boxes(None, 1, None, 0, 0, None, None, None, 0, None) == -1
