@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="headline only (used under the profiler)")
+    ap.add_argument("--bnb-nodes", type=int, default=1000, help="B&B node limit of the e2e comparison (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy, the reference for HBM counters")
     return ap.parse_args()
@@ -158,6 +159,29 @@ def forms(seed: int) -> dict:
     return out
 
 
+def bnb_forms(seed: int, max_nodes: int) -> dict:
+    """NEXT-1: host B&B on the e2e problem (10 variables, an objective and five
+    inequality constraints, [-3, 3]^10, 2^16 subdomains per node), plain
+    forward mode one node per launch vs reverse mode 16 nodes per graph replay."""
+    from paper_2507_20769_amd import inputs as I
+    from paper_2507_20769_amd import mvf
+    tape = I.e2e_tape(seed)
+    h = mvf.Tape(tape)
+    h.set_root_kinds([0] + [1] * (tape.n_roots - 1))
+    box = np.array([[-3.0, 3.0]] * tape.n_vars)
+    out = {"problem": "e2e", "n_vars": tape.n_vars, "roots": tape.n_roots, "subdomains_per_node": 1 << 16,
+           "max_nodes": max_nodes, "abs_gap": 1e-4}
+    for name, k, grad in (("plain_forward_per_node", 1, "fwd"), ("adjoint_batched_graph", 16, "rev")):
+        r = mvf.bnb_solve(h, box, max_nodes=max_nodes, gap=1e-4, budget=1 << 16, nodes_per_launch=k, grad=grad)
+        out[name] = {"nodes_per_s": r["nodes"] / r["seconds"], "subdomain_bounds_per_s": r["subdomains"] / r["seconds"],
+                     "seconds": r["seconds"], "nodes": r["nodes"], "lower": r["lower"], "upper": r["upper"],
+                     "gap": r["upper"] - r["lower"], "status": r["status"], "launches": r["launches"]}
+    out["speedup_adjoint_batched_vs_plain"] = (out["plain_forward_per_node"]["seconds"] /
+                                               out["adjoint_batched_graph"]["seconds"])
+    h.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -216,6 +240,8 @@ def main():
     }
     if not args.no_forms:
         out["forms"] = forms(args.seed)
+        if args.bnb_nodes > 0:
+            out["forms"]["bnb"] = bnb_forms(args.seed, args.bnb_nodes)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -98,6 +98,17 @@ int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
                    int32_t n_vars, const int32_t *roots, int32_t n_roots, mvf_tape_stats *stats);
 
 int mvf_tape_stats_get(const mvf_tape *tape, mvf_tape_stats *stats);
+
+/*
+ * Root kinds of the NLP min f s.t. g_i <= 0, h_j = 0 (Sec. 3.1): root 0 is the
+ * objective; every other root is unconstrained (FREE), an inequality g <= 0
+ * or an equality h = 0.  kinds [m] host, NULL resets every root to FREE.
+ * The kinds feed the two bounds a branch-and-bound needs besides the hulls
+ * (the `extra` outputs below); they are read when a call is made (a batch
+ * graph keeps the kinds it was created with).
+ */
+enum { MVF_ROOT_FREE = 0, MVF_ROOT_INEQ = 1, MVF_ROOT_EQ = 2 };
+int mvf_tape_set_root_kinds(mvf_tape *tape, const int32_t *kinds);
 int mvf_tape_destroy(mvf_tape *tape);
 
 /* ---- bounding one box ----------------------------------------------- */
@@ -115,6 +126,13 @@ typedef struct {
     size_t workspace_bytes;
     const struct mvf_tuning *tuning;   /* NULL, or a gradient mode and tangent chunk to use
                                           (grid_blocks is ignored here) */
+    double *extra;            /* device [2] or NULL: (0) the objective's lower bound over the
+                                 subdomains that no constraint proves infeasible (an inequality
+                                 with lower bound > 0, an equality bound without 0), +inf when
+                                 every subdomain is infeasible; (1) the least upper bound hi(f(c_k))
+                                 over centres whose inequality enclosures are all <= 0 (no
+                                 equality roots, MVF modes only), else +inf (Sec. 3.1, the
+                                 feasibility check; the centres are rigorously feasible points) */
 } mvf_bound_args;
 
 /*
@@ -168,6 +186,7 @@ typedef struct {
                                  every node when the batch exceeds max_subdomains (nothing runs) */
     void *workspace;          /* device scratch of mvf_batch_workspace() bytes */
     size_t workspace_bytes;
+    double *extra;            /* device [N][2] or NULL: per node, as mvf_bound_args.extra */
 } mvf_batch_args;
 
 int mvf_batch_workspace(const mvf_tape *tape, int32_t max_nodes, int64_t max_subdomains, int32_t mode,
@@ -196,7 +215,7 @@ int mvf_batch_graph_create(const mvf_tape *tape, int32_t max_nodes, int64_t max_
 int mvf_batch_graph_staging(mvf_batch_graph *g, double **boxes, int32_t **splits);
 int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stream);
 int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int64_t **argmin,
-                           const int32_t **status);
+                           const int32_t **status, const double **extra);
 int mvf_batch_graph_destroy(mvf_batch_graph *g);
 
 /*
@@ -246,6 +265,42 @@ int mvf_vjp_points(const mvf_tape *tape, int64_t B, const double *x, const doubl
  */
 int mvf_gradient_boxes(const mvf_tape *tape, int64_t B, const double *boxes, int32_t root, int32_t grad,
                        double *G, uint32_t *flags, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ---- branch and bound -------------------------------------------------
+ * Host spatial B&B over the bounding entry points (Sec. 3, Fig. BnB_decompose):
+ * best-first on the lower bound (ties to the older node), the node's lower
+ * bound = max(parent's, feasibility-filtered objective bound), upper bound =
+ * least hi(f(c)) over rigorously feasible subdomain centres (mvf_bound_args.
+ * extra; no local solver), pruning when lower >= upper - abs_gap, bisection
+ * of the widest variable (ties to the lower index) at RN((lo + hi) / 2).
+ * Subdomains per node by the adaptive partitioning (Sec. 3.1.2).  Root kinds
+ * come from mvf_tape_set_root_kinds.  Allocates its device buffers (and, for
+ * nodes_per_launch > 1, a batched graph whose breakpoint table holds up to
+ * 256 split intervals per node) for the duration of the call; synchronous.
+ */
+typedef struct {
+    int32_t max_nodes;            /* bound at most this many nodes (>= 1) */
+    int32_t nodes_per_launch;     /* 1: one mvf_bound call per node; K > 1: the K best open nodes
+                                     per replay of a batched graph */
+    int64_t subdomains_per_node;  /* adaptive-partitioning budget per node (>= 1) */
+    double abs_gap;               /* stop when upper - lower <= abs_gap (>= 0) */
+    int32_t mode, grad;           /* MVF_MODE_*, MVF_GRAD_* of the bounding calls */
+    const struct mvf_tuning *tuning;   /* NULL or the batched launches' tuning */
+} mvf_bnb_options;
+
+typedef struct {
+    double lower, upper;          /* certified bounds on the minimum; +inf, +inf when infeasible */
+    int64_t nodes;                /* nodes bounded */
+    int64_t subdomains;           /* subdomain bounds computed */
+    int64_t launches;             /* bounding launches (calls or graph replays) */
+    int32_t open;                 /* open nodes left */
+    int32_t status;               /* 0: gap reached or tree exhausted, 1: node limit, 2: infeasible */
+    double seconds;               /* wall time of the solve */
+} mvf_bnb_result;
+
+/* box: host [n][2].  Returns MVF_OK with the result, or an error code. */
+int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_options *options, mvf_bnb_result *result,
+                  hipStream_t stream);
 
 /* ---- diagnostics ----------------------------------------------------- */
 const char *mvf_strerror(int code);

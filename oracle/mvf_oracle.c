@@ -56,6 +56,8 @@
 enum { OP_VAR = 0, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_SQR, OP_SQRT, OP_EXP, OP_LOG };
 enum { MODE_NIE = 0, MODE_MVF = 1, MODE_BOTH = 2 };
 enum { GRAD_FWD = 0, GRAD_REV = 1 };
+/* root kinds: the objective or an unconstrained function, g <= 0, h = 0 (Sec. 3.1, the NLP) */
+enum { ORC_FREE = 0, ORC_INEQ = 1, ORC_EQ = 2 };
 
 typedef struct { int32_t op, a, b; } orc_node;
 typedef struct { double lo, hi; } ivl;
@@ -480,12 +482,43 @@ typedef struct {
     const int64_t *ks;          /* explicit subdomain list, or NULL */
     int64_t k0, k1, kbase;      /* this job's range; kbase = first index of the call */
     int mode, grad;
+    const int32_t *kinds;       /* [m] root kinds (ORC_FREE / ORC_INEQ / ORC_EQ) or NULL */
     double *per_sub;            /* [m][2][count] or NULL */
     uint32_t *flags;            /* [count] or NULL */
     int64_t count;
     double *red;                /* [m][2] */
     int64_t argmin;
+    double filtered_lo, ub;     /* feasibility-filtered objective bound; upper bound from centres */
 } orc_job;
+
+/*
+ * Subdomain k is proven infeasible when a constraint's bound excludes it: an
+ * inequality g <= 0 with lower bound > 0, an equality h = 0 whose bound does
+ * not contain 0 (the feasibility check of Sec. 3.1 applied per subdomain).
+ */
+static int proven_infeasible(const int32_t *kinds, int m, const ivl *B) {
+    if (!kinds) return 0;
+    for (int r = 1; r < m; ++r) {
+        if (kinds[r] == ORC_INEQ && B[r].lo > 0) return 1;
+        if (kinds[r] == ORC_EQ && (B[r].lo > 0 || B[r].hi < 0)) return 1;
+    }
+    return 0;
+}
+
+/*
+ * The centre c_k is a rigorously feasible point when every inequality's
+ * enclosure at c_k has upper bound <= 0 (no equality constraints: a point
+ * cannot be shown to satisfy h = 0); then hi(f(c_k)) bounds the minimum from
+ * above.  Needs the point pass (MVF modes) and an unflagged subdomain.
+ */
+static double centre_upper_bound(const orc_tape *t, const int32_t *kinds, const ivl *pval) {
+    const int m = t->n_roots;
+    for (int r = 1; r < m && kinds; ++r) {
+        if (kinds[r] == ORC_EQ) return INFINITY;
+        if (kinds[r] == ORC_INEQ && !(pval[t->roots[r]].hi <= 0)) return INFINITY;
+    }
+    return pval[t->roots[0]].hi;
+}
 
 static void *bound_range(void *arg) {
     orc_job *jb = arg;
@@ -497,12 +530,16 @@ static void *bound_range(void *arg) {
     double c[256];
     for (int r = 0; r < m; ++r) { jb->red[2 * r] = INFINITY; jb->red[2 * r + 1] = -INFINITY; }
     jb->argmin = -1;
+    jb->filtered_lo = INFINITY;
+    jb->ub = INFINITY;
     for (int64_t q = jb->k0; q < jb->k1; ++q) {
         int64_t k = jb->ks ? jb->ks[q] : q;
         subdomain(n, jb->box, jb->splits, k, X, c);
         uint32_t f = bound_one(&w, X, c, B);
         int64_t o = q - jb->kbase;
         if (jb->flags) jb->flags[o] = f;
+        if (!proven_infeasible(jb->kinds, m, B)) jb->filtered_lo = fmin(jb->filtered_lo, B[0].lo);
+        if (!f && jb->mode != MODE_NIE) jb->ub = fmin(jb->ub, centre_upper_bound(t, jb->kinds, w.pval));
         for (int r = 0; r < m; ++r) {
             if (jb->per_sub) {
                 jb->per_sub[((size_t)r * 2 + 0) * jb->count + o] = B[r].lo;
@@ -525,8 +562,8 @@ static void *bound_range(void *arg) {
  */
 int orc_bound(const orc_node *nodes, int32_t n_nodes, const double *consts, int32_t n_vars,
               const int32_t *roots, int32_t n_roots, const double *box, const int32_t *splits,
-              const int64_t *ks, int64_t k0, int64_t k1, int mode, int grad,
-              double *per_sub, uint32_t *flags, double *reduced, int64_t *argmin, int nthreads) {
+              const int64_t *ks, int64_t k0, int64_t k1, int mode, int grad, const int32_t *kinds,
+              double *per_sub, uint32_t *flags, double *reduced, int64_t *argmin, double *extra, int nthreads) {
     orc_tape t;
     tape_init(&t, nodes, n_nodes, consts, n_vars, roots, n_roots);
     if (nthreads < 1) nthreads = 1;
@@ -540,7 +577,7 @@ int orc_bound(const orc_node *nodes, int32_t n_nodes, const double *consts, int3
         jb->t = &t; jb->box = box; jb->splits = splits; jb->ks = ks;
         jb->k0 = k0 + count * q / nthreads; jb->k1 = k0 + count * (q + 1) / nthreads;
         jb->kbase = k0;
-        jb->mode = mode; jb->grad = grad; jb->count = count;
+        jb->mode = mode; jb->grad = grad; jb->count = count; jb->kinds = kinds;
         jb->per_sub = per_sub;                  /* [m][2][count], index q - k0 */
         jb->flags = flags;
         jb->red = reds + (size_t)q * 2 * n_roots;
@@ -563,6 +600,15 @@ int orc_bound(const orc_node *nodes, int32_t n_nodes, const double *consts, int3
         }
     }
     if (argmin) *argmin = am;
+    if (extra) {
+        extra[0] = INFINITY;
+        extra[1] = INFINITY;
+        for (int q = 0; q < nthreads; ++q) {
+            if (jobs[q].k1 <= jobs[q].k0) continue;
+            extra[0] = fmin(extra[0], jobs[q].filtered_lo);
+            extra[1] = fmin(extra[1], jobs[q].ub);
+        }
+    }
     free(jobs); free(reds); free(th);
     tape_free(&t);
     return 0;

@@ -25,6 +25,7 @@ GCC_FLAGS = ["-O2", "-std=c11", "-Wall", "-frounding-math", "-ffp-contract=off",
 
 MODE_NIE, MODE_MVF, MODE_BOTH = 0, 1, 2
 GRAD_FWD, GRAD_REV = 0, 1
+FREE, INEQ, EQ = 0, 1, 2
 ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG = 2, 3, 4, 5, 6, 7, 8, 9
 
 
@@ -52,7 +53,8 @@ def lib():
             L.orc_subdomain.argtypes = [ctypes.c_int, P, P, i64, P, P]
             tape = [P, i32, P, i32, P, i32]
             L.orc_bound.restype = ctypes.c_int
-            L.orc_bound.argtypes = tape + [P, P, P, i64, i64, ctypes.c_int, ctypes.c_int, P, P, P, P, ctypes.c_int]
+            L.orc_bound.argtypes = tape + [P, P, P, i64, i64, ctypes.c_int, ctypes.c_int, P, P, P, P, P, P,
+                                           ctypes.c_int]
             L.orc_nie_boxes.restype = ctypes.c_int
             L.orc_nie_boxes.argtypes = tape + [i64, P, P, P]
             L.orc_gradient_boxes.restype = ctypes.c_int
@@ -105,8 +107,11 @@ def subdomain(box: np.ndarray, splits: np.ndarray, k: int):
 
 
 def bound(tape, box, splits, mode: int = MODE_BOTH, grad: int = GRAD_FWD, k_range=None, ks=None,
-          per_sub: bool = True, nthreads: int = 1):
-    """Steps 1-3 on one box.  Returns dict(reduced[m,2], argmin, per_sub[m,2,count], flags[count])."""
+          per_sub: bool = True, nthreads: int = 1, kinds=None):
+    """Steps 1-3 on one box.  Returns dict(reduced[m,2], argmin, per_sub[m,2,count], flags[count],
+    extra[2]): extra = (objective lower bound over the subdomains no constraint proves
+    infeasible, upper bound from rigorously feasible subdomain centres).  kinds[m]: root
+    kinds (FREE, INEQ g <= 0, EQ h = 0); None treats every root as unconstrained."""
     keep, targs = _tape_args(tape)
     box = np.ascontiguousarray(box, dtype=np.float64)
     s = np.ascontiguousarray(splits, dtype=np.int32)
@@ -123,9 +128,12 @@ def bound(tape, box, splits, mode: int = MODE_BOTH, grad: int = GRAD_FWD, k_rang
     flags = np.zeros(max(count, 1), dtype=np.uint32)
     red = np.zeros((m, 2))
     am = ctypes.c_int64(-1)
+    kd = None if kinds is None else np.ascontiguousarray(kinds, dtype=np.int32)
+    extra = np.zeros(2)
     lib().orc_bound(*targs, _p(box), _p(s), None if ks_arr is None else _p(ks_arr), k0, k1, mode, grad,
-                    None if ps is None else _p(ps), _p(flags), _p(red), ctypes.byref(am), nthreads)
-    out = {"reduced": red, "argmin": am.value, "flags": flags[:count]}
+                    None if kd is None else _p(kd), None if ps is None else _p(ps), _p(flags), _p(red),
+                    ctypes.byref(am), _p(extra), nthreads)
+    out = {"reduced": red, "argmin": am.value, "flags": flags[:count], "extra": extra}
     if per_sub:
         out["per_sub"] = ps[:, :, :count]
     return out

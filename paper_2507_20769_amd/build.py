@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmvf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["mvf_kernels.hip", "mvf_tape.cpp", "mvf_api.cpp"]
+SOURCES = ["mvf_kernels.hip", "mvf_tape.cpp", "mvf_api.cpp", "mvf_bnb.cpp"]
 DEVICE_SOURCES = ["mvf_kernels.hip"]
 SLOT_BASE = 128
 FLAGS = [

@@ -21,6 +21,7 @@ struct mvf_tape {
     Instr *d_prog = nullptr;
     int device = 0;
     int n_cu = 256;
+    uint32_t ineq_mask = 0, eq_mask = 0;   // constraint roots (mvf_tape_set_root_kinds)
 };
 
 struct mvf_batch_graph {
@@ -33,9 +34,9 @@ struct mvf_batch_graph {
     size_t ws_bytes = 0;
     double *d_boxes = nullptr;
     int32_t *d_splits = nullptr, *d_count = nullptr, *d_status = nullptr;
-    double *d_reduced = nullptr;
+    double *d_reduced = nullptr, *d_extra = nullptr;
     int64_t *d_argmin = nullptr;
-    double *h_boxes = nullptr, *h_reduced = nullptr;
+    double *h_boxes = nullptr, *h_reduced = nullptr, *h_extra = nullptr;
     int32_t *h_splits = nullptr, *h_count = nullptr, *h_status = nullptr;
     int64_t *h_argmin = nullptr;
     hipGraph_t graph = nullptr;
@@ -120,6 +121,8 @@ TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {
     T.n = t->C.n_vars;
     T.mode = mode;
     T.root_base = t->C.root_base;
+    T.ineq_mask = t->ineq_mask;
+    T.eq_mask = t->eq_mask;
     T.nreg = chunk > 0 ? usable_dwords(T.n_roots) / (4 + 4 * chunk) : usable_dwords(T.n_roots) / 4;
     T.spill_slots = spill_for(t->C, chunk);
     return T;
@@ -156,7 +159,7 @@ int batch_grid(const mvf_tape *t, const mvf_tuning *tu) {
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
-    size_t partial, lo0, k, rec, gacc, total;
+    size_t partial, lo0, k, ext, rec, gacc, total;
     bool g_lds;
 };
 
@@ -167,14 +170,15 @@ SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total)
     L.partial = 0;
     L.lo0 = align_up(L.partial + (size_t)grid * m * 2 * 8);
     L.k = align_up(L.lo0 + (size_t)grid * 8);
-    L.rec = align_up(L.k + (size_t)grid * 8);
+    L.ext = align_up(L.k + (size_t)grid * 8);
+    L.rec = align_up(L.ext + (size_t)grid * 16);
     L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
 }
 
 struct BatchLayout {
-    size_t node_S, item_off, counter, partial, lo0, k, rec, gacc, total;
+    size_t node_S, item_off, counter, partial, lo0, k, ext, rec, gacc, total;
     bool g_lds;
 };
 
@@ -188,7 +192,8 @@ BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int 
     L.partial = align_up(L.counter + 8);
     L.lo0 = align_up(L.partial + items * m * 2 * 8);
     L.k = align_up(L.lo0 + items * 8);
-    L.rec = align_up(L.k + items * 8);
+    L.ext = align_up(L.k + items * 8);
+    L.rec = align_up(L.ext + items * 16);
     L.g_lds = grad_in_lds(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, (int)m);
     L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
@@ -275,7 +280,7 @@ int check_splits(const mvf_tape *t, const int32_t *splits, int64_t *S, int *tab_
 
 int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_dev, int max_nodes, int64_t max_sub,
                     const double *boxes, const int32_t *splits, double *reduced, int64_t *argmin, int32_t *status,
-                    void *ws, size_t ws_bytes, int grid, bool rev, BatchArgs *A) {
+                    double *extra, void *ws, size_t ws_bytes, int grid, bool rev, BatchArgs *A) {
     const BatchLayout L = batch_layout(t, max_nodes, max_sub, grid, rev);
     if (ws_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     uint8_t *w = static_cast<uint8_t *>(ws);
@@ -295,6 +300,8 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
     A->partial = reinterpret_cast<double *>(w + L.partial);
     A->partial_lo0 = reinterpret_cast<double *>(w + L.lo0);
     A->partial_k = reinterpret_cast<int64_t *>(w + L.k);
+    A->partial_ext = reinterpret_cast<double *>(w + L.ext);
+    A->extra = extra;
     A->rec = reinterpret_cast<double2 *>(w + L.rec);
     A->gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     A->item_cap = (int64_t)(max_sub / BLK) + max_nodes + 1;
@@ -303,7 +310,26 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
 
 }  // namespace
 
+int mvf::set_error(int code, const std::string &msg) { return set_err(code, msg); }
+
 extern "C" {
+
+int mvf_tape_set_root_kinds(mvf_tape *t, const int32_t *kinds) {
+    if (!t) return set_err(MVF_EINVAL, "null tape");
+    uint32_t ineq = 0, eq = 0;
+    const int m = (int)t->C.roots.size();
+    if (kinds) {
+        if (kinds[0] != MVF_ROOT_FREE) return set_err(MVF_EINVAL, "root 0 is the objective (MVF_ROOT_FREE)");
+        for (int r = 1; r < m; ++r) {
+            if (kinds[r] == MVF_ROOT_INEQ) ineq |= 1u << r;
+            else if (kinds[r] == MVF_ROOT_EQ) eq |= 1u << r;
+            else if (kinds[r] != MVF_ROOT_FREE) return set_err(MVF_EINVAL, "root kind outside MVF_ROOT_*");
+        }
+    }
+    t->ineq_mask = ineq;
+    t->eq_mask = eq;
+    return MVF_OK;
+}
 
 int mvf_points_workspace(const mvf_tape *t, int32_t op, int64_t B, size_t *bytes) {
     if (!t || !bytes) return set_err(MVF_EINVAL, "null argument");
@@ -453,6 +479,8 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     B.partial = reinterpret_cast<double *>(w + L.partial);
     B.partial_lo0 = reinterpret_cast<double *>(w + L.lo0);
     B.partial_k = reinterpret_cast<int64_t *>(w + L.k);
+    B.partial_ext = reinterpret_cast<double *>(w + L.ext);
+    B.extra = a->extra;
     B.rec = reinterpret_cast<double2 *>(w + L.rec);
     B.gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
@@ -484,7 +512,7 @@ int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning
     const int grid = batch_grid(t, tuning);
     BatchArgs A;
     rc = fill_batch_args(t, a->n_nodes, nullptr, a->max_nodes, a->max_subdomains, a->boxes, a->splits, a->reduced,
-                         a->argmin, a->status, a->workspace, a->workspace_bytes, grid, rev, &A);
+                         a->argmin, a->status, a->extra, a->workspace, a->workspace_bytes, grid, rev, &A);
     if (rc != MVF_OK) return rc;
     if (a->n_nodes == 0) return MVF_OK;
     const int m = (int)t->C.roots.size();
@@ -527,6 +555,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
         hipMalloc(&g->d_splits, (size_t)max_nodes * n * 4) != hipSuccess ||
         hipMalloc(&g->d_count, 4) != hipSuccess || hipMalloc(&g->d_status, (size_t)max_nodes * 4) != hipSuccess ||
         hipMalloc(&g->d_reduced, (size_t)max_nodes * m * 2 * 8) != hipSuccess ||
+        hipMalloc(&g->d_extra, (size_t)max_nodes * 2 * 8) != hipSuccess ||
         hipMalloc(&g->d_argmin, (size_t)max_nodes * 8) != hipSuccess)
         return fail(MVF_ENOMEM, "hipMalloc node buffers");
     if (hipHostMalloc(reinterpret_cast<void **>(&g->h_boxes), (size_t)max_nodes * n * 2 * 8, hipHostMallocDefault) !=
@@ -539,6 +568,8 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
         hipHostMalloc(reinterpret_cast<void **>(&g->h_reduced), (size_t)max_nodes * m * 2 * 8,
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&g->h_argmin), (size_t)max_nodes * 8, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&g->h_extra), (size_t)max_nodes * 2 * 8, hipHostMallocDefault) !=
             hipSuccess)
         return fail(MVF_ENOMEM, "hipHostMalloc staging");
     std::memset(g->h_boxes, 0, (size_t)max_nodes * n * 2 * 8);
@@ -547,7 +578,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
 
     BatchArgs A;
     rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
-                         g->d_argmin, g->d_status, g->d_ws, g->ws_bytes, grid, rev, &A);
+                         g->d_argmin, g->d_status, g->d_extra, g->d_ws, g->ws_bytes, grid, rev, &A);
     if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
     const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
                                  spill_bytes(spill_for(t->C, chunk), chunk));
@@ -568,7 +599,8 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     ok = ok && hipMemcpyAsync(g->h_reduced, g->d_reduced, (size_t)max_nodes * m * 2 * 8, hipMemcpyDeviceToHost, cs) ==
                    hipSuccess &&
          hipMemcpyAsync(g->h_argmin, g->d_argmin, (size_t)max_nodes * 8, hipMemcpyDeviceToHost, cs) == hipSuccess &&
-         hipMemcpyAsync(g->h_status, g->d_status, (size_t)max_nodes * 4, hipMemcpyDeviceToHost, cs) == hipSuccess;
+         hipMemcpyAsync(g->h_status, g->d_status, (size_t)max_nodes * 4, hipMemcpyDeviceToHost, cs) == hipSuccess &&
+         hipMemcpyAsync(g->h_extra, g->d_extra, (size_t)max_nodes * 2 * 8, hipMemcpyDeviceToHost, cs) == hipSuccess;
     hipError_t ee = hipStreamEndCapture(cs, &g->graph);
     hipStreamDestroy(cs);
     if (!ok || ee != hipSuccess) return fail(MVF_EHIP, "graph capture failed");
@@ -607,11 +639,12 @@ int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stre
 }
 
 int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int64_t **argmin,
-                           const int32_t **status) {
+                           const int32_t **status, const double **extra) {
     if (!g) return set_err(MVF_EINVAL, "null graph");
     if (reduced) *reduced = g->h_reduced;
     if (argmin) *argmin = g->h_argmin;
     if (status) *status = g->h_status;
+    if (extra) *extra = g->h_extra;
     return MVF_OK;
 }
 
@@ -626,6 +659,8 @@ int mvf_batch_graph_destroy(mvf_batch_graph *g) {
     hipFree(g->d_status);
     hipFree(g->d_reduced);
     hipFree(g->d_argmin);
+    hipFree(g->d_extra);
+    hipHostFree(g->h_extra);
     hipHostFree(g->h_boxes);
     hipHostFree(g->h_splits);
     hipHostFree(g->h_count);

@@ -101,6 +101,9 @@ struct Compiled {
     int64_t ref_fwd = 0, ref_rev = 0;
 };
 
+// Records the message returned by mvf_last_error() and returns code.
+int set_error(int code, const std::string &msg);
+
 // Validates and compiles; returns an MVF_* code and fills err on failure.
 int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
                  const int32_t *roots, int32_t n_roots, Compiled *out, std::string *err);

@@ -15,6 +15,7 @@ struct TapeArgs {
     const Instr *prog;
     int32_t n_instr, n_roots, n, mode;
     int32_t root_base;       // program record index of root 0's {begin, len, result slot, records}
+    uint32_t ineq_mask, eq_mask;  // roots that are constraints g <= 0 / h = 0 (bit r for root r)
     int32_t nreg;            // register slots of the launch's tangent chunk; higher slot ids live in LDS
     int32_t spill_slots;     // LDS spill slots per lane (forward tangent passes)
 };
@@ -32,6 +33,8 @@ struct BoxArgs {
     double *partial;         // [grid][m][2]
     double *partial_lo0;     // [grid]
     int64_t *partial_k;      // [grid]
+    double *partial_ext;     // [grid][2]: feasibility-filtered objective bound, upper bound from centres
+    double *extra;           // [2] or null
     double2 *rec;            // reverse-mode tape [max_rec][grid * BLK]
     double2 *gacc;           // reverse-mode gradient accumulators [n][grid * BLK] when not in LDS
 };
@@ -54,6 +57,8 @@ struct BatchArgs {
     double *partial;         // [items][m][2]
     double *partial_lo0;     // [items]
     int64_t *partial_k;      // [items]
+    double *partial_ext;     // [items][2]
+    double *extra;           // [N][2] or null
     double2 *rec;            // reverse-mode tape [max_rec][grid * BLK]
     double2 *gacc;           // reverse-mode gradient accumulators [n][grid * BLK] when not in LDS
 };
@@ -108,7 +113,7 @@ inline size_t lds_bytes(int n_instr, int tab_cap, int n, int m, bool g_in_lds, s
     size_t b = (size_t)n_instr * 16 + (size_t)tab_cap * 32;
     if (g_in_lds) b += (size_t)n * BLK * 16;
     b += spill;
-    b += ((size_t)(BLK / 64) * (2 * m + 3) * 8 + 15) & ~(size_t)15;   // per-wave reduction records
+    b += ((size_t)(BLK / 64) * (2 * m + 5) * 8 + 15) & ~(size_t)15;   // per-wave reduction records
     b += (2 * MVF_MAX_VARS + 8) * 4;
     b = (b + 15) & ~(size_t)15;
     b += (size_t)n * BLK * sizeof(uint16_t);

@@ -489,17 +489,43 @@ __device__ __forceinline__ void wave_argmin(double &v, int64_t &k) {
 // Where a lane's results go: the optional per-subdomain output and the wave's
 // running reduction record in LDS.  The record holds, for each root r, the
 // minimum lower endpoint and the minimum of -upper at [2r], [2r + 1]; the
-// objective's argmin (value, subdomain) at [2m], [2m + 1]; and the smallest
-// flagged subdomain at [2m + 2].
+// objective's argmin (value, subdomain) at [2m], [2m + 1]; the smallest
+// flagged subdomain at [2m + 2]; the feasibility-filtered objective bound at
+// [2m + 3] and the upper bound from feasible centres at [2m + 4].
 struct LaneOut {
     double *per_sub;     // [m][2][S] or null
     int64_t S, k;
     double *w;           // the wave's record
     int lane;
     bool active;
+    uint32_t ineq, eq;   // constraint roots (bit masks)
 };
 
-constexpr int wred_len(int m) { return 2 * m + 3; }
+constexpr int wred_len(int m) { return 2 * m + 5; }
+
+// Per-lane state of the two bounds a B&B needs besides the hulls: the
+// objective's lower bound unless a constraint proves the subdomain infeasible
+// (inequality lower bound > 0, or an equality bound excluding 0), and the
+// objective's upper bound at the centre when every inequality's enclosure at
+// the centre is <= 0 (no equality constraints).
+struct FeasTrack {
+    double obj_lo = 0.0, centre_hi = __builtin_inf();
+    bool infeasible = false, centre_ok = true;
+};
+
+__device__ __forceinline__ void track_root(FeasTrack &F, int r, Iv B, Iv FC, bool have_fc, const LaneOut &o) {
+    if (r == 0) {
+        F.obj_lo = B.lo;
+        F.centre_hi = -FC.nh;
+        F.centre_ok = have_fc && o.eq == 0;
+        return;
+    }
+    if ((o.ineq >> r) & 1u) {
+        F.infeasible |= B.lo > 0.0;
+        F.centre_ok &= FC.nh >= 0.0;                         // hi(g(c)) <= 0; false for NaN
+    }
+    if ((o.eq >> r) & 1u) F.infeasible |= B.lo > 0.0 || B.nh > 0.0;   // 0 not in [lo, hi]
+}
 
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
 #pragma unroll
@@ -542,8 +568,19 @@ __device__ __forceinline__ void reduce_root(int r, int m, Iv B, const LaneOut &o
 // After all roots: the domain flag, the per-subdomain bounds of a flagged
 // subdomain ([-inf, +inf] for every root), and the wave's smallest flagged
 // subdomain.
-__device__ __forceinline__ void finish_lane(int m, uint32_t bad, const LaneOut &o, uint32_t *flags) {
+__device__ __forceinline__ void finish_lane(int m, uint32_t bad, const FeasTrack &F, const LaneOut &o,
+                                            uint32_t *flags) {
     if (o.active && flags) flags[o.k] = bad;
+    {
+        const double inf = __builtin_inf();
+        const double fl = !o.active ? inf : bad ? -inf : F.infeasible ? inf : F.obj_lo;
+        const double ub = o.active && !bad && F.centre_ok && F.centre_hi == F.centre_hi ? F.centre_hi : inf;
+        const double wfl = wave_min(fl), wub = wave_min(ub);
+        if (o.lane == 0) {
+            o.w[2 * m + 3] = fmin(o.w[2 * m + 3], wfl);
+            o.w[2 * m + 4] = fmin(o.w[2 * m + 4], wub);
+        }
+    }
     if (o.active && bad && o.per_sub) {
         for (int r = 0; r < m; ++r) {
             o.per_sub[(int64_t)(2 * r) * o.S + o.k] = -__builtin_inf();
@@ -561,25 +598,28 @@ __device__ __forceinline__ void reset_wred(double *w, int m) {
     for (int r = 0; r < 2 * m + 1; ++r) w[r] = __builtin_inf();
     reinterpret_cast<int64_t *>(w)[2 * m + 1] = INT64_MAX;
     reinterpret_cast<int64_t *>(w)[2 * m + 2] = INT64_MAX;
+    w[2 * m + 3] = __builtin_inf();
+    w[2 * m + 4] = __builtin_inf();
 }
 
 // Bounds of every root on the lane's subdomain, each folded into the wave's
 // reduction record as soon as it is known.  Returns the domain flag
 // (violation or NaN).
 template <int C, bool REV>
-__device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx &X, const LaneOut &o) {
+__device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx &X, const LaneOut &o,
+                               FeasTrack &F) {
     mode_round_down();
     uint32_t bad = 0;
     for (int r = 0; r < m; ++r) {
         const uint4 ri = X.prog[root_base + r];
         const int pb = (int)__builtin_amdgcn_readfirstlane(ri.x), pl = (int)__builtin_amdgcn_readfirstlane(ri.y);
         const int rs = (int)__builtin_amdgcn_readfirstlane(ri.z);
-        Iv B;
+        Iv B, FC = kZero;
         Iv g0[1];
         if (mode == MVF_MODE_NIE) {
             B = run_program<0, false, false>(X, pb, pl, rs, 0, g0, bad);
         } else if constexpr (REV) {
-            const Iv FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
+            FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
             const Iv nie = run_program<0, false, true>(X, pb, pl, rs, 0, g0, bad);
             for (int i = 0; i < n; ++i) X.G[i * X.gstride] = make_double2(0.0, 0.0);
             slot_wr((uint32_t)rs * 4, kOne);
@@ -594,7 +634,7 @@ __device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx 
             B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};
         } else if constexpr (C > 0) {
             Iv G[C];
-            const Iv FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
+            FC = run_program<0, true, false>(X, pb, pl, rs, 0, g0, bad);
             Iv acc = FC, nie = kZero;
             for (int c0 = 0; c0 < n; c0 += C) {
                 Iv v = run_program<C, false, false>(X, pb, pl, rs, c0, G, bad);
@@ -614,6 +654,7 @@ __device__ uint32_t bound_lane(int m, int n, int mode, int root_base, const Ctx 
         }
         if (B.lo != B.lo || B.nh != B.nh) bad = 1;
         reduce_root(r, m, B, o);
+        track_root(F, r, B, FC, mode != MVF_MODE_NIE, o);
     }
     mode_round_nearest();
     return bad;
@@ -685,9 +726,16 @@ __device__ __forceinline__ Smem carve(uint8_t *smem, const TA &T, int tab_cap, i
 // subdomain makes every root's hull [-inf, +inf]; the objective's argmin is
 // then the smallest subdomain whose lower bound is -inf.
 __device__ __forceinline__ void write_partial(const double *wred, int waves, int m, double *part, double *plo0,
-                                              int64_t *pk) {
+                                              int64_t *pk, double *pext) {
     double best = __builtin_inf();
     int64_t bk = INT64_MAX, kb = INT64_MAX;
+    double fl = __builtin_inf(), ub = __builtin_inf();
+    for (int w = 0; w < waves; ++w) {
+        fl = fmin(fl, wred[w * wred_len(m) + 2 * m + 3]);
+        ub = fmin(ub, wred[w * wred_len(m) + 2 * m + 4]);
+    }
+    pext[0] = fl;
+    pext[1] = ub;
     for (int r = 0; r < m; ++r) {
         double l = __builtin_inf(), h = __builtin_inf();
         for (int w = 0; w < waves; ++w) {
@@ -762,6 +810,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         const bool active = k < S;
         decode_subdomain(n, active ? k : S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
         LaneOut o;
+        FeasTrack F;
         uint32_t bad;
         {
             const auto K = kargs<BoundKArgs>();
@@ -771,24 +820,49 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
             o.w = s.wred + wave * wred_len(m);
             o.lane = lane;
             o.active = active;
-            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o);
+            o.ineq = K->T.ineq_mask;
+            o.eq = K->T.eq_mask;
+            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o, F);
         }
-        finish_lane(m, bad, o, kargs<BoundKArgs>()->B.flags);
+        finish_lane(m, bad, F, o, kargs<BoundKArgs>()->B.flags);
     }
     __syncthreads();
     if (tid == 0) {
         const auto K = kargs<BoundKArgs>();
         write_partial(s.wred, BLK / 64, m, K->B.partial + (size_t)blockIdx.x * m * 2, K->B.partial_lo0 + blockIdx.x,
-                      K->B.partial_k + blockIdx.x);
+                      K->B.partial_k + blockIdx.x, K->B.partial_ext + 2 * (size_t)blockIdx.x);
     }
 }
 
-// Reduce per-block partials [nblocks][m][2] into reduced[m][2] (lo, hi) and argmin.
+// minimum over the workgroup of one value per thread (all threads get it)
+__device__ __forceinline__ double block_min(double v, double *sv, int tid) {
+    sv[tid] = v;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (tid < st) sv[tid] = fmin(sv[tid], sv[tid + st]);
+        __syncthreads();
+    }
+    const double r = sv[0];
+    __syncthreads();
+    return r;
+}
+
+// Reduce per-block partials [nblocks][m][2] into reduced[m][2] (lo, hi), argmin,
+// and the two B&B bounds (extra, nullable).
 __global__ __launch_bounds__(256) void finish_kernel(const double *partial, const double *plo0, const int64_t *pk,
-                                                     int nblocks, int m, double *reduced, int64_t *argmin) {
+                                                     const double *pext, int nblocks, int m, double *reduced,
+                                                     int64_t *argmin, double *extra) {
     __shared__ double sv[256];
     __shared__ int64_t sk[256];
     const int tid = threadIdx.x;
+    if (extra) {
+        for (int c = 0; c < 2; ++c) {
+            double v = __builtin_inf();
+            for (int b = tid; b < nblocks; b += 256) v = fmin(v, pext[2 * b + c]);
+            v = block_min(v, sv, tid);
+            if (tid == 0) extra[c] = v;
+        }
+    }
     for (int r = 0; r < m; ++r) {
         for (int c = 0; c < 2; ++c) {
             double v = __builtin_inf();
@@ -975,17 +1049,20 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         o.w = s.wred + wave * wred_len(m);
         o.lane = lane;
         o.active = active;
+        FeasTrack F;
         uint32_t bad;
         {
             const auto K = kargs<BatchKArgs>();
-            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o);
+            o.ineq = K->T.ineq_mask;
+            o.eq = K->T.eq_mask;
+            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o, F);
         }
-        finish_lane(m, bad, o, nullptr);
+        finish_lane(m, bad, F, o, nullptr);
         __syncthreads();
         if (tid == 0) {
             const auto K = kargs<BatchKArgs>();
             write_partial(s.wred, BLK / 64, m, K->A.partial + (size_t)item * m * 2, K->A.partial_lo0 + item,
-                          K->A.partial_k + item);
+                          K->A.partial_k + item, K->A.partial_ext + 2 * (size_t)item);
         }
     }
 }
@@ -998,6 +1075,14 @@ __global__ __launch_bounds__(256) void batch_finish_kernel(BatchArgs A, int m) {
     if (node >= node_count(A)) return;                    // uniform per block
     const int64_t b0 = A.item_off[node], b1 = A.item_off[node + 1];
     const bool ok = A.status[node] == 0;
+    if (A.extra) {
+        for (int c = 0; c < 2; ++c) {
+            double v = __builtin_inf();
+            for (int64_t b = b0 + tid; b < b1; b += 256) v = fmin(v, A.partial_ext[2 * b + c]);
+            v = block_min(v, sv, tid);
+            if (tid == 0) A.extra[2 * (size_t)node + c] = ok ? v : __builtin_nan("");
+        }
+    }
     for (int r = 0; r < m; ++r) {
         for (int c = 0; c < 2; ++c) {
             double v = __builtin_inf();
@@ -1214,8 +1299,8 @@ hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev
     });
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, stream, B.partial, B.partial_lo0, B.partial_k, grid,
-                       T.n_roots, B.reduced, B.argmin);
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, stream, B.partial, B.partial_lo0, B.partial_k,
+                       B.partial_ext, grid, T.n_roots, B.reduced, B.argmin, B.extra);
     return hipGetLastError();
 }
 

@@ -50,25 +50,39 @@ class Tuning(ctypes.Structure):
         return f"Tuning(grad={self.grad}, chunk={self.chunk}, grid_blocks={self.grid_blocks}, best_ms={self.best_ms:.3f})"
 
 
+class BnbOptions(ctypes.Structure):
+    _fields_ = [("max_nodes", ctypes.c_int32), ("nodes_per_launch", ctypes.c_int32),
+                ("subdomains_per_node", ctypes.c_int64), ("abs_gap", ctypes.c_double), ("mode", ctypes.c_int32),
+                ("grad", ctypes.c_int32), ("tuning", ctypes.c_void_p)]
+
+
+class BnbResult(ctypes.Structure):
+    _fields_ = [("lower", ctypes.c_double), ("upper", ctypes.c_double), ("nodes", ctypes.c_int64),
+                ("subdomains", ctypes.c_int64), ("launches", ctypes.c_int64), ("open", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
 class BatchArgs(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int32), ("max_nodes", ctypes.c_int32), ("max_subdomains", ctypes.c_int64),
                 ("boxes", ctypes.c_void_p), ("splits", ctypes.c_void_p), ("mode", ctypes.c_int32),
                 ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
-                ("status", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t)]
+                ("status", ctypes.c_void_p), ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("extra", ctypes.c_void_p)]
 
 
 class BoundArgs(ctypes.Structure):
     _fields_ = [("box", ctypes.c_void_p), ("splits", ctypes.c_void_p), ("mode", ctypes.c_int32),
                 ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
                 ("per_sub", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p)]
+                ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p), ("extra", ctypes.c_void_p)]
 
 
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
            "mvf_bound_workspace", "mvf_bound", "mvf_adaptive_splits", "mvf_batch_workspace", "mvf_bound_batch",
            "mvf_batch_graph_create", "mvf_batch_graph_staging", "mvf_batch_graph_launch", "mvf_batch_graph_result",
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
-           "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes"]
+           "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
+           "mvf_tape_set_root_kinds", "mvf_bnb_solve"]
 
 
 def lib():
@@ -78,6 +92,14 @@ def lib():
         if _lib is None:
             if not os.path.exists(LIB_PATH):
                 raise ImportError(f"{LIB_PATH} is not built; run paper_2507_20769_amd/build.py")
+            # torch ships its own HIP and HSA runtimes under the same sonames as the
+            # system ROCm ones that libmvf links; whichever loads first serves the whole
+            # process.  Load torch's first, so that torch and libmvf share one runtime
+            # (torch finds no device when it is handed the other one).
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = ctypes.CDLL(LIB_PATH)
             P, i32 = ctypes.c_void_p, ctypes.c_int32
             L.mvf_strerror.restype = ctypes.c_char_p
@@ -115,7 +137,12 @@ def lib():
             L.mvf_batch_graph_result.restype = ctypes.c_int
             L.mvf_batch_graph_result.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
                                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)),
-                                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
+                                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_int32)),
+                                                 ctypes.POINTER(ctypes.POINTER(ctypes.c_double))]
+            L.mvf_tape_set_root_kinds.restype = ctypes.c_int
+            L.mvf_tape_set_root_kinds.argtypes = [P, P]
+            L.mvf_bnb_solve.restype = ctypes.c_int
+            L.mvf_bnb_solve.argtypes = [P, P, ctypes.POINTER(BnbOptions), ctypes.POINTER(BnbResult), P]
             L.mvf_batch_graph_destroy.restype = ctypes.c_int
             L.mvf_batch_graph_destroy.argtypes = [P]
             L.mvf_autotune.restype = ctypes.c_int
@@ -173,6 +200,15 @@ class Tape:
         self.n_vars = int(tape.n_vars)
         self.n_roots = int(tape.n_roots)
 
+    def set_root_kinds(self, kinds):
+        """Root kinds: 0 objective/unconstrained, 1 inequality g <= 0, 2 equality h = 0 (root 0: 0)."""
+        self._kinds = None if kinds is None else np.ascontiguousarray(kinds, dtype=np.int32)
+        rc = lib().mvf_tape_set_root_kinds(self.handle, None if self._kinds is None else
+                                           self._kinds.ctypes.data_as(ctypes.c_void_p))
+        if rc != 0:
+            raise MVFError(rc, "mvf_tape_set_root_kinds")
+        return self
+
     def stats(self) -> TapeStats:
         st = TapeStats()
         rc = lib().mvf_tape_stats_get(self.handle, ctypes.byref(st))
@@ -210,6 +246,7 @@ class BoundCall:
         m = tape.n_roots
         self.reduced = torch.empty((m, 2), dtype=torch.float64, device=dev)
         self.argmin = torch.empty(1, dtype=torch.int64, device=dev)
+        self.extra = torch.empty(2, dtype=torch.float64, device=dev)
         self.per_sub = torch.empty((m, 2, self.S), dtype=torch.float64, device=dev) if per_sub else None
         self.flags = torch.empty(self.S, dtype=torch.int32, device=dev) if flags else None
         ws = ctypes.c_size_t()
@@ -223,7 +260,7 @@ class BoundCall:
                               self.per_sub.data_ptr() if per_sub else None,
                               self.flags.data_ptr() if flags else None,
                               self.workspace.data_ptr(), self.workspace.numel(),
-                              ctypes.addressof(tuning) if tuning is not None else None)
+                              ctypes.addressof(tuning) if tuning is not None else None, self.extra.data_ptr())
 
     def launch(self, stream=None):
         rc = lib().mvf_bound(self.tape.handle, ctypes.byref(self.args), _stream_ptr(stream))
@@ -240,7 +277,7 @@ def bound(tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str 
     per_sub [m, 2, S] and flags [S].  Asynchronous on ``stream``.
     """
     call = BoundCall(tape, box, splits, mode, grad, per_sub, flags).launch(stream)
-    out = {"reduced": call.reduced, "argmin": call.argmin, "workspace": call.workspace}
+    out = {"reduced": call.reduced, "argmin": call.argmin, "extra": call.extra, "workspace": call.workspace}
     if per_sub:
         out["per_sub"] = call.per_sub
     if flags:
@@ -287,10 +324,10 @@ class BatchCall:
         self.reduced = torch.empty((N, m, 2), dtype=torch.float64, device=dev)
         self.argmin = torch.empty(N, dtype=torch.int64, device=dev)
         self.status = torch.empty(N, dtype=torch.int32, device=dev)
+        self.extra = torch.empty((N, 2), dtype=torch.float64, device=dev)
         self.args = BatchArgs(N, N, max(cap, 1), self.boxes.data_ptr(), self.splits.data_ptr(), MVF_MODE[mode],
                               MVF_GRAD[grad], self.reduced.data_ptr(), self.argmin.data_ptr(), self.status.data_ptr(),
-                              self.workspace.data_ptr(), self.workspace.numel(),
-                              ctypes.addressof(tuning) if tuning is not None else None)
+                              self.workspace.data_ptr(), self.workspace.numel(), self.extra.data_ptr())
 
     def launch(self, stream=None):
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
@@ -302,7 +339,7 @@ class BatchCall:
 
 def bound_batch(tape: Tape, boxes, splits, mode: str = "both", grad: str = "rev", tuning=None, stream=None) -> dict:
     call = BatchCall(tape, boxes, splits, mode, grad, tuning).launch(stream)
-    return {"reduced": call.reduced, "argmin": call.argmin, "status": call.status}
+    return {"reduced": call.reduced, "argmin": call.argmin, "status": call.status, "extra": call.extra}
 
 
 class BatchGraph:
@@ -328,7 +365,9 @@ class BatchGraph:
         rp = ctypes.POINTER(ctypes.c_double)()
         ap = ctypes.POINTER(ctypes.c_int64)()
         stp = ctypes.POINTER(ctypes.c_int32)()
-        lib().mvf_batch_graph_result(h, ctypes.byref(rp), ctypes.byref(ap), ctypes.byref(stp))
+        ep = ctypes.POINTER(ctypes.c_double)()
+        lib().mvf_batch_graph_result(h, ctypes.byref(rp), ctypes.byref(ap), ctypes.byref(stp), ctypes.byref(ep))
+        self.h_extra = np.ctypeslib.as_array(ep, shape=(max_nodes, 2))
         self.h_reduced = np.ctypeslib.as_array(rp, shape=(max_nodes, tape.n_roots, 2))
         self.h_argmin = np.ctypeslib.as_array(ap, shape=(max_nodes,))
         self.h_status = np.ctypeslib.as_array(stp, shape=(max_nodes,))
@@ -348,6 +387,10 @@ class BatchGraph:
         """Copies of (reduced [N, m, 2], argmin [N], status [N]); synchronise first."""
         N = self.n
         return self.h_reduced[:N].copy(), self.h_argmin[:N].copy(), self.h_status[:N].copy()
+
+    def extra(self):
+        """Copy of the per-node (feasibility-filtered lower bound, centre upper bound) [N, 2]."""
+        return self.h_extra[:self.n].copy()
 
     def close(self):
         if getattr(self, "handle", None):
@@ -494,3 +537,25 @@ def MVFPoint():
 def point_function(tape: Tape, x):
     """Differentiable f(x): MVFPoint().apply(x, tape)."""
     return MVFPoint().apply(x, tape)
+
+
+# ---------------------------------------------------------------------------
+# branch and bound
+# ---------------------------------------------------------------------------
+def bnb_solve(tape: Tape, box, max_nodes: int = 1000, gap: float = 1e-4, budget: int = 4096,
+              nodes_per_launch: int = 1, mode: str = "both", grad: str = "fwd",
+              tuning: Optional[Tuning] = None, stream=None) -> dict:
+    """Spatial B&B with GPU subdomain bounding (synchronous).  box: host [n, 2].
+
+    Root kinds come from Tape.set_root_kinds.  Returns dict(lower, upper,
+    nodes, subdomains, launches, open, status, seconds)."""
+    b = np.ascontiguousarray(box, dtype=np.float64)
+    assert b.shape == (tape.n_vars, 2)
+    opt = BnbOptions(int(max_nodes), int(nodes_per_launch), int(budget), float(gap), MVF_MODE[mode], MVF_GRAD[grad],
+                     ctypes.addressof(tuning) if tuning is not None else None)
+    res = BnbResult()
+    rc = lib().mvf_bnb_solve(tape.handle, b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(res),
+                             _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_bnb_solve")
+    return {k: getattr(res, k) for k, _ in BnbResult._fields_}
