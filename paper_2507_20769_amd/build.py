@@ -31,6 +31,9 @@ FLAGS = [
     # coefficients) and argument values out of the interpreter loops and keeps
     # them in SGPRs there; rematerialising them where used spills far less
     "-mllvm", "-disable-machine-licm",
+    # branches on wave-uniform values (operand kinds, opcodes) stay plain scalar
+    # branches instead of being restructured with execution-mask flow blocks
+    "-mllvm", "-structurizecfg-skip-uniform-regions",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

@@ -216,9 +216,9 @@ __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh
 
 // enclosure of 1/(2 sqrt(u)) from Z = sqrt(U); unbounded above when z_lo is 0
 __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
-    Iv t = itwice(z);
-    if (t.lo <= 0.0) return {div_rd(1.0, -t.nh), -__builtin_inf()};
-    return irecip(t);
+    const Iv t = itwice(z);
+    const double nh = div_rd(-1.0, t.lo);             // branch-free: lanes differ in the sign test
+    return {div_rd(1.0, -t.nh), t.lo <= 0.0 ? -__builtin_inf() : nh};
 }
 
 // exp and log: library value in round-to-nearest, widened by two ulps per side

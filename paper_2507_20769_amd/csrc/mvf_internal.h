@@ -29,10 +29,10 @@ enum : uint32_t {
     I_DIVKN = 16,     // U / (-k)   (k stored as its magnitude)
     I_NOPS = 17,
 };
-// Operand kinds.  K_PREV: the result of the immediately preceding
-// instruction, which is its only consumer; that result never reaches the slot
-// file and stays in registers (value, tangents, or in the reverse sweep its
-// adjoint).
+// Operand kinds.  A result whose only consumer is the next instruction goes
+// to slot 0, which the allocator keeps for such short-lived values (its
+// adjoint in the reverse sweep lands in slot 0 the same way); K_PREV is not
+// emitted.
 enum : uint32_t { K_SLOT = 0, K_VAR = 1, K_CONST = 2, K_PREV = 3 };
 
 // 16-byte instruction, read from LDS by all lanes of a wave (broadcast):
@@ -42,7 +42,7 @@ enum : uint32_t { K_SLOT = 0, K_VAR = 1, K_CONST = 2, K_PREV = 3 };
 // init_x: this instruction is the last consumer of operand x, so in the
 // reverse sweep it makes the first contribution to that adjoint (written, not
 // accumulated).  nowrite: the result is only consumed by the next instruction
-// (as K_PREV).  For I_DIVK/I_DIVKN, b is the index of a 16-byte record after
+// (it is written to slot 0).  For I_DIVK/I_DIVKN, b is the index of a 16-byte record after
 // the programs holding the enclosure of 1/|k| as (lo, -hi).
 struct Instr {
     uint32_t w0, w1;

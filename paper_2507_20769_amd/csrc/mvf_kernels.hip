@@ -138,22 +138,18 @@ __device__ __forceinline__ void store_slot(const Ctx &X, uint32_t s, const Iv (&
     slot_wr_n<1 + C>(s * (4 + 4 * C), Z);
 }
 
-// Operand (kind, a): value in A[0]; for a slot or the previous result the C
-// tangent components in A[1..C] (dense); for a variable, hit = its component
-// index within [c0, c0 + C) (its tangent is one there and zero elsewhere), -1
-// otherwise; constants have zero tangents.
+// Operand (kind, a): value in A[0]; for a slot the C tangent components in
+// A[1..C] (dense); for a variable, hit = its component index within
+// [c0, c0 + C) (its tangent is one there and zero elsewhere), -1 otherwise;
+// constants have zero tangents.
 template <int C, bool POINT, int VS>
-__device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, double k, int c0,
-                                      const Iv (&P)[1 + C], Iv (&A)[1 + C], bool &dense, int &hit) {
+__device__ __forceinline__ void fetch(const Ctx &X, uint32_t kind, uint32_t a, double k, int c0, Iv (&A)[1 + C],
+                                      bool &dense, int &hit) {
     dense = false;
     hit = -1;
     if (kind == K_SLOT) {
         dense = true;
         load_slot<C>(X, a, A);
-    } else if (kind == K_PREV) {
-        dense = true;
-#pragma unroll
-        for (int i = 0; i <= C; ++i) A[i] = P[i];
     } else if (kind == K_VAR) {
         A[0] = var_val<VS, POINT>(X, a);
         const int h = (int)a - c0;
@@ -192,16 +188,12 @@ __device__ __forceinline__ Dec decode(uint4 raw) {
 
 // Run one root program forward; returns the root's value interval and (C > 0)
 // its tangent components [c0, c0 + C).  Each instruction moves its operands
-// and its result as whole slots (value and components); a result consumed
-// only by the next instruction stays in registers (P).  With TAPE, writes the
-// reverse-mode records.
+// and its result as whole slots (value and components).  With TAPE, writes
+// the reverse-mode records.
 template <int C, bool POINT, bool TAPE, int VS = VS_TABLE>
 __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0, Iv (&gout)[C > 0 ? C : 1],
                           uint32_t &bad) {
     constexpr int N = 1 + C;
-    Iv P[N];
-#pragma unroll
-    for (int i = 0; i < N; ++i) P[i] = kZero;
     int64_t rp = 0;                                    // record position
     const int end = begin + len;
     uint4 nxt = X.prog[begin];
@@ -210,8 +202,8 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
         Iv A[N], B[N], Z[N];
         bool ad, bd = false;
         int ha, hb = -1;
-        fetch<C, POINT, VS>(X, I.ak, I.a, I.k, c0, P, A, ad, ha);
-        if (I.op <= I_DIV) fetch<C, POINT, VS>(X, I.bk, I.b, I.k, c0, P, B, bd, hb);
+        fetch<C, POINT, VS>(X, I.ak, I.a, I.k, c0, A, ad, ha);
+        if (I.op <= I_DIV) fetch<C, POINT, VS>(X, I.bk, I.b, I.k, c0, B, bd, hb);
         nxt = X.prog[pc + 1 < end ? pc + 1 : pc];      // prefetch the next instruction
         const Iv U = A[0], V = B[0];
 #pragma unroll
@@ -362,12 +354,7 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
             break;
         }
         }
-        if (I.w0 & W0_NOWRITE) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) P[i] = Z[i];
-        } else {
-            store_slot<C>(X, I.d, Z);
-        }
+        store_slot<C>(X, I.d, Z);
     }
     if (res_slot < 0) return kZero;                    // the union program: roots are read by the caller
     Iv R[N];
@@ -384,13 +371,9 @@ __device__ __forceinline__ Iv ld_rec(const Ctx &X, int64_t rp) {
 }
 
 // adjoint contribution c to operand (kind, a); init: first contribution
-// (written, not accumulated); neg: subtract instead of add; pa is the adjoint
-// of the previous instruction's register-held result
-__device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t a, bool init, bool neg, Iv c,
-                                           Iv &pa) {
-    if (kind == K_PREV) {
-        pa = init ? (neg ? ineg(c) : c) : (neg ? isub(pa, c) : iadd(pa, c));   // 0 - [lo, hi] = [-hi, -lo]
-    } else if (kind == K_SLOT) {
+// (written, not accumulated; 0 - [lo, hi] = [-hi, -lo]); neg: subtract
+__device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t a, bool init, bool neg, Iv c) {
+    if (kind == K_SLOT) {
         const uint32_t idx = a * 4;
         if (init) {
             slot_wr(idx, neg ? ineg(c) : c);
@@ -410,7 +393,6 @@ __device__ __forceinline__ void contribute(const Ctx &X, uint32_t kind, uint32_t
 // program's results (for a root program: [1, 1] in its result slot).
 template <int VS = VS_TABLE>
 __device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
-    Iv pa = kZero;
     int64_t rp = n_rec;
     uint4 nxt = X.prog[begin + len - 1];
     for (int pc = begin + len - 1; pc >= begin; --pc) {
@@ -418,11 +400,11 @@ __device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
         nxt = X.prog[pc > begin ? pc - 1 : pc];        // prefetch the next instruction
         const Dec I = decode(raw);
         const bool ia = (I.w0 & W0_INIT_A) != 0, ib = (I.w0 & W0_INIT_B) != 0;
-        const Iv zb = (I.w0 & W0_NOWRITE) ? pa : slot_rd(I.d * 4);
+        const Iv zb = slot_rd(I.d * 4);
         switch (I.op) {
         case I_ADD: case I_SUB:
-            contribute(X, I.ak, I.a, ia, false, zb, pa);
-            contribute(X, I.bk, I.b, ib, I.op == I_SUB, zb, pa);
+            contribute(X, I.ak, I.a, ia, false, zb);
+            contribute(X, I.bk, I.b, ib, I.op == I_SUB, zb);
             break;
         case I_MUL: {
             const bool hv = is_reg_kind(I.bk) && I.ak != K_CONST, hu = is_reg_kind(I.ak) && I.bk != K_CONST;
@@ -432,12 +414,12 @@ __device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
             if (I.ak != K_CONST) {
                 if (I.bk == K_VAR) V = var_val<VS, false>(X, I.b);
                 else if (I.bk == K_CONST) V = Iv{I.k, -I.k};
-                contribute(X, I.ak, I.a, ia, false, imul(zb, V), pa);
+                contribute(X, I.ak, I.a, ia, false, imul(zb, V));
             }
             if (I.bk != K_CONST) {
                 if (I.ak == K_VAR) U = var_val<VS, false>(X, I.a);
                 else if (I.ak == K_CONST) U = Iv{I.k, -I.k};
-                contribute(X, I.bk, I.b, ib, false, imul(zb, U), pa);
+                contribute(X, I.bk, I.b, ib, false, imul(zb, U));
             }
             break;
         }
@@ -446,24 +428,24 @@ __device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
             if (I.bk != K_CONST) Z = ld_rec(X, --rp);
             const Iv R = ld_rec(X, --rp);
             const Iv T = imul(zb, R);
-            contribute(X, I.ak, I.a, ia, false, T, pa);
-            if (I.bk != K_CONST) contribute(X, I.bk, I.b, ib, true, imul(T, Z), pa);
+            contribute(X, I.ak, I.a, ia, false, T);
+            if (I.bk != K_CONST) contribute(X, I.bk, I.b, ib, true, imul(T, Z));
             break;
         }
         case I_SQR: case I_SQRT: case I_EXP: case I_LOG:
             if (I.ak != K_CONST) {
                 const Iv R = ld_rec(X, --rp);
-                contribute(X, I.ak, I.a, ia, false, imul(zb, R), pa);
+                contribute(X, I.ak, I.a, ia, false, imul(zb, R));
             }
             break;
         case I_ADDK: case I_KSUB: case I_LOAD:
-            contribute(X, I.ak, I.a, ia, I.op == I_KSUB, zb, pa);
+            contribute(X, I.ak, I.a, ia, I.op == I_KSUB, zb);
             break;
         case I_MULK: case I_MULKN:
-            contribute(X, I.ak, I.a, ia, false, imulk(I.op == I_MULKN ? ineg(zb) : zb, I.k), pa);
+            contribute(X, I.ak, I.a, ia, false, imulk(I.op == I_MULKN ? ineg(zb) : zb, I.k));
             break;
         default:     // I_DIVK, I_DIVKN
-            contribute(X, I.ak, I.a, ia, false, imul_pos(I.op == I_DIVKN ? ineg(zb) : zb, aux_rec(X, I.b)), pa);
+            contribute(X, I.ak, I.a, ia, false, imul_pos(I.op == I_DIVKN ? ineg(zb) : zb, aux_rec(X, I.b)));
             break;
         }
     }
@@ -1144,7 +1126,10 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         const uint4 *src = reinterpret_cast<const uint4 *>(K->P.prog);
         for (int i = tid; i < nr; i += BLK) lprog[i] = src[i];
         uint8_t *p = smem + (size_t)nr * 16;
-        const bool g_lds = K->P.gacc == nullptr;
+        // gradient accumulators exist only for the reverse-mode entry points (the
+        // host sizes the LDS the same way: programs, accumulators, spill slots)
+        constexpr bool REVOP = OP == PT_VJP || OP == PT_GRAD_REV;
+        const bool g_lds = REVOP && K->P.gacc == nullptr;
         X.G = g_lds ? reinterpret_cast<double2 *>(p) + tid : K->P.gacc + (int64_t)blockIdx.x * BLK + tid;
         X.gstride = g_lds ? BLK : (int64_t)gridDim.x * BLK;
         if (g_lds) p += (size_t)n * BLK * 16;

@@ -144,8 +144,9 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             const mvf_node &nd = nodes[j];
             return (nd.a == i ? 1 : 0) + (is_binary(nd.op) && nd.b == i ? 1 : 0);
         };
-        // linear scan over a pool of slots (lowest free id first)
-        std::vector<uint8_t> busy;
+        // linear scan over a pool of slots (lowest free id first); slot 0 is reserved
+        // for results consumed only by the next instruction
+        std::vector<uint8_t> busy(1, 1);
         auto take = [&]() {
             for (size_t s = 0; s < busy.size(); ++s)
                 if (!busy[s]) { busy[s] = 1; return (int32_t)s; }
@@ -156,7 +157,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             const mvf_node &nd = nodes[node];
             if (nd.op == MVF_VAR) { *kind = K_VAR; *idx = (uint32_t)nd.a; }
             else if (nd.op == MVF_CONST) { *kind = K_CONST; *idx = 0; *k = consts[nd.a]; }
-            else if (in_regs[node]) { *kind = K_PREV; *idx = 0; }
+            else if (in_regs[node]) { *kind = K_SLOT; *idx = 0; }
             else { *kind = K_SLOT; *idx = (uint32_t)slot_of[node]; }
         };
         for (size_t p = 0; p < order.size(); ++p) {
@@ -170,7 +171,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
                 // materialise operand a: a load whose only consumer is this instruction
                 C.instr.push_back(make_instr(I_LOAD, K_CONST, 0, K_SLOT, 0, 0, consts[nodes[nd.a].a]));
                 C.instr.back().w0 |= W0_NOWRITE;
-                ak = K_PREV; a = 0;
+                ak = K_SLOT; a = 0;
                 init |= 1u;
             } else {
                 operand(nd.a, &ak, &a, &ka);
