@@ -30,9 +30,11 @@
 #ifndef MVF_H
 #define MVF_H
 
+#ifndef __HIPCC_RTC__   /* the library's run-time-compiled kernels read the constants only */
 #include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
+#endif
 
 #ifdef __cplusplus
 extern "C" {
@@ -133,7 +135,15 @@ typedef struct {
                                  over centres whose inequality enclosures are all <= 0 (no
                                  equality roots, MVF modes only), else +inf (Sec. 3.1, the
                                  feasibility check; the centres are rigorously feasible points) */
+    int32_t engine;           /* MVF_ENGINE_*: which kernel runs forward-mode and NIE calls */
 } mvf_bound_args;
+
+/* Kernel choice of mvf_bound for forward-mode (and NIE) calls: AUTO runs the
+ * tape's specialised kernel when mvf_tape_specialize has built one, else the
+ * interpreter; INTERP always the interpreter; SPEC the specialised kernel, or
+ * MVF_EINVAL when there is none.  Reverse-mode calls always interpret.  Both
+ * kernels give the same bits. */
+enum { MVF_ENGINE_AUTO = 0, MVF_ENGINE_INTERP = 1, MVF_ENGINE_SPEC = 2 };
 
 /*
  * Subdomain k (0 <= k < S = prod s_i) has indices j_i = (k / prod_{l<i} s_l) mod s_i
@@ -153,6 +163,43 @@ int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mod
  * a tape whose live set leaves no room for tangent components.
  */
 int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
+
+/* ---- specialised forward kernels ------------------------------------
+ * The interpreter kernels evaluate the DAG node by node (the single-kernel
+ * evaluation of Sec. 3.2), decoding every instruction at run time.
+ * mvf_tape_specialize generates straight-line device code of the tape's root
+ * programs instead (per root: the point pass at the centre, the NIE value
+ * pass, and tangent passes of `chunk` gradient components; the MVF combine of
+ * Sec. 2.2 and the Step 3 reduction as in the interpreter), compiles it at
+ * run time with hiprtc for the current device and keeps the loaded module in
+ * the tape.  Each operation is the one the interpreter performs, in the same
+ * order, so the bounds are bitwise identical; no instruction is decoded or
+ * dispatched at run time.  Compilation takes seconds to a minute,
+ * about linear in the generated size (code_units = sum over roots of program
+ * length x passes); MVF_ELIMIT above max_code.  With use_cache the code
+ * object is kept under $MVF_SPEC_CACHE (default ~/.cache/mvf_spec; "off"
+ * disables) keyed by a hash of the source, options and compiler version.
+ * Not thread-safe against concurrent calls on the same tape.
+ */
+typedef struct {
+    int32_t chunk;            /* tangent components per pass, 1..n; 0 = library choice */
+    int32_t waves;            /* waves per SIMD the kernel is compiled for, 1..4; 0 = 2 */
+    int64_t max_code;         /* size limit in instruction-passes; 0 = default (6000) */
+    int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache */
+} mvf_spec_options;
+typedef struct {
+    int32_t chunk, waves;
+    int64_t code_units;       /* instruction-passes generated */
+    int64_t code_bytes;       /* size of the code object */
+    double seconds;           /* generation + compilation (or cache read) */
+    int32_t from_cache;
+} mvf_spec_info;
+int mvf_tape_specialize(mvf_tape *tape, const mvf_spec_options *opt, mvf_spec_info *info);
+/* Generate and compile for gfx950 without a device or a tape handle (no
+ * cache): a check that a tape specialises, and what it costs. */
+int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
+                   int32_t n_vars, const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt,
+                   mvf_spec_info *info);
 
 /* ---- tuning ----------------------------------------------------------- */
 typedef struct mvf_tuning {

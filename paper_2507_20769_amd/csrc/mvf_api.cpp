@@ -13,6 +13,7 @@
 #include "mvf.h"
 #include "mvf_internal.h"
 #include "mvf_kernels.h"
+#include "mvf_spec_internal.h"
 
 using namespace mvf;
 
@@ -22,6 +23,9 @@ struct mvf_tape {
     int device = 0;
     int n_cu = 256;
     uint32_t ineq_mask = 0, eq_mask = 0;   // constraint roots (mvf_tape_set_root_kinds)
+    hipModule_t spec_mod = nullptr;         // specialised forward kernel (mvf_tape_specialize)
+    hipFunction_t spec_fn = nullptr;
+    mvf_spec_info spec_info{};
 };
 
 struct mvf_batch_graph {
@@ -422,6 +426,7 @@ int mvf_tape_stats_get(const mvf_tape *t, mvf_tape_stats *stats) {
 
 int mvf_tape_destroy(mvf_tape *t) {
     if (!t) return MVF_OK;
+    if (t->spec_mod) hipModuleUnload(t->spec_mod);
     if (t->d_prog) hipFree(t->d_prog);
     delete t;
     return MVF_OK;
@@ -446,6 +451,7 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     if (!a->box || !a->reduced || !a->workspace) return set_err(MVF_EINVAL, "box, reduced and workspace are required");
     if (a->mode < MVF_MODE_NIE || a->mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
     if (a->grad < MVF_GRAD_FWD || a->grad > MVF_GRAD_AUTO) return set_err(MVF_EINVAL, "bad grad");
+    if (a->engine < MVF_ENGINE_AUTO || a->engine > MVF_ENGINE_SPEC) return set_err(MVF_EINVAL, "bad engine");
     int64_t S;
     int tt;
     int rc = check_splits(t, a->splits, &S, &tt);
@@ -454,11 +460,16 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     int chunk;
     rc = resolve_grad(t, a->mode, a->grad, a->tuning, &rev, &chunk);
     if (rc != MVF_OK) return rc;
+    if (a->engine == MVF_ENGINE_SPEC && (rev || !t->spec_fn))
+        return set_err(MVF_EINVAL, rev ? "the specialised kernel is forward mode only"
+                                       : "no specialised kernel: call mvf_tape_specialize first");
+    const bool spec = !rev && t->spec_fn && a->engine != MVF_ENGINE_INTERP;
     const int grid = single_grid(t, S, rev);
     const SingleLayout L = single_layout(t, grid, rev, tt);
     if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
-    const size_t lds = lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
+    const size_t lds = spec ? spec_lds_bytes(tt, m)
+                            : lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
 
     const TapeArgs T = tape_args(t, a->mode, chunk);
@@ -483,8 +494,81 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     B.extra = a->extra;
     B.rec = reinterpret_cast<double2 *>(w + L.rec);
     B.gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
+    if (spec) {
+        BoundKArgs K{T, B};
+        void *params[] = {&K};
+        hipError_t e = hipModuleLaunchKernel(t->spec_fn, grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr);
+        if (e != hipSuccess) return hip_err(e, "hipModuleLaunchKernel (specialised kernel)");
+        e = launch_finish(B, grid, m, stream);
+        if (e != hipSuccess) return hip_err(e, "finish kernel");
+        return MVF_OK;
+    }
     hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
     if (e != hipSuccess) return hip_err(e, "launch_bound");
+    return MVF_OK;
+}
+
+int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info *info) {
+    if (!t) return set_err(MVF_EINVAL, "null tape");
+    if (opt && (opt->waves < 0 || opt->waves > 4)) return set_err(MVF_EINVAL, "waves out of range [0, 4]");
+    int chunk;
+    int64_t units;
+    int rc = spec_plan(t->C, opt, &chunk, &units);
+    if (rc != MVF_OK) return rc;
+    const int waves = opt && opt->waves > 0 ? opt->waves : 2;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, t->device));
+    std::vector<char> code;
+    mvf_spec_info in{};
+    bool cached = false;
+    const auto t0 = std::chrono::steady_clock::now();
+    rc = spec_compile(spec_source(t->C, chunk, waves), prop.gcnArchName, opt && opt->use_cache, code, &cached,
+                      &in.seconds);
+    if (rc != MVF_OK) return rc;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    HIP_TRY(hipModuleLoadData(&mod, code.data()));
+    hipError_t e = hipModuleGetFunction(&fn, mod, "mvf_spec_bound");
+    if (e != hipSuccess) {
+        hipModuleUnload(mod);
+        return hip_err(e, "hipModuleGetFunction");
+    }
+    if (t->spec_mod) hipModuleUnload(t->spec_mod);
+    t->spec_mod = mod;
+    t->spec_fn = fn;
+    in.chunk = chunk;
+    in.waves = waves;
+    in.code_units = units;
+    in.code_bytes = (int64_t)code.size();
+    in.from_cache = cached ? 1 : 0;
+    in.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    t->spec_info = in;
+    if (info) *info = in;
+    return MVF_OK;
+}
+
+int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                   const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt, mvf_spec_info *info) {
+    if (opt && (opt->waves < 0 || opt->waves > 4)) return set_err(MVF_EINVAL, "waves out of range [0, 4]");
+    Compiled C;
+    std::string err;
+    int rc = compile_tape(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, &C, &err);
+    if (rc != MVF_OK) return set_err(rc, err);
+    int chunk;
+    int64_t units;
+    rc = spec_plan(C, opt, &chunk, &units);
+    if (rc != MVF_OK) return rc;
+    const int waves = opt && opt->waves > 0 ? opt->waves : 2;
+    std::vector<char> code;
+    bool cached = false;
+    mvf_spec_info in{};
+    rc = spec_compile(spec_source(C, chunk, waves), "gfx950", false, code, &cached, &in.seconds);
+    if (rc != MVF_OK) return rc;
+    in.chunk = chunk;
+    in.waves = waves;
+    in.code_units = units;
+    in.code_bytes = (int64_t)code.size();
+    if (info) *info = in;
     return MVF_OK;
 }
 

@@ -21,10 +21,11 @@
 // below the slot file; the build verifies the ISA).  A slot is read or written
 // with s_set_gpr_idx_on (index in M0) and v_mov_b64.
 #pragma once
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
-#include <stdint.h>
+#endif
 
-#include "mvf_internal.h"
+#include "mvf_isa.h"
 
 namespace mvf {
 namespace dev {

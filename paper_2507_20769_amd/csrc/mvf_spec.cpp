@@ -1,0 +1,442 @@
+// mvf_spec.cpp -- specialised forward-mode bounding kernels: generation of
+// straight-line device code from a tape's compiled root programs, run-time
+// compilation with hiprtc, an on-disk code-object cache, and the launch.
+//
+// What the generated kernel computes is exactly what the interpreter kernel
+// computes (Sec. 3.1 Steps 1-3 with the mean value form of Sec. 2.2 and the
+// tangent-mode interval gradient of Sec. 3.2): per root a point pass at the
+// centre, tangent passes over the subdomain a chunk of gradient components at
+// a time, MVF = [f(c)] + sum_i G_i (X_i - c_i) intersected with the NIE.  The
+// generator walks the same instructions (with their constant-operand forms and
+// slot-0 forwarding) and emits, per instruction, the calls the interpreter
+// makes for that opcode and operand kinds; slots become variables.  Only the
+// decode, the dispatch and the slot-file moves disappear.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <chrono>
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <sys/stat.h>
+#include <unistd.h>
+#include <vector>
+
+#include "mvf.h"
+#include "mvf_internal.h"
+#include "mvf_kernels.h"
+#include "mvf_spec_internal.h"
+
+namespace mvf {
+namespace {
+
+// the device headers the generated source includes (text embedded at build time)
+#include "mvf_spec_headers.inc"
+
+constexpr int64_t DEFAULT_MAX_CODE = 6000;      // instruction-passes (compile time grows about linearly)
+constexpr int SEGMENT = 32;                      // instructions per guarded block
+
+struct Dec {
+    uint32_t op, ak, bk, a, b, d;
+    double k;
+};
+
+Dec decode(const Instr &I) {
+    Dec D;
+    D.op = I.w0 & 31u;
+    D.ak = (I.w0 >> 5) & 3u;
+    D.bk = (I.w0 >> 7) & 3u;
+    D.a = I.w0 >> 16;
+    D.b = I.w1 & 0xffffu;
+    D.d = I.w1 >> 16;
+    D.k = I.k;
+    return D;
+}
+
+std::string lit(double x) {               // exact double literal
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%a", x);
+    return buf;
+}
+
+// One pass over one root program.  C == 0: values only, variables at the
+// centre (point) or over the subdomain; C > 0: values and the tangent
+// components [c0, c0 + C).
+class PassWriter {
+  public:
+    PassWriter(const Compiled &Cp, int root, int C, int c0, bool point)
+        : P(Cp), r(root), C(C), c0(c0), point(point) {}
+
+    // body lines (declarations first, then guarded blocks) and the names of
+    // the result's value and components
+    void emit(std::vector<std::string> &decl, std::vector<std::string> &body, std::string &val,
+              std::vector<std::string> &tan) {
+        const RootProg &rp = P.roots[r];
+        slot_val.assign(std::max(rp.n_slots, 1) + 1, "");
+        slot_tan.assign(slot_val.size(), std::vector<std::string>());
+        for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) instr(pc, decl, body);
+        const int rs = rp.result_slot;
+        val = slot_val.at(rs);
+        tan = slot_tan.at(rs);
+    }
+
+  private:
+    const Compiled &P;
+    int r, C, c0;
+    bool point;
+    std::vector<std::string> slot_val;
+    std::vector<std::vector<std::string>> slot_tan;
+
+    void ensure(size_t s) {
+        if (s >= slot_val.size()) {
+            slot_val.resize(s + 1);
+            slot_tan.resize(s + 1);
+        }
+    }
+
+    // operand: value expression; components (dense), or the hit component of
+    // a variable (-1 otherwise)
+    void fetch(uint32_t kind, uint32_t a, double k, std::string &v, std::vector<std::string> &t, bool &dense,
+               int &hit) {
+        dense = false;
+        hit = -1;
+        t.clear();
+        if (kind == K_SLOT) {
+            ensure(a);
+            v = slot_val[a];
+            t = slot_tan[a];
+            dense = true;
+        } else if (kind == K_VAR) {
+            v = std::string(point ? "spec_c(L, " : "spec_x(L, ") + std::to_string(a) + ")";
+            const int h = (int)a - c0;
+            hit = h >= 0 && h < C ? h : -1;
+        } else {
+            v = "Iv{" + lit(k) + ", " + lit(-k) + "}";
+        }
+    }
+
+    void instr(int pc, std::vector<std::string> &decl, std::vector<std::string> &body) {
+        const Dec I = decode(P.instr[pc]);
+        std::string U, V;
+        std::vector<std::string> A, B;
+        bool ad = false, bd = false;
+        int ha = -1, hb = -1;
+        fetch(I.ak, I.a, I.k, U, A, ad, ha);
+        if (I.op <= I_DIV) fetch(I.bk, I.b, I.k, V, B, bd, hb);
+        const std::string z = "v" + std::to_string(pc);
+        std::string s;                                   // the statements of this instruction
+        std::vector<std::string> Z(C, "kZero");
+        auto at_hit = [&](int h, const std::string &fz) {   // fz(x) with x = current component
+            if (h < 0) return;
+            std::string e = fz;
+            for (size_t p; (p = e.find("@")) != std::string::npos;) e.replace(p, 1, Z[h]);
+            Z[h] = e;
+        };
+        const std::string k = lit(I.k);
+        switch (I.op) {
+        case I_ADD:
+        case I_SUB: {
+            const bool add = I.op == I_ADD;
+            s += z + " = " + (add ? "iadd(" : "isub(") + U + ", " + V + ");";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
+            if (bd) for (int t = 0; t < C; ++t) Z[t] = std::string(add ? "iadd(" : "isub(") + Z[t] + ", " + B[t] + ")";
+            at_hit(ha, "iadd(@, kOne)");
+            at_hit(hb, add ? "iadd(@, kOne)" : "isub(@, kOne)");
+            break;
+        }
+        case I_MUL:
+            s += z + " = imul(" + U + ", " + V + ");";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul(" + V + ", " + A[t] + ")";
+            if (bd) for (int t = 0; t < C; ++t) Z[t] = "iadd(" + Z[t] + ", imul(" + U + ", " + B[t] + "))";
+            at_hit(ha, "iadd(@, " + V + ")");
+            at_hit(hb, "iadd(@, " + U + ")");
+            break;
+        case I_DIV: {
+            const std::string tv = "b" + std::to_string(pc);
+            decl.push_back("Iv " + tv + ";");
+            s += tv + " = " + V + "; bad |= (" + tv + ".lo <= 0.0 && " + tv + ".nh <= 0.0) ? 1u : 0u; ";
+            s += z + " = idiv(" + U + ", " + tv + ");";
+            if (C > 0) {
+                const std::string R = "r" + std::to_string(pc);
+                decl.push_back("Iv " + R + ";");
+                s += " " + R + " = irecip(" + tv + ");";
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
+                if (bd) for (int t = 0; t < C; ++t) Z[t] = "isub(" + Z[t] + ", imul(" + z + ", " + B[t] + "))";
+                at_hit(ha, "iadd(@, kOne)");
+                at_hit(hb, "isub(@, " + z + ")");
+                if (ad || bd || ha >= 0 || hb >= 0)
+                    for (int t = 0; t < C; ++t) Z[t] = "imul(" + Z[t] + ", " + R + ")";
+            }
+            break;
+        }
+        case I_SQR:
+        case I_SQRT:
+        case I_EXP:
+        case I_LOG: {
+            const std::string tu = "u" + std::to_string(pc), D = "q" + std::to_string(pc);
+            decl.push_back("Iv " + tu + ";");
+            s += tu + " = " + U + "; ";
+            std::string dexpr;
+            if (I.op == I_SQR) {
+                s += z + " = isqr(" + tu + ");";
+                dexpr = "itwice(" + tu + ")";
+            } else if (I.op == I_SQRT) {
+                s += "bad |= " + tu + ".lo < 0.0 ? 1u : 0u; " + z + " = isqrt(" + tu + ");";
+                dexpr = "isqrt_deriv(" + z + ")";
+            } else if (I.op == I_EXP) {
+                s += z + " = iexp(" + tu + ");";
+                dexpr = z;
+            } else {
+                s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; " + z + " = ilog(" + tu + ");";
+                dexpr = "irecip(" + tu + ")";
+            }
+            if (C > 0) {
+                decl.push_back("Iv " + D + ";");
+                s += " " + D + " = " + dexpr + ";";
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul(" + D + ", " + A[t] + ")";
+                if (ha >= 0) Z[ha] = D;
+            }
+            break;
+        }
+        case I_ADDK:
+        case I_KSUB:
+        case I_LOAD: {
+            const bool ks = I.op == I_KSUB;
+            const std::string tu = "u" + std::to_string(pc);
+            decl.push_back("Iv " + tu + ";");
+            s += tu + " = " + U + "; ";
+            if (I.op == I_ADDK) s += z + " = Iv{fadd(" + tu + ".lo, " + k + "), fsub(" + tu + ".nh, " + k + ")};";
+            else if (ks) s += z + " = Iv{fadd(" + k + ", " + tu + ".nh), fsub(" + tu + ".lo, " + k + ")};";
+            else s += z + " = " + tu + ";";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = ks ? "ineg(" + A[t] + ")" : A[t];
+            if (ha >= 0) Z[ha] = ks ? "ineg(kOne)" : "kOne";
+            break;
+        }
+        case I_MULK:
+        case I_MULKN: {
+            const bool ng = I.op == I_MULKN;
+            auto sg = [&](const std::string &x) { return ng ? "ineg(" + x + ")" : x; };
+            s += z + " = imulk(" + sg(U) + ", " + k + ");";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = "imulk(" + sg(A[t]) + ", " + k + ")";
+            if (ha >= 0) Z[ha] = "imulk(" + sg("kOne") + ", " + k + ")";
+            break;
+        }
+        default: {   // I_DIVK, I_DIVKN: operand b indexes the enclosure of 1/k
+            const bool ng = I.op == I_DIVKN;
+            auto sg = [&](const std::string &x) { return ng ? "ineg(" + x + ")" : x; };
+            s += z + " = idivk(" + sg(U) + ", " + k + ");";
+            if (C > 0) {
+                const Instr &aux = P.instr.at(I.b);
+                uint64_t bits = (uint64_t)aux.w1 << 32 | aux.w0;
+                double rlo;
+                std::memcpy(&rlo, &bits, 8);
+                const std::string R = "Iv{" + lit(rlo) + ", " + lit(aux.k) + "}";
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul_pos(" + sg(A[t]) + ", " + R + ")";
+                if (ha >= 0) Z[ha] = "imul_pos(" + sg("kOne") + ", " + R + ")";
+            }
+            break;
+        }
+        }
+        decl.push_back("Iv " + z + ";");
+        std::vector<std::string> tn(C);
+        for (int t = 0; t < C; ++t) {
+            tn[t] = "g" + std::to_string(pc) + "_" + std::to_string(t);
+            decl.push_back("Iv " + tn[t] + ";");
+            s += " " + tn[t] + " = " + Z[t] + ";";
+        }
+        body.push_back(s);
+        ensure(I.d);
+        slot_val[I.d] = z;
+        slot_tan[I.d] = tn;
+    }
+};
+
+// a pass as a function: C == 0 returns the value; C > 0 also writes G[0..C)
+void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool point, const std::string &name) {
+    std::vector<std::string> decl, body, tan;
+    std::string val;
+    PassWriter(P, r, C, c0, point).emit(decl, body, val, tan);
+    out += "__device__ __forceinline__ Iv " + name + "(const SpecLane &L, bool go, uint32_t &bad";
+    if (C > 0) out += ", Iv (&G)[" + std::to_string(C) + "]";
+    out += ") {\n";
+    for (const auto &d : decl) out += "    " + d + "\n";
+    for (size_t i = 0; i < body.size(); i += SEGMENT) {
+        out += "    if (go) {\n";
+        for (size_t j = i; j < std::min(body.size(), i + SEGMENT); ++j) out += "        " + body[j] + "\n";
+        out += "    }\n";
+    }
+    for (int t = 0; t < C; ++t) out += "    G[" + std::to_string(t) + "] = " + tan[t] + ";\n";
+    out += "    return " + val + ";\n}\n";
+}
+
+}  // namespace
+
+int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_t *units) {
+    const int n = P.n_vars;
+    int c = opt && opt->chunk > 0 ? opt->chunk : 0;
+    if (c == 0) {
+        const int passes = (n + 2) / 3;
+        c = (n + passes - 1) / passes;
+    }
+    if (c < 1 || c > n) return set_error(MVF_EINVAL, "chunk out of range [1, n]");
+    const int passes = (n + c - 1) / c;
+    int64_t u = 0;
+    for (const auto &rp : P.roots) u += (int64_t)rp.len * (2 + passes);
+    const int64_t cap = opt && opt->max_code > 0 ? opt->max_code : DEFAULT_MAX_CODE;
+    *chunk = c;
+    *units = u;
+    if (u > cap)
+        return set_error(MVF_ELIMIT, "tape too large to specialise: " + std::to_string(u) + " instruction-passes > " +
+                                         std::to_string(cap));
+    return MVF_OK;
+}
+
+std::string spec_source(const Compiled &P, int chunk, int waves) {
+    const int n = P.n_vars, m = (int)P.roots.size();
+    std::string s;
+    s += "// generated: specialised bounding kernel, " + std::to_string(n) + " variables, " + std::to_string(m) +
+         " roots, " + std::to_string(chunk) + " tangent components per pass\n";
+    s += "#define MVF_SPEC_WAVES " + std::to_string(waves) + "\n";
+    s += "#include \"mvf_spec.h\"\nnamespace mvf {\nnamespace dev {\nnamespace spec {\n";
+    s += "constexpr int N_VARS = " + std::to_string(n) + ", N_ROOTS = " + std::to_string(m) + ";\n";
+    for (int r = 0; r < m; ++r) {
+        write_pass(s, P, r, 0, 0, true, "point_" + std::to_string(r));
+        write_pass(s, P, r, 0, 0, false, "value_" + std::to_string(r));
+        for (int c0 = 0; c0 < n; c0 += chunk)
+            write_pass(s, P, r, std::min(chunk, n - c0), c0, false,
+                       "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
+    }
+    // every root in turn, as the interpreter's bound_lane with tangent passes
+    s += "__device__ __forceinline__ uint32_t lane_bounds(const SpecLane &L, int mode, bool go, const LaneOut &o, "
+         "FeasTrack &F) {\n    uint32_t bad = 0;\n";
+    for (int r = 0; r < m; ++r) {
+        const std::string R = std::to_string(r);
+        s += "    {\n        Iv B, FC = kZero;\n";
+        s += "        if (mode == MVF_MODE_NIE) {\n            B = value_" + R + "(L, go, bad);\n        } else {\n";
+        s += "            FC = point_" + R + "(L, go, bad);\n            Iv acc = FC, nie = kZero;\n";
+        for (int c0 = 0; c0 < n; c0 += chunk) {
+            const int c = std::min(chunk, n - c0);
+            s += "            {\n                Iv G[" + std::to_string(c) + "];\n";
+            s += "                const Iv v = tangent_" + R + "_" + std::to_string(c0) + "(L, go, bad, G);\n";
+            if (c0 == 0) s += "                nie = v;\n";
+            for (int t = 0; t < c; ++t)
+                s += "                acc = iadd(acc, imul(G[" + std::to_string(t) + "], spec_dx(L, " +
+                     std::to_string(c0 + t) + ")));\n";
+            s += "            }\n";
+        }
+        s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";
+        s += "        }\n        if (B.lo != B.lo || B.nh != B.nh) bad = 1;\n";
+        s += "        reduce_root(" + R + ", N_ROOTS, B, o);\n";
+        s += "        track_root(F, " + R + ", B, FC, mode != MVF_MODE_NIE, o);\n    }\n";
+    }
+    s += "    return bad;\n}\n}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n";
+    s += "#include \"mvf_spec_kernel.h\"\n";
+    return s;
+}
+
+namespace {
+
+uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
+    for (unsigned char c : s) {
+        h ^= c;
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+std::string cache_dir() {
+    const char *e = std::getenv("MVF_SPEC_CACHE");
+    if (e && *e) return std::string(e) == "off" ? "" : std::string(e);
+    const char *home = std::getenv("HOME");
+    return home && *home ? std::string(home) + "/.cache/mvf_spec" : "";
+}
+
+void mkdirs(const std::string &d) {
+    for (size_t p = 1; p <= d.size(); ++p)
+        if (p == d.size() || d[p] == '/') mkdir(d.substr(0, p).c_str(), 0755);
+}
+
+bool read_file(const std::string &path, std::vector<char> &out) {
+    FILE *f = std::fopen(path.c_str(), "rb");
+    if (!f) return false;
+    std::fseek(f, 0, SEEK_END);
+    const long sz = std::ftell(f);
+    std::fseek(f, 0, SEEK_SET);
+    out.resize(sz > 0 ? (size_t)sz : 0);
+    const bool ok = sz > 0 && std::fread(out.data(), 1, out.size(), f) == out.size();
+    std::fclose(f);
+    return ok;
+}
+
+void write_file_atomic(const std::string &path, const std::vector<char> &data) {
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    const bool ok = std::fwrite(data.data(), 1, data.size(), f) == data.size();
+    std::fclose(f);
+    if (ok) std::rename(tmp.c_str(), path.c_str());
+    else std::remove(tmp.c_str());
+}
+
+}  // namespace
+
+int spec_compile(const std::string &src, const std::string &arch, bool use_cache, std::vector<char> &code,
+                 bool *from_cache, double *seconds) {
+    const auto t0 = std::chrono::steady_clock::now();
+    *from_cache = false;
+    std::vector<std::string> opts = {"--offload-arch=" + arch, "-O3", "-std=c++17", "-ffp-contract=off",
+                                     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    int ver_major = 0, ver_minor = 0;
+    hiprtcVersion(&ver_major, &ver_minor);
+    std::string key = src;
+    for (const auto &o : opts) key += "\n" + o;
+    for (size_t i = 0; i < k_spec_header_count; ++i) key += k_spec_header_src[i];
+    key += "\nhiprtc " + std::to_string(ver_major) + "." + std::to_string(ver_minor);
+    char hex[17];
+    std::snprintf(hex, sizeof hex, "%016" PRIx64, fnv1a(key));
+    const std::string dir = use_cache ? cache_dir() : "";
+    const std::string path = dir.empty() ? "" : dir + "/mvf_spec_" + hex + ".co";
+    if (!path.empty() && read_file(path, code)) {
+        *from_cache = true;
+        *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return MVF_OK;
+    }
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "mvf_spec.hip", (int)k_spec_header_count, k_spec_header_src,
+                            k_spec_header_name) != HIPRTC_SUCCESS)
+        return set_error(MVF_EHIP, "hiprtcCreateProgram failed");
+    std::vector<const char *> po;
+    for (const auto &o : opts) po.push_back(o.c_str());
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)po.size(), po.data());
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls, '\0');
+        if (ls) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        if (log.size() > 4000) log = log.substr(0, 4000) + "...";
+        return set_error(MVF_EHIP, std::string("hiprtc: ") + hiprtcGetErrorString(rc) + "\n" + log);
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    code.resize(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    if (!path.empty()) {
+        mkdirs(dir);
+        write_file_atomic(path, code);
+    }
+    *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return MVF_OK;
+}
+
+size_t spec_lds_bytes(int tab_total, int m) {
+    size_t b = (size_t)tab_total * 32;
+    b += ((size_t)(BLK / 64) * (2 * m + 5) * 8 + 15) & ~(size_t)15;
+    b += (2 * MVF_MAX_VARS + 8) * 4;
+    return b;
+}
+
+}  // namespace mvf

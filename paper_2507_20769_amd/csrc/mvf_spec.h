@@ -1,0 +1,43 @@
+// mvf_spec.h -- device helpers of the specialised (run-time-compiled) bounding
+// kernel.
+//
+// The interpreter kernels decode every instruction of a root program at run
+// time and move operands through a GPR-indexed slot file.  A specialised
+// kernel is generated per tape instead: the same root programs (Sec. 3.2, the
+// DAG evaluated node by node) become straight-line code whose operands are
+// ordinary variables, so the compiler allocates registers and no instruction
+// is decoded or dispatched.  Every operation calls the same interval
+// primitives in the same order as the interpreter, so both produce the same
+// bits.  The generated functions (namespace spec) are compiled between this
+// header and mvf_spec_kernel.h.
+#pragma once
+#include "mvf_lane.h"
+
+namespace mvf {
+namespace dev {
+
+// A lane's subdomain: the breakpoint table in LDS and, per variable, the
+// index of the lane's table entry {lo, -hi, c, -c}.
+struct SpecLane {
+    const double4 *tab;
+    int vi[MVF_MAX_VARS];
+};
+
+// variable i over the subdomain, [lo, hi]
+__device__ __forceinline__ Iv spec_x(const SpecLane &L, int i) {
+    const double4 r = L.tab[L.vi[i]];
+    return Iv{r.x, r.y};
+}
+// variable i at the subdomain's centre, [c, c]
+__device__ __forceinline__ Iv spec_c(const SpecLane &L, int i) {
+    const double4 r = L.tab[L.vi[i]];
+    return Iv{r.z, r.w};
+}
+// X_i - c_i, the factor of G_i in the mean value form
+__device__ __forceinline__ Iv spec_dx(const SpecLane &L, int i) {
+    const double4 r = L.tab[L.vi[i]];
+    return Iv{fadd(r.x, r.w), fadd(r.y, r.z)};
+}
+
+}  // namespace dev
+}  // namespace mvf

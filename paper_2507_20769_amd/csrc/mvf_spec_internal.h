@@ -1,0 +1,25 @@
+// mvf_spec_internal.h -- host interface of the specialised-kernel generator.
+#pragma once
+#include <string>
+#include <vector>
+
+#include "mvf.h"
+#include "mvf_internal.h"
+
+namespace mvf {
+
+// Tangent components per pass and generated size (instruction-passes: root
+// program lengths times passes per root); MVF_ELIMIT above the size limit.
+int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_t *units);
+
+// The generated device source (compiled with the embedded device headers).
+std::string spec_source(const Compiled &P, int chunk, int waves);
+
+// hiprtc compilation for `arch` (or the on-disk cache's copy).
+int spec_compile(const std::string &src, const std::string &arch, bool use_cache, std::vector<char> &code,
+                 bool *from_cache, double *seconds);
+
+// dynamic LDS of the specialised kernel
+size_t spec_lds_bytes(int tab_total, int m);
+
+}  // namespace mvf

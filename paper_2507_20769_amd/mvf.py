@@ -74,7 +74,24 @@ class BoundArgs(ctypes.Structure):
     _fields_ = [("box", ctypes.c_void_p), ("splits", ctypes.c_void_p), ("mode", ctypes.c_int32),
                 ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
                 ("per_sub", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p), ("extra", ctypes.c_void_p)]
+                ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p), ("extra", ctypes.c_void_p),
+                ("engine", ctypes.c_int32)]
+
+
+class SpecOptions(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("max_code", ctypes.c_int64),
+                ("use_cache", ctypes.c_int32)]
+
+
+class SpecInfo(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("code_units", ctypes.c_int64),
+                ("code_bytes", ctypes.c_int64), ("seconds", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+MVF_ENGINE = {"auto": 0, "interp": 1, "spec": 2}
 
 
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
@@ -82,7 +99,7 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_create", "mvf_batch_graph_staging", "mvf_batch_graph_launch", "mvf_batch_graph_result",
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
-           "mvf_tape_set_root_kinds", "mvf_bnb_solve"]
+           "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check"]
 
 
 def lib():
@@ -155,6 +172,10 @@ def lib():
             L.mvf_vjp_points.argtypes = [P, i64, P, P, P, P, P, ctypes.c_size_t, P]
             L.mvf_gradient_boxes.restype = ctypes.c_int
             L.mvf_gradient_boxes.argtypes = [P, i64, P, i32, i32, P, P, P, ctypes.c_size_t, P]
+            L.mvf_tape_specialize.restype = ctypes.c_int
+            L.mvf_tape_specialize.argtypes = [P, ctypes.POINTER(SpecOptions), ctypes.POINTER(SpecInfo)]
+            L.mvf_spec_check.restype = ctypes.c_int
+            L.mvf_spec_check.argtypes = tape_args + [ctypes.POINTER(SpecOptions), ctypes.POINTER(SpecInfo)]
             _lib = L
     return _lib
 
@@ -178,6 +199,17 @@ def check(tape) -> TapeStats:
     if rc != 0:
         raise MVFError(rc, "mvf_tape_check")
     return st
+
+
+def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0) -> dict:
+    """Generate and compile the specialised kernel of a tape for gfx950 on the
+    host (no device, no cache); returns the mvf_spec_info fields."""
+    keep, args = _tape_arrays(tape)
+    info = SpecInfo()
+    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0)), ctypes.byref(info))
+    if rc != 0:
+        raise MVFError(rc, "mvf_spec_check")
+    return info.as_dict()
 
 
 def _stream_ptr(stream):
@@ -209,6 +241,16 @@ class Tape:
             raise MVFError(rc, "mvf_tape_set_root_kinds")
         return self
 
+    def specialize(self, chunk: int = 0, waves: int = 0, max_code: int = 0, cache: bool = True) -> dict:
+        """Build the tape's specialised forward kernel (mvf_tape_specialize)."""
+        info = SpecInfo()
+        rc = lib().mvf_tape_specialize(self.handle, ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache))),
+                                       ctypes.byref(info))
+        if rc != 0:
+            raise MVFError(rc, "mvf_tape_specialize")
+        self.spec_info = info.as_dict()
+        return self.spec_info
+
     def stats(self) -> TapeStats:
         st = TapeStats()
         rc = lib().mvf_tape_stats_get(self.handle, ctypes.byref(st))
@@ -233,7 +275,7 @@ class BoundCall:
     so repeated launches only enqueue kernels)."""
 
     def __init__(self, tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str = "fwd",
-                 per_sub: bool = False, flags: bool = False, tuning: "Tuning | None" = None):
+                 per_sub: bool = False, flags: bool = False, tuning: "Tuning | None" = None, engine: str = "auto"):
         import torch
         self.tape = tape
         self.tuning = tuning
@@ -260,7 +302,8 @@ class BoundCall:
                               self.per_sub.data_ptr() if per_sub else None,
                               self.flags.data_ptr() if flags else None,
                               self.workspace.data_ptr(), self.workspace.numel(),
-                              ctypes.addressof(tuning) if tuning is not None else None, self.extra.data_ptr())
+                              ctypes.addressof(tuning) if tuning is not None else None, self.extra.data_ptr(),
+                              MVF_ENGINE[engine])
 
     def launch(self, stream=None):
         rc = lib().mvf_bound(self.tape.handle, ctypes.byref(self.args), _stream_ptr(stream))
@@ -270,13 +313,14 @@ class BoundCall:
 
 
 def bound(tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str = "fwd",
-          per_sub: bool = False, flags: bool = False, stream=None) -> dict:
+          per_sub: bool = False, flags: bool = False, stream=None, engine: str = "auto") -> dict:
     """Bound every subdomain of ``box`` (device float64 [n, 2]).
 
     Returns device tensors: reduced [m, 2] (lo, hi), argmin [1], and when asked
-    per_sub [m, 2, S] and flags [S].  Asynchronous on ``stream``.
+    per_sub [m, 2, S] and flags [S].  Asynchronous on ``stream``.  ``engine``:
+    "auto" (the specialised kernel when the tape has one), "interp" or "spec".
     """
-    call = BoundCall(tape, box, splits, mode, grad, per_sub, flags).launch(stream)
+    call = BoundCall(tape, box, splits, mode, grad, per_sub, flags, engine=engine).launch(stream)
     out = {"reduced": call.reduced, "argmin": call.argmin, "extra": call.extra, "workspace": call.workspace}
     if per_sub:
         out["per_sub"] = call.per_sub

@@ -10,12 +10,12 @@ def has_transcendental(tape) -> bool:
     return bool(np.any((ops == I.EXP) | (ops == I.LOG)))
 
 
-def gpu_bound(tape, box, splits, mode="both", grad="fwd", per_sub=True, flags=True, handle=None):
+def gpu_bound(tape, box, splits, mode="both", grad="fwd", per_sub=True, flags=True, handle=None, engine="auto"):
     import torch
     from paper_2507_20769_amd import mvf
     t = handle if handle is not None else mvf.Tape(tape)
     dbox = torch.tensor(np.asarray(box, dtype=np.float64), device="cuda")
-    out = mvf.bound(t, dbox, splits, mode=mode, grad=grad, per_sub=per_sub, flags=flags)
+    out = mvf.bound(t, dbox, splits, mode=mode, grad=grad, per_sub=per_sub, flags=flags, engine=engine)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items() if k != "workspace"}
     if handle is None:
