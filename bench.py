@@ -4,8 +4,11 @@ Headline step = one call of the whole bounding path on one node box of the
 mid workload (6 variables, a 200-op objective and three 80-op constraints,
 8^6 = 262,144 subdomains) in the plain form: forward (tangent) mode, one
 launch per box -- subdomain generation, point pass, tangent passes, MVF
-intersected with the NIE, min/max reduction with argmin.  Inputs are resident
-in HBM before the timed region.
+intersected with the NIE, min/max reduction with argmin.  The tape is
+specialised first (straight-line kernel compiled at run time; the compile
+time is reported, outside the timed region); --engine interp times the
+interpreter kernel instead, which is also reported among the forms.  Inputs
+are resident in HBM before the timed region.
 
 The same JSON line carries the comparison of the two forms on the batch
 workload (512 B&B-like nodes of [-3,3]^8 with 2^10..2^18 subdomains each,
@@ -39,6 +42,9 @@ sys.path.insert(0, ROOT)
 # published 78.6 TFLOP/s counts an FMA as two operations.
 FP64_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9          # 39.3e12 op/s
 FP64_PUBLISHED_PEAK = 78.6e12
+# HBM bytes per launch of the headline kernel from rocprofv3 counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00,
+# the factors from a 256 MiB copy in the same runs), valid for the kernel and tape they were taken on
+TRAFFIC = {("spec", "aa75c5b416e4faea"): (4504.5 * 2.0 + 5280.0) * 1024}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 
@@ -52,6 +58,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="headline only (used under the profiler)")
     ap.add_argument("--bnb-nodes", type=int, default=1000, help="B&B node limit of the e2e comparison (0: skip)")
+    ap.add_argument("--engine", choices=["spec", "interp"], default="spec",
+                    help="headline kernel: the tape's specialised kernel or the interpreter")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy, the reference for HBM counters")
     return ap.parse_args()
@@ -91,13 +99,25 @@ def time_calls(launch, steps: int, warmup: int, stream) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def forms(seed: int) -> dict:
+def forms(seed: int, headline_engine: str) -> dict:
     import torch
 
     from paper_2507_20769_amd import inputs as I
     from paper_2507_20769_amd import mvf
     out = {}
     stream = torch.cuda.current_stream()
+    # the headline step with the other kernel
+    w = I.mid(seed)
+    h = mvf.Tape(w.tape)
+    other = "interp" if headline_engine == "spec" else "spec"
+    if other == "spec":
+        h.specialize()
+    call = mvf.BoundCall(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both", grad="fwd", engine=other)
+    ms = time_calls(call.launch, 20, 2, stream)
+    out[f"mid_forward_{'specialised' if other == 'spec' else 'interpreter'}"] = {
+        "subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms,
+        "issue_peak_frac": h.stats().ref_ops_fwd * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
+    h.close()
     # reverse mode on mid and on the 32-variable differentiation workload
     for name, steps in (("mid", 20), ("diff", 4)):
         w = getattr(I, name)(seed)
@@ -114,19 +134,26 @@ def forms(seed: int) -> dict:
     st = h.stats()
     total = int(bw.n_sub.sum())
     boxes = torch.tensor(bw.boxes, device="cuda")
-    calls = [mvf.BoundCall(h, boxes[i], bw.splits[i], mode="both", grad="fwd") for i in range(len(bw.boxes))]
-    red_plain = np.empty((len(calls), bw.tape.n_roots, 2))
+    red_plain = np.empty((len(bw.boxes), bw.tape.n_roots, 2))
+    spec_info = h.specialize()
+    t_plain = {}
+    for engine in ("interp", "spec"):
+        calls = [mvf.BoundCall(h, boxes[i], bw.splits[i], mode="both", grad="fwd", engine=engine)
+                 for i in range(len(bw.boxes))]
 
-    def plain():
-        for i, c in enumerate(calls):
-            c.launch(stream)
-            stream.synchronize()                   # a B&B loop needs each node's bound before going on
-    plain()
-    t0 = time.perf_counter()
-    plain()
-    t_plain = time.perf_counter() - t0
-    for i, c in enumerate(calls):
-        red_plain[i] = c.reduced.cpu().numpy()
+        def plain():
+            for c in calls:
+                c.launch(stream)
+                stream.synchronize()               # a B&B loop needs each node's bound before going on
+        plain()
+        t0 = time.perf_counter()
+        plain()
+        t_plain[engine] = time.perf_counter() - t0
+        red = np.stack([c.reduced.cpu().numpy() for c in calls])
+        if engine == "interp":
+            red_plain[:] = red
+        else:
+            same_plain = float(np.mean(red == red_plain))   # the two kernels agree bitwise up to libm
     g = mvf.BatchGraph(h, len(bw.boxes), total, mode="both", grad="rev")
     gs = torch.cuda.Stream()
 
@@ -146,11 +173,16 @@ def forms(seed: int) -> dict:
     scale = np.maximum(1.0, np.abs(red_plain[:, 0, :]).max(axis=1))
     out["batch"] = {
         "nodes": len(bw.boxes), "subdomains": total,
-        "plain_forward_per_node": {"subdomain_bounds_per_s": total / t_plain, "s": t_plain,
-                                   "tangent_chunk": st.tangent_chunk},
+        "plain_forward_per_node": {"subdomain_bounds_per_s": total / t_plain["interp"], "s": t_plain["interp"],
+                                   "tangent_chunk": st.tangent_chunk, "kernel": "interpreter"},
+        "plain_forward_per_node_specialised": {"subdomain_bounds_per_s": total / t_plain["spec"],
+                                               "s": t_plain["spec"], "tangent_chunk": spec_info["chunk"],
+                                               "compile_s": spec_info["seconds"],
+                                               "hull_endpoints_equal_to_interpreter": same_plain},
         "adjoint_batched_graph": {"subdomain_bounds_per_s": total / t_batched, "s": t_batched,
                                   "status_ok": bool((status == 0).all())},
-        "speedup_adjoint_batched_vs_plain": t_plain / t_batched,
+        "speedup_adjoint_batched_vs_plain": t_plain["interp"] / t_batched,
+        "speedup_adjoint_batched_vs_plain_specialised": t_plain["spec"] / t_batched,
         "objective_lb_adjoint_minus_forward": {"tighter_frac": float(np.mean(d > 0)),
                                                "looser_frac": float(np.mean(d < 0)),
                                                "mean_rel": float(np.mean(d / scale))},
@@ -202,8 +234,9 @@ def main():
     w = I.mid(args.seed)
     tape = mvf.Tape(w.tape)
     st = tape.stats()
+    spec = tape.specialize() if args.engine == "spec" else None
     box = torch.tensor(w.box, dtype=torch.float64, device="cuda")
-    call = mvf.BoundCall(tape, box, w.splits, mode="both", grad="fwd")
+    call = mvf.BoundCall(tape, box, w.splits, mode="both", grad="fwd", engine=args.engine)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     ms = time_calls(lambda: call.launch(stream), args.steps, args.warmup, stream)
@@ -229,17 +262,24 @@ def main():
         "config": {"workload": "mid", "form": "plain: forward-mode MVF, one launch per node box",
                    "n_vars": w.tape.n_vars, "tape_ops": w.tape.n_ops(), "roots": w.tape.n_roots,
                    "subdomains": S, "splits": [int(s) for s in w.splits], "seed": args.seed,
-                   "tape_hash": w.tape.digest(), "tangent_chunk": st.tangent_chunk},
+                   "tape_hash": w.tape.digest(), "engine": args.engine,
+                   "tangent_chunk": spec["chunk"] if spec else st.tangent_chunk},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_ISSUE_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_ISSUE_PEAK, "traffic": None,
-                     "kernel": "bound_kernel<2,false> (+ its 1-block finish kernel inside the timed call)",
+                     "unit": "TFLOP/s", "frac": achieved / FP64_ISSUE_PEAK,
+                     "traffic": TRAFFIC.get((args.engine, w.tape.digest())),
+                     "kernel": ("mvf_spec_bound" if spec else f"bound_kernel<{st.tangent_chunk},false>") +
+                               " (+ the 1-block finish kernel inside the timed call)",
                      "ops_per_subdomain": st.ref_ops_fwd,
                      "frac_of_published_78.6": achieved / FP64_PUBLISHED_PEAK},
         "wall_s": wall,
         "objective_lower_bound": float(reduced[0, 0]),
     }
+    if spec:
+        out["specialisation"] = {"compile_s": spec["seconds"], "from_cache": bool(spec["from_cache"]),
+                                 "code_units": spec["code_units"], "code_bytes": spec["code_bytes"],
+                                 "waves_per_simd": spec["waves"]}
     if not args.no_forms:
-        out["forms"] = forms(args.seed)
+        out["forms"] = forms(args.seed, args.engine)
         if args.bnb_nodes > 0:
             out["forms"]["bnb"] = bnb_forms(args.seed, args.bnb_nodes)
     if not args.no_cpu:

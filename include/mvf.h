@@ -178,7 +178,8 @@ int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stre
  * about linear in the generated size (code_units = sum over roots of program
  * length x passes); MVF_ELIMIT above max_code.  With use_cache the code
  * object is kept under $MVF_SPEC_CACHE (default ~/.cache/mvf_spec; "off"
- * disables) keyed by a hash of the source, options and compiler version.
+ * disables) keyed by a hash of the source, options and compiler version;
+ * $MVF_SPEC_DUMP names a file that receives a copy of the generated source.
  * Not thread-safe against concurrent calls on the same tape.
  */
 typedef struct {

@@ -396,6 +396,13 @@ int spec_compile(const std::string &src, const std::string &arch, bool use_cache
     key += "\nhiprtc " + std::to_string(ver_major) + "." + std::to_string(ver_minor);
     char hex[17];
     std::snprintf(hex, sizeof hex, "%016" PRIx64, fnv1a(key));
+    if (const char *dump = std::getenv("MVF_SPEC_DUMP")) {       // a copy of the generated source, for inspection
+        FILE *f = std::fopen(dump, "w");
+        if (f) {
+            std::fwrite(src.data(), 1, src.size(), f);
+            std::fclose(f);
+        }
+    }
     const std::string dir = use_cache ? cache_dir() : "";
     const std::string path = dir.empty() ? "" : dir + "/mvf_spec_" + hex + ".co";
     if (!path.empty() && read_file(path, code)) {
