@@ -9,6 +9,7 @@ refinement, finite differences and high-precision decimal exp/log.
 """
 import decimal
 import math
+import os
 import random
 from fractions import Fraction
 
@@ -17,6 +18,8 @@ import pytest
 
 from oracle import oracle as O
 from paper_2507_20769_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG = O.ADD, O.SUB, O.MUL, O.DIV, O.SQR, O.SQRT, O.EXP, O.LOG
 
@@ -145,13 +148,24 @@ def test_exp_log_padding_encloses_high_precision_values():
 # Step 1: splitting
 # --------------------------------------------------------------------------
 
+def _golden(name):
+    rows = {}
+    for line in open(os.path.join(GOLDEN, name)):
+        line = line.split("#")[0].split()
+        if line:
+            rows.setdefault(line[0], []).append([float(x) for x in line[1:]])
+    return rows
+
+
 def test_uniform_partition_worked_example():
-    # Sec. 3.1.1: X = [-3,1] x [0,2] into four subdomains X_1..X_4
-    box = np.array([[-3.0, 1.0], [0.0, 2.0]])
-    want = [[[-3, -1], [0, 1]], [[-1, 1], [0, 1]], [[-3, -1], [1, 2]], [[-1, 1], [1, 2]]]
-    for k, w in enumerate(want):
-        X, c = O.subdomain(box, np.array([2, 2]), k)
-        assert X.tolist() == w
+    # Sec. 3.1.1: X = [-3,1] x [0,2] into four subdomains X_1..X_4 (tests/golden fixture)
+    g = _golden("uniform_partition_example.txt")
+    box = np.array(g["box"])
+    splits = np.array(g["splits"][0], dtype=np.int32)
+    for row in g["sub"]:
+        k, w = int(row[0]), np.array(row[1:]).reshape(2, 2)
+        X, c = O.subdomain(box, splits, k)
+        assert X.tolist() == w.tolist()
         assert c.tolist() == [0.5 * (w[0][0] + w[0][1]), 0.5 * (w[1][0] + w[1][1])]
 
 
@@ -176,10 +190,13 @@ def test_partition_covers_box_exactly():
 
 def test_adaptive_partition_worked_example():
     # Sec. 3.1.2: five dimensions, 2560 cores -> uniform 4^5 = 1024, adaptive 5^4 * 4 = 2500
-    s, count = O.adaptive_splits(np.ones(5), 2560)
-    assert count == 2500 and sorted(s.tolist()) == [4, 5, 5, 5, 5]
-    s, count = O.adaptive_splits(np.ones(5), 1024)
-    assert count == 1024 and s.tolist() == [4] * 5
+    g = _golden("adaptive_partition_example.txt")
+    n, budget = int(g["n"][0][0]), int(g["budget"][0][0])
+    s, count = O.adaptive_splits(np.ones(n), budget)
+    assert count == int(g["adaptive_count"][0][0]) and sorted(s.tolist()) == g["adaptive_splits_sorted"][0]
+    uc = int(g["uniform_count"][0][0])
+    s, count = O.adaptive_splits(np.ones(n), uc)
+    assert count == uc and s.tolist() == [round(uc ** (1 / n))] * n
     # uniform 8x8 = 64 first, then the relatively wider dimension grows: 8x9, 8x10
     s, count = O.adaptive_splits(np.array([1.0, 4.0]), 80)
     assert count == 80 and s.tolist() == [8, 10]
