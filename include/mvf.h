@@ -208,6 +208,10 @@ typedef struct mvf_tuning {
     int32_t chunk;            /* tangent components per forward pass (1 .. tangent_chunk); 0: default */
     int32_t grid_blocks;      /* persistent workgroups of a batched launch; 0: two per compute unit */
     float best_ms;            /* written by mvf_autotune: time of the chosen configuration */
+    int32_t sub_per_lane;     /* batched launches: subdomains per lane of a work item (a work item is
+                                 256 * sub_per_lane subdomains of one node), 1..16; 0: 1 */
+    int32_t engine;           /* batched forward launches: MVF_ENGINE_* (the specialised kernel needs
+                                 mvf_tape_specialize; reverse mode always interprets) */
 } mvf_tuning;
 
 /*
@@ -242,8 +246,9 @@ int mvf_batch_workspace(const mvf_tape *tape, int32_t max_nodes, int64_t max_sub
 /*
  * Bound every node of a batch in one persistent launch: per node the same
  * result as mvf_bound on that node's box and splits, bit for bit.  The node
- * list lives in device memory; work is split into chunks of 256 subdomains
- * that persistent workgroups take from an atomic counter.  tuning may be NULL.
+ * list lives in device memory; work is split into chunks of 256 *
+ * sub_per_lane subdomains that persistent workgroups take from an atomic
+ * counter.  tuning may be NULL.
  */
 int mvf_bound_batch(const mvf_tape *tape, const mvf_batch_args *args, const mvf_tuning *tuning,
                     hipStream_t stream);
@@ -267,9 +272,13 @@ int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int
 int mvf_batch_graph_destroy(mvf_batch_graph *g);
 
 /*
- * Autotuner: times the batched launch on the given nodes (device arrays)
- * for each gradient mode, tangent chunk and persistent grid size, and
- * returns the fastest configuration.  Allocates temporary device memory.
+ * Autotuner (the batched form's launch configuration): times the batched
+ * launch on the given nodes (device arrays) for each gradient mode and
+ * kernel (interpreter with each tangent chunk, the specialised kernel when
+ * the tape has one, the reverse-mode adjoint), persistent grid size (1, 2, 4
+ * workgroups per CU) and subdomains per lane (1, 2, 4), and returns the
+ * fastest.  The workgroup is fixed at 256 lanes (four waves).  Allocates
+ * temporary device memory.
  */
 int mvf_autotune(const mvf_tape *tape, int32_t n_nodes, const double *boxes, const int32_t *splits,
                  int64_t n_subdomains, int32_t mode, mvf_tuning *out, hipStream_t stream);

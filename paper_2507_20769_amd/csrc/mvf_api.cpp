@@ -23,8 +23,8 @@ struct mvf_tape {
     int device = 0;
     int n_cu = 256;
     uint32_t ineq_mask = 0, eq_mask = 0;   // constraint roots (mvf_tape_set_root_kinds)
-    hipModule_t spec_mod = nullptr;         // specialised forward kernel (mvf_tape_specialize)
-    hipFunction_t spec_fn = nullptr;
+    hipModule_t spec_mod = nullptr;         // specialised forward kernels (mvf_tape_specialize)
+    hipFunction_t spec_fn = nullptr, spec_batch_fn = nullptr;
     mvf_spec_info spec_info{};
 };
 
@@ -160,6 +160,20 @@ int batch_grid(const mvf_tape *t, const mvf_tuning *tu) {
     return 2 * t->n_cu;
 }
 
+int batch_spl(const mvf_tuning *tu) { return tu && tu->sub_per_lane > 0 ? tu->sub_per_lane : 1; }
+
+// the batched forward launch runs the specialised kernel unless told otherwise
+int batch_engine(const mvf_tape *t, const mvf_tuning *tu, bool rev, bool *spec) {
+    const int e = tu ? tu->engine : MVF_ENGINE_AUTO;
+    if (e < MVF_ENGINE_AUTO || e > MVF_ENGINE_SPEC) return set_err(MVF_EINVAL, "bad engine");
+    if (tu && (tu->sub_per_lane < 0 || tu->sub_per_lane > 16)) return set_err(MVF_EINVAL, "sub_per_lane outside [0, 16]");
+    if (e == MVF_ENGINE_SPEC && (rev || !t->spec_batch_fn))
+        return set_err(MVF_EINVAL, rev ? "the specialised kernel is forward mode only"
+                                       : "no specialised kernel: call mvf_tape_specialize first");
+    *spec = !rev && t->spec_batch_fn && e != MVF_ENGINE_INTERP;
+    return MVF_OK;
+}
+
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SingleLayout {
@@ -284,7 +298,7 @@ int check_splits(const mvf_tape *t, const int32_t *splits, int64_t *S, int *tab_
 
 int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_dev, int max_nodes, int64_t max_sub,
                     const double *boxes, const int32_t *splits, double *reduced, int64_t *argmin, int32_t *status,
-                    double *extra, void *ws, size_t ws_bytes, int grid, bool rev, BatchArgs *A) {
+                    double *extra, void *ws, size_t ws_bytes, int grid, bool rev, int spl, BatchArgs *A) {
     const BatchLayout L = batch_layout(t, max_nodes, max_sub, grid, rev);
     if (ws_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     uint8_t *w = static_cast<uint8_t *>(ws);
@@ -293,6 +307,7 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
     A->n_nodes_val = n_nodes;
     A->n = t->C.n_vars;
     A->tab_cap = BATCH_TAB_CAP;
+    A->spl = spl;
     A->boxes = boxes;
     A->splits = splits;
     A->reduced = reduced;
@@ -309,6 +324,27 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
     A->rec = reinterpret_cast<double2 *>(w + L.rec);
     A->gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     A->item_cap = (int64_t)(max_sub / BLK) + max_nodes + 1;
+    return MVF_OK;
+}
+
+// plan -> persistent bounding kernel (specialised or interpreter) -> per-node finish
+int launch_batched(const mvf_tape *t, int mode, int chunk, bool rev, bool spec, const BatchArgs &A, int grid,
+                   int max_nodes, hipStream_t stream) {
+    const int m = (int)t->C.roots.size(), n = t->C.n_vars;
+    if (spec) {
+        const size_t lds = spec_lds_bytes(BATCH_TAB_CAP, m);
+        HIP_TRY(launch_batch_plan(A, stream));
+        BatchKArgs K{tape_args(t, mode, 0), A};
+        void *params[] = {&K};
+        HIP_TRY(hipModuleLaunchKernel(t->spec_batch_fn, grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr));
+        HIP_TRY(launch_batch_finish(A, m, max_nodes, stream));
+        return MVF_OK;
+    }
+    const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
+                                 spill_bytes(spill_for(t->C, chunk), chunk));
+    if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
+    hipError_t e = launch_batch(tape_args(t, mode, chunk), A, chunk, rev, grid, lds, max_nodes, stream);
+    if (e != hipSuccess) return hip_err(e, "launch_batch");
     return MVF_OK;
 }
 
@@ -528,7 +564,9 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     hipModule_t mod = nullptr;
     hipFunction_t fn = nullptr;
     HIP_TRY(hipModuleLoadData(&mod, code.data()));
+    hipFunction_t bfn = nullptr;
     hipError_t e = hipModuleGetFunction(&fn, mod, "mvf_spec_bound");
+    if (e == hipSuccess) e = hipModuleGetFunction(&bfn, mod, "mvf_spec_batch");
     if (e != hipSuccess) {
         hipModuleUnload(mod);
         return hip_err(e, "hipModuleGetFunction");
@@ -536,6 +574,7 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     t->spec_mod = mod;
     t->spec_fn = fn;
+    t->spec_batch_fn = bfn;
     in.chunk = chunk;
     in.waves = waves;
     in.code_units = units;
@@ -589,32 +628,31 @@ int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning
     if (!a->boxes || !a->splits || !a->reduced || !a->status || !a->workspace)
         return set_err(MVF_EINVAL, "boxes, splits, reduced, status and workspace are required");
     if (a->mode < MVF_MODE_NIE || a->mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
-    bool rev;
+    bool rev, spec;
     int chunk;
     int rc = resolve_grad(t, a->mode, a->grad, tuning, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    rc = batch_engine(t, tuning, rev, &spec);
     if (rc != MVF_OK) return rc;
     const int grid = batch_grid(t, tuning);
     BatchArgs A;
     rc = fill_batch_args(t, a->n_nodes, nullptr, a->max_nodes, a->max_subdomains, a->boxes, a->splits, a->reduced,
-                         a->argmin, a->status, a->extra, a->workspace, a->workspace_bytes, grid, rev, &A);
+                         a->argmin, a->status, a->extra, a->workspace, a->workspace_bytes, grid, rev, batch_spl(tuning),
+                         &A);
     if (rc != MVF_OK) return rc;
     if (a->n_nodes == 0) return MVF_OK;
-    const int m = (int)t->C.roots.size();
-    const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, m, rev && A.gacc == nullptr,
-                                 spill_bytes(spill_for(t->C, chunk), chunk));
-    if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
-    hipError_t e = launch_batch(tape_args(t, a->mode, chunk), A, chunk, rev, grid, lds, a->n_nodes, stream);
-    if (e != hipSuccess) return hip_err(e, "launch_batch");
-    return MVF_OK;
+    return launch_batched(t, a->mode, chunk, rev, spec, A, grid, a->n_nodes, stream);
 }
 
 int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_subdomains, int32_t mode, int32_t grad,
                            const mvf_tuning *tuning, hipStream_t stream, mvf_batch_graph **out) {
     if (!t || !out || max_nodes < 1 || max_subdomains < 1) return set_err(MVF_EINVAL, "bad argument");
     *out = nullptr;
-    bool rev;
+    bool rev, spec;
     int chunk;
     int rc = resolve_grad(t, mode, grad, tuning, &rev, &chunk);
+    if (rc != MVF_OK) return rc;
+    rc = batch_engine(t, tuning, rev, &spec);
     if (rc != MVF_OK) return rc;
     mvf_batch_graph *g = new (std::nothrow) mvf_batch_graph;
     if (!g) return set_err(MVF_ENOMEM, "host allocation failed");
@@ -627,6 +665,8 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     g->tuning.grad = g->grad;
     g->tuning.chunk = chunk;
     g->tuning.grid_blocks = batch_grid(t, tuning);
+    g->tuning.sub_per_lane = batch_spl(tuning);
+    g->tuning.engine = spec ? MVF_ENGINE_SPEC : MVF_ENGINE_INTERP;
     const int n = t->C.n_vars, m = (int)t->C.roots.size();
     const int grid = g->tuning.grid_blocks;
     g->ws_bytes = batch_layout(t, max_nodes, max_subdomains, grid, rev).total;
@@ -662,11 +702,14 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
 
     BatchArgs A;
     rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
-                         g->d_argmin, g->d_status, g->d_extra, g->d_ws, g->ws_bytes, grid, rev, &A);
+                         g->d_argmin, g->d_status, g->d_extra, g->d_ws, g->ws_bytes, grid, rev, g->tuning.sub_per_lane,
+                         &A);
     if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
-    const size_t lds = lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
-                                 spill_bytes(spill_for(t->C, chunk), chunk));
-    if (lds > LDS_BUDGET - 1024) { mvf_batch_graph_destroy(g); return set_err(MVF_ELIMIT, "LDS budget"); }
+    if (!spec && lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
+                           spill_bytes(spill_for(t->C, chunk), chunk)) > LDS_BUDGET - 1024) {
+        mvf_batch_graph_destroy(g);
+        return set_err(MVF_ELIMIT, "LDS budget");
+    }
     (void)stream;
     hipStream_t cs = nullptr;                    // private capture stream, default priority
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MVF_EHIP, "hipStreamCreate");
@@ -679,7 +722,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
                   hipSuccess &&
               hipMemcpyAsync(g->d_splits, g->h_splits, (size_t)max_nodes * n * 4, hipMemcpyHostToDevice, cs) ==
                   hipSuccess;
-    ok = ok && launch_batch(tape_args(t, mode, chunk), A, chunk, rev, grid, lds, max_nodes, cs) == hipSuccess;
+    ok = ok && launch_batched(t, mode, chunk, rev, spec, A, grid, max_nodes, cs) == MVF_OK;
     ok = ok && hipMemcpyAsync(g->h_reduced, g->d_reduced, (size_t)max_nodes * m * 2 * 8, hipMemcpyDeviceToHost, cs) ==
                    hipSuccess &&
          hipMemcpyAsync(g->h_argmin, g->d_argmin, (size_t)max_nodes * 8, hipMemcpyDeviceToHost, cs) == hipSuccess &&
@@ -785,20 +828,38 @@ int64_t mvf_adaptive_splits(int32_t n, const double *widths, int64_t budget, int
 int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const int32_t *splits, int64_t n_sub,
                  int32_t mode, mvf_tuning *out, hipStream_t stream) {
     if (!t || !out || n_nodes < 1 || !boxes || !splits || n_sub < 1) return set_err(MVF_EINVAL, "bad argument");
-    // candidates: gradient mode x tangent chunk x persistent grid size
+    // candidates: kernel (interpreter forward per tangent chunk, specialised
+    // forward, reverse-mode adjoint) x persistent grid size x subdomains per lane
+    std::vector<mvf_tuning> kernels;
+    for (int chunk = 1; chunk <= t->C.chunk; ++chunk) {
+        mvf_tuning c{};
+        c.grad = MVF_GRAD_FWD;
+        c.chunk = chunk;
+        c.engine = MVF_ENGINE_INTERP;
+        kernels.push_back(c);
+    }
+    if (t->spec_batch_fn) {
+        mvf_tuning c{};
+        c.grad = MVF_GRAD_FWD;
+        c.engine = MVF_ENGINE_SPEC;
+        kernels.push_back(c);
+    }
+    {
+        mvf_tuning c{};
+        c.grad = MVF_GRAD_REV;
+        c.engine = MVF_ENGINE_INTERP;
+        kernels.push_back(c);
+    }
     std::vector<mvf_tuning> cand;
     const int cu = t->n_cu;
-    for (int grad = MVF_GRAD_FWD; grad <= MVF_GRAD_REV; ++grad) {
-        for (int chunk = 1; chunk <= (grad == MVF_GRAD_FWD ? t->C.chunk : 1); ++chunk) {
-            for (int mult : {1, 2, 4}) {
-                mvf_tuning c{};
-                c.grad = grad;
-                c.chunk = grad == MVF_GRAD_FWD ? chunk : 0;
+    for (const mvf_tuning &kc : kernels)
+        for (int mult : {1, 2, 4})
+            for (int spl : {1, 2, 4}) {
+                mvf_tuning c = kc;
                 c.grid_blocks = mult * cu;
+                c.sub_per_lane = spl;
                 cand.push_back(c);
             }
-        }
-    }
     size_t max_ws = 0;
     for (auto &c : cand) {
         size_t b = 0;

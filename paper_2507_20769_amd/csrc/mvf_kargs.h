@@ -48,6 +48,7 @@ struct BatchArgs {
     int32_t n_nodes_val;         // node count when n_nodes_dev is null
     int32_t n;
     int32_t tab_cap;         // breakpoint-table capacity per node (entries)
+    int32_t spl;             // subdomains per lane: a work item is spl * BLK subdomains of one node
     const double *boxes;     // [N][n][2]
     const int32_t *splits;   // [N][n]
     double *reduced;         // [N][m][2]

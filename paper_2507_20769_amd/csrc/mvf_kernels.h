@@ -17,6 +17,9 @@ hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev
 hipError_t launch_finish(const BoxArgs &B, int grid, int m, hipStream_t stream);
 hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool rev, int grid, size_t lds,
                         int max_nodes, hipStream_t stream);
+// the batched launch's plan kernel and per-node finish kernel (around any persistent bounding kernel)
+hipError_t launch_batch_plan(const BatchArgs &A, hipStream_t stream);
+hipError_t launch_batch_finish(const BatchArgs &A, int m, int max_nodes, hipStream_t stream);
 
 constexpr size_t LDS_BUDGET = 160 * 1024;
 

@@ -660,7 +660,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const double *partial, cons
 // batched: many nodes in one persistent launch
 // ---------------------------------------------------------------------------
 
-// One workgroup: validate every node, count its work items (chunks of BLK
+// One workgroup: validate every node, count its work items (chunks of spl * BLK
 // subdomains), exclusive prefix sum into item_off[N + 1], reset the work
 // counter.  Invalid nodes (split outside [1, 65535], table above the LDS
 // table capacity, more than 2^40 subdomains) get no items and status 1; if
@@ -671,6 +671,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs A) {
     const int N = node_count(A);
     const int n = A.n;
     const int per = (N + 255) / 256;
+    const int64_t isz = (int64_t)A.spl * BLK;      // subdomains per work item
     int64_t local = 0;
     for (int q = 0; q < per; ++q) {
         const int node = tid * per + q;
@@ -688,7 +689,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs A) {
         if (tab > A.tab_cap) ok = 0;
         A.node_S[node] = ok ? S : 0;
         A.status[node] = ok ? 0 : 1;
-        local += ok ? (S + BLK - 1) / BLK : 0;
+        local += ok ? (S + isz - 1) / isz : 0;
     }
     part[tid] = local;
     __syncthreads();
@@ -715,7 +716,7 @@ __global__ __launch_bounds__(256) void batch_plan_kernel(BatchArgs A) {
             A.status[node] = 2;
         }
         const int64_t S = A.node_S[node];
-        run += (S + BLK - 1) / BLK;
+        run += (S + isz - 1) / isz;
     }
 }
 
@@ -790,30 +791,35 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         }
         if (lane == 0) reset_wred(s.wred + wave * wred_len(m), m);
         __syncthreads();
-        int64_t S, k;
+        int64_t S, base;
+        int spl;
         {
             const auto K = kargs<BatchKArgs>();
             S = K->A.node_S[node];
-            k = (item - K->A.item_off[node]) * BLK + tid;
+            spl = K->A.spl;
+            base = (item - K->A.item_off[node]) * spl * BLK;
         }
-        const bool active = k < S;
-        decode_subdomain(n, active ? k : S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
-        LaneOut o;
-        o.per_sub = nullptr;
-        o.S = S;
-        o.k = k;
-        o.w = s.wred + wave * wred_len(m);
-        o.lane = lane;
-        o.active = active;
-        FeasTrack F;
-        uint32_t bad;
-        {
-            const auto K = kargs<BatchKArgs>();
-            o.ineq = K->T.ineq_mask;
-            o.eq = K->T.eq_mask;
-            bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o, F);
+        for (int j = 0; j < spl && base + (int64_t)j * BLK < S; ++j) {      // uniform over the workgroup
+            const int64_t k = base + (int64_t)j * BLK + tid;
+            const bool active = k < S;
+            decode_subdomain(n, active ? k : S - 1, s.ints, s.ints + MVF_MAX_VARS, s.vrec, tid, BLK);
+            LaneOut o;
+            o.per_sub = nullptr;
+            o.S = S;
+            o.k = k;
+            o.w = s.wred + wave * wred_len(m);
+            o.lane = lane;
+            o.active = active;
+            FeasTrack F;
+            uint32_t bad;
+            {
+                const auto K = kargs<BatchKArgs>();
+                o.ineq = K->T.ineq_mask;
+                o.eq = K->T.eq_mask;
+                bad = bound_lane<C, REV>(m, n, K->T.mode, K->T.root_base, X, o, F);
+            }
+            finish_lane(m, bad, F, o, nullptr);
         }
-        finish_lane(m, bad, F, o, nullptr);
         __syncthreads();
         if (tid == 0) {
             const auto K = kargs<BatchKArgs>();
@@ -1067,10 +1073,19 @@ hipError_t launch_finish(const BoxArgs &B, int grid, int m, hipStream_t stream) 
     return hipGetLastError();
 }
 
+hipError_t launch_batch_plan(const BatchArgs &A, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(256), 0, stream, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_finish(const BatchArgs &A, int m, int max_nodes, hipStream_t stream) {
+    hipLaunchKernelGGL(batch_finish_kernel, dim3(max_nodes), dim3(256), 0, stream, A, m);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool rev, int grid, size_t lds,
                         int max_nodes, hipStream_t stream) {
-    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(256), 0, stream, A);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_batch_plan(A, stream);
     if (e != hipSuccess) return e;
     MVF_DISPATCH(chunk, rev, {
         static std::once_flag once;
@@ -1081,8 +1096,7 @@ hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool r
     });
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_finish_kernel, dim3(max_nodes), dim3(256), 0, stream, A, T.n_roots);
-    return hipGetLastError();
+    return launch_batch_finish(A, T.n_roots, max_nodes, stream);
 }
 
 hipError_t launch_points(const PointsArgs &A, int op, int chunk, int grid, size_t lds, hipStream_t stream) {

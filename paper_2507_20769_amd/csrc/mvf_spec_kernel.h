@@ -1,10 +1,11 @@
-// mvf_spec_kernel.h -- the specialised bounding kernel (one node box).
+// mvf_spec_kernel.h -- the specialised bounding kernels (one node box; many nodes).
 //
 // Compiled at run time after the generated namespace spec, which provides
 // N_VARS, N_ROOTS and lane_bounds() (every root's bound on one lane's
 // subdomain, folded into the wave's reduction record).  Launch shape,
-// arguments, LDS reduction records and per-block partials are those of the
-// interpreter's single-box kernel, so its finish kernel completes Step 3.
+// arguments, LDS reduction records and partials are those of the
+// interpreter's single-box and batched kernels, so their finish kernels
+// complete Step 3.
 #pragma once
 
 #ifndef MVF_SPEC_WAVES
@@ -74,5 +75,111 @@ void mvf_spec_bound(mvf::BoundKArgs /* read through kargs() */) {
         const auto K = kargs<BoundKArgs>();
         write_partial(wred, BLK / 64, m, K->B.partial + (size_t)blockIdx.x * m * 2, K->B.partial_lo0 + blockIdx.x,
                       K->B.partial_k + blockIdx.x, K->B.partial_ext + 2 * (size_t)blockIdx.x);
+    }
+}
+
+// The batched form: persistent workgroups take work items (spl * BLK
+// subdomains of one node) from the plan kernel's counter, as the
+// interpreter's batch kernel does, and leave one partial per item for the
+// per-node finish kernel.
+extern "C" __global__ __launch_bounds__(mvf::BLK) __attribute__((amdgpu_waves_per_eu(MVF_SPEC_WAVES, MVF_SPEC_WAVES)))
+void mvf_spec_batch(mvf::BatchKArgs /* read through kargs() */) {
+    using namespace mvf;
+    using namespace mvf::dev;
+    constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int64_t sh_item;
+    __shared__ int sh_node;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tab_cap = kargs<BatchKArgs>()->A.tab_cap;
+    double4 *tab = reinterpret_cast<double4 *>(smem);
+    double *wred = reinterpret_cast<double *>(smem + (size_t)tab_cap * 32);
+    int32_t *ints = reinterpret_cast<int32_t *>(smem + (size_t)tab_cap * 32 +
+                                                (((size_t)(BLK / 64) * wred_len(m) * 8 + 15) & ~(size_t)15));
+    const bool go = kargs<BatchKArgs>()->T.n == n;        // always true, opaque (see mvf_spec_bound)
+    int cur = -1;
+    for (;;) {
+        {
+            const auto K = kargs<BatchKArgs>();
+            if (tid == 0) sh_item = atomicAdd(reinterpret_cast<unsigned long long *>(K->A.counter), 1ull);
+        }
+        __syncthreads();
+        const int64_t item = sh_item;
+        {
+            const auto K = kargs<BatchKArgs>();
+            const int N = node_count(K->A);
+            if (item >= K->A.item_off[N]) break;           // uniform exit: every wave reaches it
+            if (tid == 0) {                                 // node owning the item: last node with item_off <= item
+                int lo = 0, hi = N - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (K->A.item_off[mid] <= item) lo = mid; else hi = mid - 1;
+                }
+                while (lo < N - 1 && K->A.item_off[lo + 1] <= item) ++lo;   // skip nodes without items
+                sh_node = lo;
+            }
+        }
+        __syncthreads();
+        const int node = sh_node;
+        if (node != cur) {                              // new node: splits, offsets, breakpoint table
+            const auto K = kargs<BatchKArgs>();
+            if (tid < n) ints[tid] = K->A.splits[(int64_t)node * n + tid];
+            __syncthreads();
+            if (tid == 0) {
+                int acc = 0;
+                for (int i = 0; i < n; ++i) { ints[MVF_MAX_VARS + i] = acc; acc += ints[i]; }
+                ints[MVF_MAX_VARS + n] = acc;
+            }
+            __syncthreads();
+            build_table(n, K->A.boxes + (int64_t)node * n * 2, ints, ints + MVF_MAX_VARS, tab, tid, BLK);
+            cur = node;
+        }
+        if (lane == 0) reset_wred(wred + wave * wred_len(m), m);
+        __syncthreads();
+        int64_t S, base;
+        int spl;
+        {
+            const auto K = kargs<BatchKArgs>();
+            S = K->A.node_S[node];
+            spl = K->A.spl;
+            base = (item - K->A.item_off[node]) * spl * BLK;
+        }
+        for (int j = 0; j < spl && base + (int64_t)j * BLK < S; ++j) {      // uniform over the workgroup
+            const int64_t k = base + (int64_t)j * BLK + tid;
+            const bool active = k < S;
+            SpecLane L;
+            L.tab = tab;
+            int64_t q = active ? k : S - 1;
+#pragma unroll
+            for (int i = 0; i < n; ++i) {
+                const int s = ints[i];
+                L.vi[i] = ints[MVF_MAX_VARS + i] + (int)(q % s);
+                q /= s;
+            }
+            LaneOut o;
+            o.per_sub = nullptr;
+            o.S = S;
+            o.k = k;
+            o.w = wred + wave * wred_len(m);
+            o.lane = lane;
+            o.active = active;
+            FeasTrack F;
+            uint32_t bad;
+            {
+                const auto K = kargs<BatchKArgs>();
+                o.ineq = K->T.ineq_mask;
+                o.eq = K->T.eq_mask;
+                mode_round_down();
+                bad = spec::lane_bounds(L, K->T.mode, go, o, F);
+                mode_round_nearest();
+            }
+            finish_lane(m, bad, F, o, nullptr);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const auto K = kargs<BatchKArgs>();
+            write_partial(wred, BLK / 64, m, K->A.partial + (size_t)item * m * 2, K->A.partial_lo0 + item,
+                          K->A.partial_k + item, K->A.partial_ext + 2 * (size_t)item);
+        }
     }
 }

@@ -43,11 +43,13 @@ class TapeStats(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
+    """mvf_tuning; grad -1 keeps the call's gradient mode."""
     _fields_ = [("grad", ctypes.c_int32), ("chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("best_ms", ctypes.c_float)]
+                ("best_ms", ctypes.c_float), ("sub_per_lane", ctypes.c_int32), ("engine", ctypes.c_int32)]
 
     def __repr__(self):
-        return f"Tuning(grad={self.grad}, chunk={self.chunk}, grid_blocks={self.grid_blocks}, best_ms={self.best_ms:.3f})"
+        return (f"Tuning(grad={self.grad}, chunk={self.chunk}, grid_blocks={self.grid_blocks}, "
+                f"sub_per_lane={self.sub_per_lane}, engine={self.engine}, best_ms={self.best_ms:.3f})")
 
 
 class BnbOptions(ctypes.Structure):

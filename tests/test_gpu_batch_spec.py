@@ -1,0 +1,130 @@
+"""GPU tests of the batched launch configurations: subdomains per lane and the
+specialised batch kernel give per node exactly the single-box result, inside
+and outside a captured graph, and the autotuner's choice among them is
+feasible and exact."""
+import numpy as np
+import pytest
+
+from paper_2507_20769_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _rational(t):
+    nodes = t.nodes.copy()
+    nodes["op"][nodes["op"] == I.EXP] = I.SQR
+    nodes["op"][nodes["op"] == I.LOG] = I.SQRT
+    return I.Tape(nodes, t.consts, t.roots, t.n_vars)
+
+
+def _per_node(h, bw, grad):
+    import torch
+    from paper_2507_20769_amd import mvf
+    red, am, ex = [], [], []
+    for i in range(len(bw.boxes)):
+        out = mvf.bound(h, torch.tensor(bw.boxes[i], device="cuda"), bw.splits[i], mode="both", grad=grad,
+                        engine="interp")
+        torch.cuda.synchronize()
+        red.append(out["reduced"].cpu().numpy())
+        am.append(int(out["argmin"].item()))
+        ex.append(out["extra"].cpu().numpy())
+    return np.stack(red), np.array(am), np.stack(ex)
+
+
+def _tuning(grad, spl, engine, grid=0):
+    from paper_2507_20769_amd import mvf
+    return mvf.Tuning(grad=grad, chunk=0, grid_blocks=grid, best_ms=0.0, sub_per_lane=spl,
+                      engine=mvf.MVF_ENGINE[engine])
+
+
+@pytest.mark.parametrize("grad,spl,engine", [("fwd", 2, "interp"), ("fwd", 4, "interp"), ("rev", 2, "interp"),
+                                             ("rev", 4, "interp"), ("fwd", 1, "spec"), ("fwd", 2, "spec"),
+                                             ("fwd", 4, "spec")])
+def test_batched_configurations_equal_per_node(grad, spl, engine):
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(21, 20, k_range=(3, 12))           # 8 .. 4096 subdomains: ragged items
+    tape = _rational(bw.tape)
+    h = mvf.Tape(tape)
+    h.set_root_kinds([0] + [1] * (tape.n_roots - 1))
+    if engine == "spec":
+        h.specialize()
+    print(f"[case] grad={grad} spl={spl} engine={engine}", flush=True)
+    tu = _tuning(0 if grad == "fwd" else 1, spl, engine, grid=37)   # an odd grid: items wrap unevenly
+    out = mvf.bound_batch(h, torch.tensor(bw.boxes, device="cuda"), torch.tensor(bw.splits, device="cuda"),
+                          mode="both", grad=grad, tuning=tu)
+    torch.cuda.synchronize()
+    assert not out["status"].cpu().numpy().any()
+    red, am, ex = _per_node(h, bw, grad)
+    assert np.array_equal(out["reduced"].cpu().numpy(), red)
+    assert np.array_equal(out["argmin"].cpu().numpy(), am)
+    assert np.array_equal(out["extra"].cpu().numpy(), ex)
+    h.close()
+
+
+def test_spec_batch_graph_replays_match_fresh_launches():
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(22, 24, k_range=(4, 10))
+    h = mvf.Tape(_rational(bw.tape))
+    h.specialize()
+    total = int(np.prod(bw.splits.astype(np.int64), axis=1).sum())
+    g = mvf.BatchGraph(h, len(bw.boxes), total, mode="both", grad="fwd", tuning=_tuning(0, 2, "spec"))
+    s = torch.cuda.Stream()
+    ref = mvf.bound_batch(h, torch.tensor(bw.boxes, device="cuda"), torch.tensor(bw.splits, device="cuda"),
+                          mode="both", grad="fwd", tuning=_tuning(0, 1, "interp"))
+    torch.cuda.synchronize()
+    want = ref["reduced"].cpu().numpy()
+    for rep in range(3):                                # several replays, eager work in between
+        n = len(bw.boxes) - 4 * rep
+        g.launch(bw.boxes[:n], bw.splits[:n], stream=s)
+        s.synchronize()
+        red, am, st = g.result()
+        assert not st.any()
+        assert np.array_equal(red, want[:n]), rep
+        torch.cuda.synchronize()
+    g.close()
+    h.close()
+
+
+def test_autotuner_considers_the_specialised_kernel():
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(23, 16, k_range=(6, 11))
+    h = mvf.Tape(bw.tape)
+    h.specialize()
+    boxes = torch.tensor(bw.boxes, device="cuda")
+    splits = torch.tensor(bw.splits, device="cuda")
+    tu = mvf.autotune(h, boxes, splits, mode="both")
+    print(f"[autotune] {tu}", flush=True)
+    assert tu.grad in (0, 1) and tu.grid_blocks > 0 and tu.best_ms > 0 and tu.sub_per_lane in (1, 2, 4)
+    assert tu.engine in (1, 2)
+    out = mvf.bound_batch(h, boxes, splits, mode="both", grad="rev", tuning=tu)
+    ref = mvf.bound_batch(h, boxes, splits, mode="both", grad="fwd" if tu.grad == 0 else "rev",
+                          tuning=_tuning(tu.grad, 1, "interp"))
+    torch.cuda.synchronize()
+    a, b = out["reduced"].cpu().numpy(), ref["reduced"].cpu().numpy()
+    if tu.engine == 1:
+        assert np.array_equal(a, b)
+    else:   # the specialised kernel: bitwise up to the libm build of exp/log
+        assert np.allclose(a, b, rtol=1e-12, atol=0)
+    h.close()
+
+
+def test_batched_engine_errors():
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(24, 4, k_range=(3, 5))
+    h = mvf.Tape(bw.tape)
+    boxes = torch.tensor(bw.boxes, device="cuda")
+    splits = torch.tensor(bw.splits, device="cuda")
+    for tu, grad in ((_tuning(0, 1, "spec"), "fwd"),      # not specialised
+                     (_tuning(0, 17, "interp"), "fwd")):  # sub_per_lane out of range
+        with pytest.raises(mvf.MVFError) as e:
+            mvf.bound_batch(h, boxes, splits, grad=grad, tuning=tu)
+        assert e.value.code == -1
+    h.specialize()
+    with pytest.raises(mvf.MVFError) as e:
+        mvf.bound_batch(h, boxes, splits, grad="rev", tuning=_tuning(1, 1, "spec"))
+    assert e.value.code == -1
+    h.close()
