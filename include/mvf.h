@@ -223,6 +223,28 @@ typedef struct mvf_tuning {
  */
 int64_t mvf_adaptive_splits(int32_t n, const double *widths, int64_t budget, int32_t *splits);
 
+/*
+ * Split rules for a subdomain budget: MVF_SPLITS_ADAPTIVE is the adaptive
+ * partitioning above (Sec. 3.1.2); MVF_SPLITS_DOUBLING starts from one
+ * subdomain and doubles the split count of the dimension with the largest
+ * w_i / s_i (ties to the lower index; counts stay <= 65535) while the
+ * product stays <= budget, giving power-of-two counts (bisection-shaped
+ * subdomains).  Host only;
+ * returns the subdomain count or a negative error code.
+ */
+enum { MVF_SPLITS_ADAPTIVE = 0, MVF_SPLITS_DOUBLING = 1 };
+int64_t mvf_splits(int32_t rule, int32_t n, const double *widths, int64_t budget, int32_t *splits);
+/*
+ * Split-rule tuning: bounds n_nodes sample node boxes (host [N][n][2]) with
+ * each rule at the given budget in one batched launch per rule, and writes
+ * to *rule the rule that gives the larger objective lower bound (the
+ * feasibility-filtered bound) on more of the nodes; ties go to the adaptive
+ * rule.  *better_nodes receives, per rule, the count of nodes where it is
+ * strictly tighter.  Allocates temporary device memory.
+ */
+int mvf_autotune_splits(const mvf_tape *tape, int32_t n_nodes, const double *boxes, int64_t budget, int32_t mode,
+                        int32_t grad, int32_t *rule, int32_t better_nodes[2], hipStream_t stream);
+
 /* ---- batched bounding of many nodes ----------------------------------- */
 typedef struct {
     int32_t n_nodes;          /* nodes in this call, 0 <= n_nodes <= max_nodes */
@@ -343,6 +365,7 @@ typedef struct {
     double abs_gap;               /* stop when upper - lower <= abs_gap (>= 0) */
     int32_t mode, grad;           /* MVF_MODE_*, MVF_GRAD_* of the bounding calls */
     const struct mvf_tuning *tuning;   /* NULL or the batched launches' tuning */
+    int32_t split_rule;           /* MVF_SPLITS_* of each node's partition */
 } mvf_bnb_options;
 
 typedef struct {

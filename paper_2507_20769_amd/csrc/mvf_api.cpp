@@ -825,6 +825,102 @@ int64_t mvf_adaptive_splits(int32_t n, const double *widths, int64_t budget, int
     return count;
 }
 
+int64_t mvf_splits(int32_t rule, int32_t n, const double *widths, int64_t budget, int32_t *splits) {
+    if (rule == MVF_SPLITS_ADAPTIVE) return mvf_adaptive_splits(n, widths, budget, splits);
+    if (rule != MVF_SPLITS_DOUBLING) return set_err(MVF_EINVAL, "unknown split rule");
+    if (n < 1 || !widths || !splits || budget < 1) return set_err(MVF_EINVAL, "bad argument");
+    int64_t count = 1;
+    for (int i = 0; i < n; ++i) splits[i] = 1;
+    while (count * 2 <= budget) {
+        int best = -1;                            // a split count stays <= 65535
+        for (int i = 0; i < n; ++i)
+            if (splits[i] <= 32767 && (best < 0 || widths[i] / splits[i] > widths[best] / splits[best])) best = i;
+        if (best < 0) break;
+        splits[best] *= 2;
+        count *= 2;
+    }
+    return count;
+}
+
+int mvf_autotune_splits(const mvf_tape *t, int32_t n_nodes, const double *boxes, int64_t budget, int32_t mode,
+                        int32_t grad, int32_t *rule, int32_t better_nodes[2], hipStream_t stream) {
+    if (!t || n_nodes < 1 || !boxes || budget < 1 || !rule) return set_err(MVF_EINVAL, "bad argument");
+    const int n = t->C.n_vars, m = (int)t->C.roots.size();
+    std::vector<int32_t> sp[2];
+    std::vector<double> widths(n);
+    int64_t total[2] = {0, 0};
+    for (int r = 0; r < 2; ++r) {
+        sp[r].resize((size_t)n_nodes * n);
+        for (int q = 0; q < n_nodes; ++q) {
+            for (int i = 0; i < n; ++i) widths[i] = boxes[((size_t)q * n + i) * 2 + 1] - boxes[((size_t)q * n + i) * 2];
+            const int64_t c = mvf_splits(r, n, widths.data(), budget, &sp[r][(size_t)q * n]);
+            if (c < 1) return c < 0 ? (int)c : set_err(MVF_EINVAL, "partitioning failed");
+            total[r] += c;
+        }
+    }
+    const int64_t cap = std::max(total[0], total[1]);
+    size_t ws_bytes = 0;
+    int rc = mvf_batch_workspace(t, n_nodes, cap, mode, grad, nullptr, &ws_bytes);
+    if (rc != MVF_OK) return rc;
+    void *ws = nullptr;
+    double *d_boxes = nullptr, *d_red = nullptr, *d_ex = nullptr;
+    int32_t *d_splits = nullptr, *d_st = nullptr;
+    auto cleanup = [&]() {
+        hipFree(ws);
+        hipFree(d_boxes);
+        hipFree(d_red);
+        hipFree(d_ex);
+        hipFree(d_splits);
+        hipFree(d_st);
+    };
+    if (hipMalloc(&ws, ws_bytes) != hipSuccess || hipMalloc(&d_boxes, (size_t)n_nodes * n * 16) != hipSuccess ||
+        hipMalloc(&d_red, (size_t)n_nodes * m * 16) != hipSuccess || hipMalloc(&d_ex, (size_t)n_nodes * 16) != hipSuccess ||
+        hipMalloc(&d_splits, (size_t)n_nodes * n * 4) != hipSuccess || hipMalloc(&d_st, (size_t)n_nodes * 4) != hipSuccess) {
+        cleanup();
+        return set_err(MVF_ENOMEM, "split tuning buffers");
+    }
+    std::vector<double> lb[2];
+    hipError_t e = hipMemcpyAsync(d_boxes, boxes, (size_t)n_nodes * n * 16, hipMemcpyHostToDevice, stream);
+    for (int r = 0; r < 2 && e == hipSuccess && rc == MVF_OK; ++r) {
+        e = hipMemcpyAsync(d_splits, sp[r].data(), (size_t)n_nodes * n * 4, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) break;
+        mvf_batch_args a{};
+        a.n_nodes = n_nodes;
+        a.max_nodes = n_nodes;
+        a.max_subdomains = cap;
+        a.boxes = d_boxes;
+        a.splits = d_splits;
+        a.mode = mode;
+        a.grad = grad;
+        a.reduced = d_red;
+        a.status = d_st;
+        a.workspace = ws;
+        a.workspace_bytes = ws_bytes;
+        a.extra = d_ex;
+        rc = mvf_bound_batch(t, &a, nullptr, stream);
+        if (rc != MVF_OK) break;
+        std::vector<double> ex((size_t)n_nodes * 2);
+        e = hipMemcpyAsync(ex.data(), d_ex, ex.size() * 8, hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        lb[r].resize(n_nodes);
+        for (int q = 0; q < n_nodes; ++q) lb[r][q] = ex[2 * (size_t)q];
+    }
+    cleanup();
+    if (rc != MVF_OK) return rc;
+    if (e != hipSuccess) return hip_err(e, "split tuning");
+    int better[2] = {0, 0};
+    for (int q = 0; q < n_nodes; ++q) {
+        if (lb[0][q] > lb[1][q]) ++better[0];
+        if (lb[1][q] > lb[0][q]) ++better[1];
+    }
+    *rule = better[1] > better[0] ? MVF_SPLITS_DOUBLING : MVF_SPLITS_ADAPTIVE;
+    if (better_nodes) {
+        better_nodes[0] = better[0];
+        better_nodes[1] = better[1];
+    }
+    return MVF_OK;
+}
+
 int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const int32_t *splits, int64_t n_sub,
                  int32_t mode, mvf_tuning *out, hipStream_t stream) {
     if (!t || !out || n_nodes < 1 || !boxes || !splits || n_sub < 1) return set_err(MVF_EINVAL, "bad argument");

@@ -120,8 +120,9 @@ extern "C" int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_op
         const int cnt = (int)take.size();
         for (int q = 0; q < cnt; ++q) {
             for (int i = 0; i < n; ++i) widths[i] = take[q].box[2 * i + 1] - take[q].box[2 * i];
-            const int64_t c = mvf_adaptive_splits(n, widths.data(), opt->subdomains_per_node, &splits[(size_t)q * n]);
-            if (c < 1) { cleanup(); return set_error(MVF_EINVAL, "adaptive partitioning failed"); }
+            const int64_t c = mvf_splits(opt->split_rule, n, widths.data(), opt->subdomains_per_node,
+                                         &splits[(size_t)q * n]);
+            if (c < 1) { cleanup(); return c < 0 ? (int)c : set_error(MVF_EINVAL, "partitioning failed"); }
             subdomains += c;
         }
         if (K > 1) {

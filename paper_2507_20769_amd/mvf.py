@@ -55,7 +55,7 @@ class Tuning(ctypes.Structure):
 class BnbOptions(ctypes.Structure):
     _fields_ = [("max_nodes", ctypes.c_int32), ("nodes_per_launch", ctypes.c_int32),
                 ("subdomains_per_node", ctypes.c_int64), ("abs_gap", ctypes.c_double), ("mode", ctypes.c_int32),
-                ("grad", ctypes.c_int32), ("tuning", ctypes.c_void_p)]
+                ("grad", ctypes.c_int32), ("tuning", ctypes.c_void_p), ("split_rule", ctypes.c_int32)]
 
 
 class BnbResult(ctypes.Structure):
@@ -94,6 +94,7 @@ class SpecInfo(ctypes.Structure):
 
 
 MVF_ENGINE = {"auto": 0, "interp": 1, "spec": 2}
+SPLIT_RULES = {"adaptive": 0, "doubling": 1}
 
 
 EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_destroy",
@@ -101,7 +102,8 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_create", "mvf_batch_graph_staging", "mvf_batch_graph_launch", "mvf_batch_graph_result",
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
-           "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check"]
+           "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check", "mvf_splits",
+           "mvf_autotune_splits"]
 
 
 def lib():
@@ -141,6 +143,10 @@ def lib():
             i64 = ctypes.c_int64
             L.mvf_adaptive_splits.restype = i64
             L.mvf_adaptive_splits.argtypes = [i32, P, i64, P]
+            L.mvf_splits.restype = i64
+            L.mvf_splits.argtypes = [i32, i32, P, i64, P]
+            L.mvf_autotune_splits.restype = ctypes.c_int
+            L.mvf_autotune_splits.argtypes = [P, i32, P, i64, i32, i32, ctypes.POINTER(ctypes.c_int32), P, P]
             L.mvf_batch_workspace.restype = ctypes.c_int
             L.mvf_batch_workspace.argtypes = [P, i32, i64, i32, i32, ctypes.POINTER(Tuning),
                                               ctypes.POINTER(ctypes.c_size_t)]
@@ -340,6 +346,31 @@ def adaptive_splits(widths, budget: int):
     if count < 0:
         raise MVFError(int(count), "mvf_adaptive_splits")
     return out, int(count)
+
+
+def splits(rule: str, widths, budget: int):
+    """Split counts of one box under a split rule ("adaptive", Sec. 3.1.2, or "doubling")."""
+    w = np.ascontiguousarray(widths, dtype=np.float64)
+    out = np.zeros(len(w), dtype=np.int32)
+    count = lib().mvf_splits(SPLIT_RULES[rule], len(w), w.ctypes.data_as(ctypes.c_void_p), int(budget),
+                             out.ctypes.data_as(ctypes.c_void_p))
+    if count < 0:
+        raise MVFError(int(count), "mvf_splits")
+    return out, int(count)
+
+
+def autotune_splits(tape: Tape, boxes, budget: int, mode: str = "both", grad: str = "rev", stream=None):
+    """The split rule giving the tighter objective bounds on sample node boxes (host [N, n, 2]).
+    Returns (rule name, [nodes where adaptive is tighter, nodes where doubling is tighter])."""
+    b = np.ascontiguousarray(boxes, dtype=np.float64)
+    assert b.ndim == 3 and b.shape[1:] == (tape.n_vars, 2)
+    rule = ctypes.c_int32()
+    better = (ctypes.c_int32 * 2)()
+    rc = lib().mvf_autotune_splits(tape.handle, b.shape[0], b.ctypes.data_as(ctypes.c_void_p), int(budget),
+                                   MVF_MODE[mode], MVF_GRAD[grad], ctypes.byref(rule), better, _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_autotune_splits")
+    return ("adaptive", "doubling")[rule.value], [better[0], better[1]]
 
 
 class BatchCall:
@@ -590,7 +621,7 @@ def point_function(tape: Tape, x):
 # ---------------------------------------------------------------------------
 def bnb_solve(tape: Tape, box, max_nodes: int = 1000, gap: float = 1e-4, budget: int = 4096,
               nodes_per_launch: int = 1, mode: str = "both", grad: str = "fwd",
-              tuning: Optional[Tuning] = None, stream=None) -> dict:
+              tuning: Optional[Tuning] = None, stream=None, split_rule: str = "adaptive") -> dict:
     """Spatial B&B with GPU subdomain bounding (synchronous).  box: host [n, 2].
 
     Root kinds come from Tape.set_root_kinds.  Returns dict(lower, upper,
@@ -598,7 +629,7 @@ def bnb_solve(tape: Tape, box, max_nodes: int = 1000, gap: float = 1e-4, budget:
     b = np.ascontiguousarray(box, dtype=np.float64)
     assert b.shape == (tape.n_vars, 2)
     opt = BnbOptions(int(max_nodes), int(nodes_per_launch), int(budget), float(gap), MVF_MODE[mode], MVF_GRAD[grad],
-                     ctypes.addressof(tuning) if tuning is not None else None)
+                     ctypes.addressof(tuning) if tuning is not None else None, SPLIT_RULES[split_rule])
     res = BnbResult()
     rc = lib().mvf_bnb_solve(tape.handle, b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(res),
                              _stream_ptr(stream))

@@ -128,3 +128,32 @@ def test_batched_engine_errors():
         mvf.bound_batch(h, boxes, splits, grad="rev", tuning=_tuning(1, 1, "spec"))
     assert e.value.code == -1
     h.close()
+
+
+def test_split_rule_tuning_and_bnb_under_both_rules():
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(25, 12, k_range=(3, 6))
+    h = mvf.Tape(bw.tape)
+    rule, better = mvf.autotune_splits(h, bw.boxes, 512, mode="both", grad="rev")
+    print(f"[splits] rule={rule} better={better}", flush=True)
+    # the same comparison by hand
+    lbs = []
+    for r in ("adaptive", "doubling"):
+        sp = np.stack([mvf.splits(r, b[:, 1] - b[:, 0], 512)[0] for b in bw.boxes])
+        out = mvf.bound_batch(h, torch.tensor(bw.boxes, device="cuda"), torch.tensor(sp, device="cuda"),
+                              mode="both", grad="rev")
+        torch.cuda.synchronize()
+        lbs.append(out["extra"].cpu().numpy()[:, 0])
+    assert better == [int(np.sum(lbs[0] > lbs[1])), int(np.sum(lbs[1] > lbs[0]))]
+    assert rule == ("doubling" if better[1] > better[0] else "adaptive")
+    # the B&B driver under both rules brackets the cubic's minimum
+    t = I.cubic_tape()
+    hc = mvf.Tape(t)
+    xs = (-2.0 + np.sqrt(184.0)) / 18.0
+    fs = 3 * xs ** 3 + xs ** 2 - 5 * xs - 1
+    for r in ("adaptive", "doubling"):
+        res = mvf.bnb_solve(hc, [[-1.0, 2.0]], max_nodes=300, gap=1e-6, budget=64, split_rule=r)
+        assert res["status"] == 0 and res["lower"] <= fs <= res["upper"] and res["upper"] - res["lower"] <= 1e-6, r
+    hc.close()
+    h.close()
