@@ -135,14 +135,14 @@ typedef struct {
                                  over centres whose inequality enclosures are all <= 0 (no
                                  equality roots, MVF modes only), else +inf (Sec. 3.1, the
                                  feasibility check; the centres are rigorously feasible points) */
-    int32_t engine;           /* MVF_ENGINE_*: which kernel runs forward-mode and NIE calls */
+    int32_t engine;           /* MVF_ENGINE_*: the interpreter or the tape's specialised kernel */
 } mvf_bound_args;
 
-/* Kernel choice of mvf_bound for forward-mode (and NIE) calls: AUTO runs the
- * tape's specialised kernel when mvf_tape_specialize has built one, else the
- * interpreter; INTERP always the interpreter; SPEC the specialised kernel, or
- * MVF_EINVAL when there is none.  Reverse-mode calls always interpret.  Both
- * kernels give the same bits. */
+/* Kernel choice of mvf_bound: AUTO runs the tape's specialised kernel for the
+ * call's gradient mode (NIE calls: the tangent-mode one) when
+ * mvf_tape_specialize has built it, else the interpreter; INTERP always the
+ * interpreter; SPEC the specialised kernel, or MVF_EINVAL when there is none.
+ * Both kernels give the same bits. */
 enum { MVF_ENGINE_AUTO = 0, MVF_ENGINE_INTERP = 1, MVF_ENGINE_SPEC = 2 };
 
 /*
@@ -164,19 +164,21 @@ int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mod
  */
 int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
 
-/* ---- specialised forward kernels ------------------------------------
+/* ---- specialised kernels ---------------------------------------------
  * The interpreter kernels evaluate the DAG node by node (the single-kernel
  * evaluation of Sec. 3.2), decoding every instruction at run time.
  * mvf_tape_specialize generates straight-line device code of the tape's root
  * programs instead (per root: the point pass at the centre, the NIE value
- * pass, and tangent passes of `chunk` gradient components; the MVF combine of
- * Sec. 2.2 and the Step 3 reduction as in the interpreter), compiles it at
+ * pass, and tangent passes of `chunk` gradient components, or the value pass
+ * with its local partials followed by the reverse-mode adjoint sweep; the MVF
+ * combine of Sec. 2.2 and the Step 3 reduction as in the interpreter),
+ * single-box and batched, compiles it at
  * run time with hiprtc for the current device and keeps the loaded module in
  * the tape.  Each operation is the one the interpreter performs, in the same
  * order, so the bounds are bitwise identical; no instruction is decoded or
  * dispatched at run time.  Compilation takes seconds to a minute,
  * about linear in the generated size (code_units = sum over roots of program
- * length x passes); MVF_ELIMIT above max_code.  With use_cache the code
+ * length x passes, the adjoint counting two); MVF_ELIMIT above max_code.  With use_cache the code
  * object is kept under $MVF_SPEC_CACHE (default ~/.cache/mvf_spec; "off"
  * disables) keyed by a hash of the source, options and compiler version;
  * $MVF_SPEC_DUMP names a file that receives a copy of the generated source.
@@ -187,9 +189,11 @@ typedef struct {
     int32_t waves;            /* waves per SIMD the kernel is compiled for, 1..4; 0 = 2 */
     int64_t max_code;         /* size limit in instruction-passes; 0 = default (6000) */
     int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache */
+    int32_t grad;             /* kernels to build: MVF_GRAD_FWD (tangent mode), MVF_GRAD_REV
+                                 (reverse-mode adjoint) or MVF_GRAD_AUTO (both) */
 } mvf_spec_options;
 typedef struct {
-    int32_t chunk, waves;
+    int32_t chunk, waves, grad;
     int64_t code_units;       /* instruction-passes generated */
     int64_t code_bytes;       /* size of the code object */
     double seconds;           /* generation + compilation (or cache read) */

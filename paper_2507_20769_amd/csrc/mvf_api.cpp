@@ -23,8 +23,9 @@ struct mvf_tape {
     int device = 0;
     int n_cu = 256;
     uint32_t ineq_mask = 0, eq_mask = 0;   // constraint roots (mvf_tape_set_root_kinds)
-    hipModule_t spec_mod = nullptr;         // specialised forward kernels (mvf_tape_specialize)
-    hipFunction_t spec_fn = nullptr, spec_batch_fn = nullptr;
+    hipModule_t spec_mod = nullptr;         // specialised kernels (mvf_tape_specialize)
+    hipFunction_t spec_fn[2] = {nullptr, nullptr};        // single box: [0] tangent mode, [1] adjoint
+    hipFunction_t spec_batch_fn[2] = {nullptr, nullptr};  // batched
     mvf_spec_info spec_info{};
 };
 
@@ -167,10 +168,9 @@ int batch_engine(const mvf_tape *t, const mvf_tuning *tu, bool rev, bool *spec) 
     const int e = tu ? tu->engine : MVF_ENGINE_AUTO;
     if (e < MVF_ENGINE_AUTO || e > MVF_ENGINE_SPEC) return set_err(MVF_EINVAL, "bad engine");
     if (tu && (tu->sub_per_lane < 0 || tu->sub_per_lane > 16)) return set_err(MVF_EINVAL, "sub_per_lane outside [0, 16]");
-    if (e == MVF_ENGINE_SPEC && (rev || !t->spec_batch_fn))
-        return set_err(MVF_EINVAL, rev ? "the specialised kernel is forward mode only"
-                                       : "no specialised kernel: call mvf_tape_specialize first");
-    *spec = !rev && t->spec_batch_fn && e != MVF_ENGINE_INTERP;
+    if (e == MVF_ENGINE_SPEC && !t->spec_batch_fn[rev])
+        return set_err(MVF_EINVAL, "no specialised kernel for this gradient mode: see mvf_tape_specialize");
+    *spec = t->spec_batch_fn[rev] && e != MVF_ENGINE_INTERP;
     return MVF_OK;
 }
 
@@ -336,7 +336,8 @@ int launch_batched(const mvf_tape *t, int mode, int chunk, bool rev, bool spec, 
         HIP_TRY(launch_batch_plan(A, stream));
         BatchKArgs K{tape_args(t, mode, 0), A};
         void *params[] = {&K};
-        HIP_TRY(hipModuleLaunchKernel(t->spec_batch_fn, grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr));
+        HIP_TRY(hipModuleLaunchKernel(t->spec_batch_fn[rev], grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params,
+                                      nullptr));
         HIP_TRY(launch_batch_finish(A, m, max_nodes, stream));
         return MVF_OK;
     }
@@ -496,10 +497,9 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     int chunk;
     rc = resolve_grad(t, a->mode, a->grad, a->tuning, &rev, &chunk);
     if (rc != MVF_OK) return rc;
-    if (a->engine == MVF_ENGINE_SPEC && (rev || !t->spec_fn))
-        return set_err(MVF_EINVAL, rev ? "the specialised kernel is forward mode only"
-                                       : "no specialised kernel: call mvf_tape_specialize first");
-    const bool spec = !rev && t->spec_fn && a->engine != MVF_ENGINE_INTERP;
+    if (a->engine == MVF_ENGINE_SPEC && !t->spec_fn[rev])
+        return set_err(MVF_EINVAL, "no specialised kernel for this gradient mode: see mvf_tape_specialize");
+    const bool spec = t->spec_fn[rev] && a->engine != MVF_ENGINE_INTERP;
     const int grid = single_grid(t, S, rev);
     const SingleLayout L = single_layout(t, grid, rev, tt);
     if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
@@ -533,7 +533,8 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     if (spec) {
         BoundKArgs K{T, B};
         void *params[] = {&K};
-        hipError_t e = hipModuleLaunchKernel(t->spec_fn, grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr);
+        hipError_t e =
+            hipModuleLaunchKernel(t->spec_fn[rev], grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr);
         if (e != hipSuccess) return hip_err(e, "hipModuleLaunchKernel (specialised kernel)");
         e = launch_finish(B, grid, m, stream);
         if (e != hipSuccess) return hip_err(e, "finish kernel");
@@ -558,25 +559,32 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     mvf_spec_info in{};
     bool cached = false;
     const auto t0 = std::chrono::steady_clock::now();
-    rc = spec_compile(spec_source(t->C, chunk, waves), prop.gcnArchName, opt && opt->use_cache, code, &cached,
+    const int grad = opt ? opt->grad : MVF_GRAD_FWD;
+    rc = spec_compile(spec_source(t->C, chunk, waves, grad), prop.gcnArchName, opt && opt->use_cache, code, &cached,
                       &in.seconds);
     if (rc != MVF_OK) return rc;
     hipModule_t mod = nullptr;
-    hipFunction_t fn = nullptr;
     HIP_TRY(hipModuleLoadData(&mod, code.data()));
-    hipFunction_t bfn = nullptr;
-    hipError_t e = hipModuleGetFunction(&fn, mod, "mvf_spec_bound");
-    if (e == hipSuccess) e = hipModuleGetFunction(&bfn, mod, "mvf_spec_batch");
+    hipFunction_t fns[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};    // [rev][batched]
+    const char *names[2][2] = {{"mvf_spec_bound", "mvf_spec_batch"}, {"mvf_spec_bound_rev", "mvf_spec_batch_rev"}};
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < 2 && e == hipSuccess; ++r) {
+        if ((r == 0 && grad == MVF_GRAD_REV) || (r == 1 && grad == MVF_GRAD_FWD)) continue;
+        for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipModuleGetFunction(&fns[r][b], mod, names[r][b]);
+    }
     if (e != hipSuccess) {
         hipModuleUnload(mod);
         return hip_err(e, "hipModuleGetFunction");
     }
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     t->spec_mod = mod;
-    t->spec_fn = fn;
-    t->spec_batch_fn = bfn;
+    for (int r = 0; r < 2; ++r) {
+        t->spec_fn[r] = fns[r][0];
+        t->spec_batch_fn[r] = fns[r][1];
+    }
     in.chunk = chunk;
     in.waves = waves;
+    in.grad = grad;
     in.code_units = units;
     in.code_bytes = (int64_t)code.size();
     in.from_cache = cached ? 1 : 0;
@@ -601,10 +609,12 @@ int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
     std::vector<char> code;
     bool cached = false;
     mvf_spec_info in{};
-    rc = spec_compile(spec_source(C, chunk, waves), "gfx950", false, code, &cached, &in.seconds);
+    const int grad = opt ? opt->grad : MVF_GRAD_FWD;
+    rc = spec_compile(spec_source(C, chunk, waves, grad), "gfx950", false, code, &cached, &in.seconds);
     if (rc != MVF_OK) return rc;
     in.chunk = chunk;
     in.waves = waves;
+    in.grad = grad;
     in.code_units = units;
     in.code_bytes = (int64_t)code.size();
     if (info) *info = in;
@@ -934,9 +944,10 @@ int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const 
         c.engine = MVF_ENGINE_INTERP;
         kernels.push_back(c);
     }
-    if (t->spec_batch_fn) {
+    for (int r = 0; r < 2; ++r) {
+        if (!t->spec_batch_fn[r]) continue;
         mvf_tuning c{};
-        c.grad = MVF_GRAD_FWD;
+        c.grad = r ? MVF_GRAD_REV : MVF_GRAD_FWD;
         c.engine = MVF_ENGINE_SPEC;
         kernels.push_back(c);
     }

@@ -39,12 +39,13 @@ constexpr int64_t DEFAULT_MAX_CODE = 6000;      // instruction-passes (compile t
 constexpr int SEGMENT = 32;                      // instructions per guarded block
 
 struct Dec {
-    uint32_t op, ak, bk, a, b, d;
+    uint32_t w0, op, ak, bk, a, b, d;
     double k;
 };
 
 Dec decode(const Instr &I) {
     Dec D;
+    D.w0 = I.w0;
     D.op = I.w0 & 31u;
     D.ak = (I.w0 >> 5) & 3u;
     D.bk = (I.w0 >> 7) & 3u;
@@ -63,11 +64,13 @@ std::string lit(double x) {               // exact double literal
 
 // One pass over one root program.  C == 0: values only, variables at the
 // centre (point) or over the subdomain; C > 0: values and the tangent
-// components [c0, c0 + C).
+// components [c0, c0 + C).  With tape (C == 0 over the subdomain) the value
+// pass also computes the local partials the reverse sweep needs (those the
+// interpreter writes to its record tape), and reverse() then emits the sweep.
 class PassWriter {
   public:
-    PassWriter(const Compiled &Cp, int root, int C, int c0, bool point)
-        : P(Cp), r(root), C(C), c0(c0), point(point) {}
+    PassWriter(const Compiled &Cp, int root, int C, int c0, bool point, bool tape = false)
+        : P(Cp), r(root), C(C), c0(c0), point(point), tape(tape) {}
 
     // body lines (declarations first, then guarded blocks) and the names of
     // the result's value and components
@@ -76,24 +79,110 @@ class PassWriter {
         const RootProg &rp = P.roots[r];
         slot_val.assign(std::max(rp.n_slots, 1) + 1, "");
         slot_tan.assign(slot_val.size(), std::vector<std::string>());
+        slot_prod.assign(slot_val.size(), -1);
         for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) instr(pc, decl, body);
         const int rs = rp.result_slot;
         val = slot_val.at(rs);
         tan = slot_tan.at(rs);
     }
 
+    // The reverse sweep after emit() with tape: the root's adjoint is [1, 1],
+    // instructions in reverse order, each contribution to a slot operand
+    // written at the operand's last use (its init flag) and accumulated
+    // otherwise, contributions to variables accumulated into G[i] in sweep
+    // order (the interpreter's reverse_sweep, with records read from the
+    // value pass's variables).
+    void reverse(std::vector<std::string> &decl, std::vector<std::string> &body) {
+        const RootProg &rp = P.roots[r];
+        for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) decl.push_back("Iv y" + std::to_string(pc) + ";");
+        body.push_back("y" + std::to_string(slot_prod.at(rp.result_slot)) + " = kOne;");
+        for (auto it = steps.rbegin(); it != steps.rend(); ++it) {
+            const Step &st = *it;
+            const Dec &I = st.I;
+            const std::string pc = std::to_string(st.pc), zb = "y" + pc;
+            const bool ia = (I.w0 & W0_INIT_A) != 0, ib = (I.w0 & W0_INIT_B) != 0;
+            std::string s;
+            auto contribute = [&](uint32_t kind, uint32_t a, int prod, bool init, bool neg, const std::string &c) {
+                if (kind == K_SLOT) {
+                    const std::string y = "y" + std::to_string(prod);
+                    if (init) s += y + " = " + (neg ? "ineg(" + c + ")" : c) + "; ";
+                    else s += y + " = " + (neg ? "isub(" : "iadd(") + y + ", " + c + "); ";
+                } else if (kind == K_VAR) {
+                    const std::string g = "G[" + std::to_string(a) + "]";
+                    s += g + " = " + (neg ? "isub(" : "iadd(") + g + ", " + c + "); ";
+                }
+            };
+            switch (I.op) {
+            case I_ADD:
+            case I_SUB:
+                contribute(I.ak, I.a, st.pa, ia, false, zb);
+                contribute(I.bk, I.b, st.pb, ib, I.op == I_SUB, zb);
+                break;
+            case I_MUL:
+                if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, "imul(" + zb + ", " + st.V + ")");
+                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, false, "imul(" + zb + ", " + st.U + ")");
+                break;
+            case I_DIV: {
+                const std::string T = "t" + pc;
+                decl.push_back("Iv " + T + ";");
+                s += T + " = imul(" + zb + ", r" + pc + "); ";
+                contribute(I.ak, I.a, st.pa, ia, false, T);
+                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, true, "imul(" + T + ", v" + pc + ")");
+                break;
+            }
+            case I_SQR:
+            case I_SQRT:
+            case I_EXP:
+            case I_LOG:
+                if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, "imul(" + zb + ", q" + pc + ")");
+                break;
+            case I_ADDK:
+            case I_KSUB:
+            case I_LOAD:
+                contribute(I.ak, I.a, st.pa, ia, I.op == I_KSUB, zb);
+                break;
+            case I_MULK:
+            case I_MULKN:
+                contribute(I.ak, I.a, st.pa, ia, false,
+                           "imulk(" + (I.op == I_MULKN ? "ineg(" + zb + ")" : zb) + ", " + lit(I.k) + ")");
+                break;
+            default:   // I_DIVK, I_DIVKN
+                contribute(I.ak, I.a, st.pa, ia, false,
+                           "imul_pos(" + (I.op == I_DIVKN ? "ineg(" + zb + ")" : zb) + ", " + st.aux + ")");
+                break;
+            }
+            body.push_back(s);
+        }
+    }
+
   private:
     const Compiled &P;
     int r, C, c0;
-    bool point;
+    bool point, tape;
     std::vector<std::string> slot_val;
     std::vector<std::vector<std::string>> slot_tan;
+    std::vector<int> slot_prod;                  // instruction that wrote the slot's current value
+    struct Step {
+        int pc;
+        Dec I;
+        std::string U, V, aux;                   // operand value expressions; 1/k enclosure of a DIVK
+        int pa, pb;                              // producers of slot operands
+    };
+    std::vector<Step> steps;
 
     void ensure(size_t s) {
         if (s >= slot_val.size()) {
             slot_val.resize(s + 1);
             slot_tan.resize(s + 1);
+            slot_prod.resize(s + 1, -1);
         }
+    }
+
+    static std::string aux_literal(const Instr &aux) {
+        uint64_t bits = (uint64_t)aux.w1 << 32 | aux.w0;
+        double rlo;
+        std::memcpy(&rlo, &bits, 8);
+        return "Iv{" + lit(rlo) + ", " + lit(aux.k) + "}";
     }
 
     // operand: value expression; components (dense), or the hit component of
@@ -125,6 +214,12 @@ class PassWriter {
         int ha = -1, hb = -1;
         fetch(I.ak, I.a, I.k, U, A, ad, ha);
         if (I.op <= I_DIV) fetch(I.bk, I.b, I.k, V, B, bd, hb);
+        if (tape) {
+            Step st{pc, I, U, V, "", I.ak == K_SLOT ? slot_prod.at(I.a) : -1,
+                    I.op <= I_DIV && I.bk == K_SLOT ? slot_prod.at(I.b) : -1};
+            if (I.op == I_DIVK || I.op == I_DIVKN) st.aux = aux_literal(P.instr.at(I.b));
+            steps.push_back(st);
+        }
         const std::string z = "v" + std::to_string(pc);
         std::string s;                                   // the statements of this instruction
         std::vector<std::string> Z(C, "kZero");
@@ -158,10 +253,13 @@ class PassWriter {
             decl.push_back("Iv " + tv + ";");
             s += tv + " = " + V + "; bad |= (" + tv + ".lo <= 0.0 && " + tv + ".nh <= 0.0) ? 1u : 0u; ";
             s += z + " = idiv(" + U + ", " + tv + ");";
-            if (C > 0) {
+            if (C > 0 || tape) {
                 const std::string R = "r" + std::to_string(pc);
                 decl.push_back("Iv " + R + ";");
                 s += " " + R + " = irecip(" + tv + ");";
+            }
+            if (C > 0) {
+                const std::string R = "r" + std::to_string(pc);
                 if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
                 if (bd) for (int t = 0; t < C; ++t) Z[t] = "isub(" + Z[t] + ", imul(" + z + ", " + B[t] + "))";
                 at_hit(ha, "iadd(@, kOne)");
@@ -192,9 +290,11 @@ class PassWriter {
                 s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; " + z + " = ilog(" + tu + ");";
                 dexpr = "irecip(" + tu + ")";
             }
-            if (C > 0) {
+            if (C > 0 || tape) {
                 decl.push_back("Iv " + D + ";");
                 s += " " + D + " = " + dexpr + ";";
+            }
+            if (C > 0) {
                 if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul(" + D + ", " + A[t] + ")";
                 if (ha >= 0) Z[ha] = D;
             }
@@ -228,11 +328,7 @@ class PassWriter {
             auto sg = [&](const std::string &x) { return ng ? "ineg(" + x + ")" : x; };
             s += z + " = idivk(" + sg(U) + ", " + k + ");";
             if (C > 0) {
-                const Instr &aux = P.instr.at(I.b);
-                uint64_t bits = (uint64_t)aux.w1 << 32 | aux.w0;
-                double rlo;
-                std::memcpy(&rlo, &bits, 8);
-                const std::string R = "Iv{" + lit(rlo) + ", " + lit(aux.k) + "}";
+                const std::string R = aux_literal(P.instr.at(I.b));
                 if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul_pos(" + sg(A[t]) + ", " + R + ")";
                 if (ha >= 0) Z[ha] = "imul_pos(" + sg("kOne") + ", " + R + ")";
             }
@@ -250,8 +346,34 @@ class PassWriter {
         ensure(I.d);
         slot_val[I.d] = z;
         slot_tan[I.d] = tn;
+        slot_prod[I.d] = pc;
     }
 };
+
+void write_guarded(std::string &out, const std::vector<std::string> &body) {
+    for (size_t i = 0; i < body.size(); i += SEGMENT) {
+        out += "    if (go) {\n";
+        for (size_t j = i; j < std::min(body.size(), i + SEGMENT); ++j) out += "        " + body[j] + "\n";
+        out += "    }\n";
+    }
+}
+
+// the value pass with its local partials and the reverse sweep of one root:
+// returns the NIE value, G[0..n) receives the interval gradient
+void write_adjoint(std::string &out, const Compiled &P, int r, const std::string &name) {
+    std::vector<std::string> decl, fwd, rev, tan;
+    std::string val;
+    PassWriter w(P, r, 0, 0, false, true);
+    w.emit(decl, fwd, val, tan);
+    w.reverse(decl, rev);
+    out += "__device__ __forceinline__ Iv " + name + "(const SpecLane &L, bool go, uint32_t &bad, Iv (&G)[" +
+           std::to_string(P.n_vars) + "]) {\n";
+    for (const auto &d : decl) out += "    " + d + "\n";
+    write_guarded(out, fwd);
+    for (int i = 0; i < P.n_vars; ++i) out += "    G[" + std::to_string(i) + "] = kZero;\n";
+    write_guarded(out, rev);
+    out += "    return " + val + ";\n}\n";
+}
 
 // a pass as a function: C == 0 returns the value; C > 0 also writes G[0..C)
 void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool point, const std::string &name) {
@@ -262,11 +384,7 @@ void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool 
     if (C > 0) out += ", Iv (&G)[" + std::to_string(C) + "]";
     out += ") {\n";
     for (const auto &d : decl) out += "    " + d + "\n";
-    for (size_t i = 0; i < body.size(); i += SEGMENT) {
-        out += "    if (go) {\n";
-        for (size_t j = i; j < std::min(body.size(), i + SEGMENT); ++j) out += "        " + body[j] + "\n";
-        out += "    }\n";
-    }
+    write_guarded(out, body);
     for (int t = 0; t < C; ++t) out += "    G[" + std::to_string(t) + "] = " + tan[t] + ";\n";
     out += "    return " + val + ";\n}\n";
 }
@@ -275,6 +393,9 @@ void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool 
 
 int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_t *units) {
     const int n = P.n_vars;
+    const int grad = opt ? opt->grad : MVF_GRAD_FWD;
+    if (grad < MVF_GRAD_FWD || grad > MVF_GRAD_AUTO) return set_error(MVF_EINVAL, "bad grad");
+    const bool fwd = grad != MVF_GRAD_REV, rev = grad != MVF_GRAD_FWD;
     int c = opt && opt->chunk > 0 ? opt->chunk : 0;
     if (c == 0) {
         const int passes = (n + 2) / 3;
@@ -282,8 +403,8 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     }
     if (c < 1 || c > n) return set_error(MVF_EINVAL, "chunk out of range [1, n]");
     const int passes = (n + c - 1) / c;
-    int64_t u = 0;
-    for (const auto &rp : P.roots) u += (int64_t)rp.len * (2 + passes);
+    int64_t u = 0;     // point and value passes, tangent passes, the adjoint's value pass and sweep
+    for (const auto &rp : P.roots) u += (int64_t)rp.len * (2 + (fwd ? passes : 0) + (rev ? 2 : 0));
     const int64_t cap = opt && opt->max_code > 0 ? opt->max_code : DEFAULT_MAX_CODE;
     *chunk = c;
     *units = u;
@@ -293,24 +414,57 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     return MVF_OK;
 }
 
-std::string spec_source(const Compiled &P, int chunk, int waves) {
+std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
     const int n = P.n_vars, m = (int)P.roots.size();
+    const bool fwd = grad != MVF_GRAD_REV, rev = grad != MVF_GRAD_FWD;
     std::string s;
-    s += "// generated: specialised bounding kernel, " + std::to_string(n) + " variables, " + std::to_string(m) +
-         " roots, " + std::to_string(chunk) + " tangent components per pass\n";
+    s += "// generated: specialised bounding kernels, " + std::to_string(n) + " variables, " + std::to_string(m) +
+         " roots" + (fwd ? ", tangent mode with " + std::to_string(chunk) + " components per pass" : "") +
+         (rev ? ", reverse-mode adjoint" : "") + "\n";
     s += "#define MVF_SPEC_WAVES " + std::to_string(waves) + "\n";
+    if (fwd) s += "#define MVF_SPEC_FWD 1\n";
+    if (rev) s += "#define MVF_SPEC_REV 1\n";
     s += "#include \"mvf_spec.h\"\nnamespace mvf {\nnamespace dev {\nnamespace spec {\n";
     s += "constexpr int N_VARS = " + std::to_string(n) + ", N_ROOTS = " + std::to_string(m) + ";\n";
+    s += "template <bool REV>\n__device__ uint32_t lane(const SpecLane &L, int mode, bool go, const LaneOut &o, "
+         "FeasTrack &F);\n";
     for (int r = 0; r < m; ++r) {
         write_pass(s, P, r, 0, 0, true, "point_" + std::to_string(r));
         write_pass(s, P, r, 0, 0, false, "value_" + std::to_string(r));
-        for (int c0 = 0; c0 < n; c0 += chunk)
-            write_pass(s, P, r, std::min(chunk, n - c0), c0, false,
-                       "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
+        if (fwd)
+            for (int c0 = 0; c0 < n; c0 += chunk)
+                write_pass(s, P, r, std::min(chunk, n - c0), c0, false,
+                           "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
+        if (rev) write_adjoint(s, P, r, "adjoint_" + std::to_string(r));
+    }
+    if (rev) {
+        // every root in turn, as the interpreter's bound_lane with the reverse-mode adjoint
+        s += "template <>\n__device__ __forceinline__ uint32_t lane<true>(const SpecLane &L, int mode, bool go, "
+             "const LaneOut &o, FeasTrack &F) {\n    uint32_t bad = 0;\n";
+        for (int r = 0; r < m; ++r) {
+            const std::string R = std::to_string(r);
+            s += "    {\n        Iv B, FC = kZero;\n";
+            s += "        if (mode == MVF_MODE_NIE) {\n            B = value_" + R + "(L, go, bad);\n        } else {\n";
+            s += "            FC = point_" + R + "(L, go, bad);\n";
+            s += "            Iv G[N_VARS];\n            const Iv nie = adjoint_" + R + "(L, go, bad, G);\n";
+            s += "            Iv acc = FC;\n";
+            for (int i = 0; i < n; ++i)
+                s += "            acc = iadd(acc, imul(G[" + std::to_string(i) + "], spec_dx(L, " + std::to_string(i) +
+                     ")));\n";
+            s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";
+            s += "        }\n        if (B.lo != B.lo || B.nh != B.nh) bad = 1;\n";
+            s += "        reduce_root(" + R + ", N_ROOTS, B, o);\n";
+            s += "        track_root(F, " + R + ", B, FC, mode != MVF_MODE_NIE, o);\n    }\n";
+        }
+        s += "    return bad;\n}\n";
+    }
+    if (!fwd) {
+        s += "}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n#include \"mvf_spec_kernel.h\"\n";
+        return s;
     }
     // every root in turn, as the interpreter's bound_lane with tangent passes
-    s += "__device__ __forceinline__ uint32_t lane_bounds(const SpecLane &L, int mode, bool go, const LaneOut &o, "
-         "FeasTrack &F) {\n    uint32_t bad = 0;\n";
+    s += "template <>\n__device__ __forceinline__ uint32_t lane<false>(const SpecLane &L, int mode, bool go, "
+         "const LaneOut &o, FeasTrack &F) {\n    uint32_t bad = 0;\n";
     for (int r = 0; r < m; ++r) {
         const std::string R = std::to_string(r);
         s += "    {\n        Iv B, FC = kZero;\n";

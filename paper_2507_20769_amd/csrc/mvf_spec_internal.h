@@ -12,8 +12,9 @@ namespace mvf {
 // program lengths times passes per root); MVF_ELIMIT above the size limit.
 int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_t *units);
 
-// The generated device source (compiled with the embedded device headers).
-std::string spec_source(const Compiled &P, int chunk, int waves);
+// The generated device source (compiled with the embedded device headers):
+// forward kernels (grad FWD), reverse-mode kernels (REV) or both (AUTO).
+std::string spec_source(const Compiled &P, int chunk, int waves, int grad);
 
 // hiprtc compilation for `arch` (or the on-disk cache's copy).
 int spec_compile(const std::string &src, const std::string &arch, bool use_cache, std::vector<char> &code,

@@ -1,21 +1,23 @@
-// mvf_spec_kernel.h -- the specialised bounding kernels (one node box; many nodes).
+// mvf_spec_kernel.h -- the specialised bounding kernels (one node box; many
+// nodes), in tangent mode and with the reverse-mode adjoint.
 //
 // Compiled at run time after the generated namespace spec, which provides
-// N_VARS, N_ROOTS and lane_bounds() (every root's bound on one lane's
-// subdomain, folded into the wave's reduction record).  Launch shape,
-// arguments, LDS reduction records and partials are those of the
-// interpreter's single-box and batched kernels, so their finish kernels
-// complete Step 3.
+// N_VARS, N_ROOTS and lane<REV>() (every root's bound on one lane's
+// subdomain, folded into the wave's reduction record) for the modes it was
+// generated for (MVF_SPEC_FWD, MVF_SPEC_REV).  Launch shape, arguments, LDS
+// reduction records and partials are those of the interpreter's single-box
+// and batched kernels, so their finish kernels complete Step 3.
 #pragma once
 
 #ifndef MVF_SPEC_WAVES
 #define MVF_SPEC_WAVES 2
 #endif
 
-extern "C" __global__ __launch_bounds__(mvf::BLK) __attribute__((amdgpu_waves_per_eu(MVF_SPEC_WAVES, MVF_SPEC_WAVES)))
-void mvf_spec_bound(mvf::BoundKArgs /* read through kargs() */) {
-    using namespace mvf;
-    using namespace mvf::dev;
+namespace mvf {
+namespace dev {
+
+template <bool REV>
+__device__ __forceinline__ void spec_bound_body() {
     constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
     extern __shared__ __align__(16) uint8_t smem[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -65,7 +67,7 @@ void mvf_spec_bound(mvf::BoundKArgs /* read through kargs() */) {
             o.ineq = K->T.ineq_mask;
             o.eq = K->T.eq_mask;
             mode_round_down();
-            bad = spec::lane_bounds(L, K->T.mode, go, o, F);
+            bad = spec::lane<REV>(L, K->T.mode, go, o, F);
             mode_round_nearest();
         }
         finish_lane(m, bad, F, o, kargs<BoundKArgs>()->B.flags);
@@ -82,10 +84,8 @@ void mvf_spec_bound(mvf::BoundKArgs /* read through kargs() */) {
 // subdomains of one node) from the plan kernel's counter, as the
 // interpreter's batch kernel does, and leave one partial per item for the
 // per-node finish kernel.
-extern "C" __global__ __launch_bounds__(mvf::BLK) __attribute__((amdgpu_waves_per_eu(MVF_SPEC_WAVES, MVF_SPEC_WAVES)))
-void mvf_spec_batch(mvf::BatchKArgs /* read through kargs() */) {
-    using namespace mvf;
-    using namespace mvf::dev;
+template <bool REV>
+__device__ __forceinline__ void spec_batch_body() {
     constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int64_t sh_item;
@@ -170,7 +170,7 @@ void mvf_spec_batch(mvf::BatchKArgs /* read through kargs() */) {
                 o.ineq = K->T.ineq_mask;
                 o.eq = K->T.eq_mask;
                 mode_round_down();
-                bad = spec::lane_bounds(L, K->T.mode, go, o, F);
+                bad = spec::lane<REV>(L, K->T.mode, go, o, F);
                 mode_round_nearest();
             }
             finish_lane(m, bad, F, o, nullptr);
@@ -183,3 +183,20 @@ void mvf_spec_batch(mvf::BatchKArgs /* read through kargs() */) {
         }
     }
 }
+
+}  // namespace dev
+}  // namespace mvf
+
+#define MVF_SPEC_KERNEL(name, KA, body)                                                                     \
+    extern "C" __global__ __launch_bounds__(mvf::BLK)                                                       \
+        __attribute__((amdgpu_waves_per_eu(MVF_SPEC_WAVES, MVF_SPEC_WAVES))) void name(mvf::KA) {          \
+        body;                                                                                               \
+    }
+#ifdef MVF_SPEC_FWD
+MVF_SPEC_KERNEL(mvf_spec_bound, BoundKArgs, mvf::dev::spec_bound_body<false>())
+MVF_SPEC_KERNEL(mvf_spec_batch, BatchKArgs, mvf::dev::spec_batch_body<false>())
+#endif
+#ifdef MVF_SPEC_REV
+MVF_SPEC_KERNEL(mvf_spec_bound_rev, BoundKArgs, mvf::dev::spec_bound_body<true>())
+MVF_SPEC_KERNEL(mvf_spec_batch_rev, BatchKArgs, mvf::dev::spec_batch_body<true>())
+#endif

@@ -82,11 +82,12 @@ class BoundArgs(ctypes.Structure):
 
 class SpecOptions(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("max_code", ctypes.c_int64),
-                ("use_cache", ctypes.c_int32)]
+                ("use_cache", ctypes.c_int32), ("grad", ctypes.c_int32)]
 
 
 class SpecInfo(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("code_units", ctypes.c_int64),
+    _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("grad", ctypes.c_int32),
+                ("code_units", ctypes.c_int64),
                 ("code_bytes", ctypes.c_int64), ("seconds", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
@@ -209,12 +210,13 @@ def check(tape) -> TapeStats:
     return st
 
 
-def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0) -> dict:
-    """Generate and compile the specialised kernel of a tape for gfx950 on the
+def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0, grad: str = "fwd") -> dict:
+    """Generate and compile the specialised kernels of a tape for gfx950 on the
     host (no device, no cache); returns the mvf_spec_info fields."""
     keep, args = _tape_arrays(tape)
     info = SpecInfo()
-    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0)), ctypes.byref(info))
+    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0, MVF_GRAD[grad])),
+                              ctypes.byref(info))
     if rc != 0:
         raise MVFError(rc, "mvf_spec_check")
     return info.as_dict()
@@ -249,10 +251,12 @@ class Tape:
             raise MVFError(rc, "mvf_tape_set_root_kinds")
         return self
 
-    def specialize(self, chunk: int = 0, waves: int = 0, max_code: int = 0, cache: bool = True) -> dict:
-        """Build the tape's specialised forward kernel (mvf_tape_specialize)."""
+    def specialize(self, chunk: int = 0, waves: int = 0, max_code: int = 0, cache: bool = True,
+                   grad: str = "fwd") -> dict:
+        """Build the tape's specialised kernels (mvf_tape_specialize); grad "fwd", "rev" or "auto" (both)."""
         info = SpecInfo()
-        rc = lib().mvf_tape_specialize(self.handle, ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache))),
+        rc = lib().mvf_tape_specialize(self.handle,
+                                       ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache), MVF_GRAD[grad])),
                                        ctypes.byref(info))
         if rc != 0:
             raise MVFError(rc, "mvf_tape_specialize")

@@ -39,7 +39,7 @@ def _tuning(grad, spl, engine, grid=0):
 
 @pytest.mark.parametrize("grad,spl,engine", [("fwd", 2, "interp"), ("fwd", 4, "interp"), ("rev", 2, "interp"),
                                              ("rev", 4, "interp"), ("fwd", 1, "spec"), ("fwd", 2, "spec"),
-                                             ("fwd", 4, "spec")])
+                                             ("fwd", 4, "spec"), ("rev", 1, "spec"), ("rev", 4, "spec")])
 def test_batched_configurations_equal_per_node(grad, spl, engine):
     import torch
     from paper_2507_20769_amd import mvf
@@ -48,7 +48,7 @@ def test_batched_configurations_equal_per_node(grad, spl, engine):
     h = mvf.Tape(tape)
     h.set_root_kinds([0] + [1] * (tape.n_roots - 1))
     if engine == "spec":
-        h.specialize()
+        h.specialize(grad="auto")
     print(f"[case] grad={grad} spl={spl} engine={engine}", flush=True)
     tu = _tuning(0 if grad == "fwd" else 1, spl, engine, grid=37)   # an odd grid: items wrap unevenly
     out = mvf.bound_batch(h, torch.tensor(bw.boxes, device="cuda"), torch.tensor(bw.splits, device="cuda"),
@@ -92,7 +92,7 @@ def test_autotuner_considers_the_specialised_kernel():
     from paper_2507_20769_amd import mvf
     bw = I.small_batch(23, 16, k_range=(6, 11))
     h = mvf.Tape(bw.tape)
-    h.specialize()
+    h.specialize(grad="auto")
     boxes = torch.tensor(bw.boxes, device="cuda")
     splits = torch.tensor(bw.splits, device="cuda")
     tu = mvf.autotune(h, boxes, splits, mode="both")
@@ -123,9 +123,13 @@ def test_batched_engine_errors():
         with pytest.raises(mvf.MVFError) as e:
             mvf.bound_batch(h, boxes, splits, grad=grad, tuning=tu)
         assert e.value.code == -1
-    h.specialize()
+    h.specialize()                                         # tangent mode only
     with pytest.raises(mvf.MVFError) as e:
         mvf.bound_batch(h, boxes, splits, grad="rev", tuning=_tuning(1, 1, "spec"))
+    assert e.value.code == -1
+    h.specialize(grad="rev")                               # adjoint only
+    with pytest.raises(mvf.MVFError) as e:
+        mvf.bound_batch(h, boxes, splits, grad="fwd", tuning=_tuning(0, 1, "spec"))
     assert e.value.code == -1
     h.close()
 

@@ -30,11 +30,12 @@ def _handle(tape, kinds=None, **spec):
     return h
 
 
-def _compare(h, tape, box, splits, mode="both", kinds=None):
-    print(f"[case] n={tape.n_vars} nodes={tape.n_nodes} splits={list(splits)} mode={mode}", flush=True)
-    g = gpu_bound(tape, box, splits, mode=mode, handle=h, engine="spec")
-    gi = gpu_bound(tape, box, splits, mode=mode, handle=h, engine="interp")
-    o = O.bound(tape, box, splits, mode=MODES[mode], nthreads=8, kinds=kinds)
+def _compare(h, tape, box, splits, mode="both", kinds=None, grad="fwd"):
+    print(f"[case] n={tape.n_vars} nodes={tape.n_nodes} splits={list(splits)} mode={mode} grad={grad}", flush=True)
+    g = gpu_bound(tape, box, splits, mode=mode, grad=grad, handle=h, engine="spec")
+    gi = gpu_bound(tape, box, splits, mode=mode, grad=grad, handle=h, engine="interp")
+    o = O.bound(tape, box, splits, mode=MODES[mode], grad=O.GRAD_FWD if grad == "fwd" else O.GRAD_REV, nthreads=8,
+                kinds=kinds)
     exact = not has_transcendental(tape)
     sc = scale_of(O.bound(tape, box, splits, mode=O.MODE_NIE, per_sub=False, nthreads=8)["reduced"])
     assert_parity(g["per_sub"], o["per_sub"], exact, sc, "per_sub vs oracle")
@@ -156,11 +157,53 @@ def test_engine_selection_errors():
     assert e.value.code == -1
     h.specialize()
     with pytest.raises(mvf.MVFError) as e:
-        mvf.bound(h, box, [8], grad="rev", engine="spec")  # forward mode only
+        mvf.bound(h, box, [8], grad="rev", engine="spec")  # built for tangent mode only
     assert e.value.code == -1
     mvf.bound(h, box, [8], grad="rev")                     # auto: reverse mode interprets
     a = mvf.bound(h, box, [8], grad="fwd")                 # auto: the specialised kernel
     b = mvf.bound(h, box, [8], grad="fwd", engine="interp")
     torch.cuda.synchronize()
     assert torch.equal(a["reduced"], b["reduced"]) and torch.equal(a["argmin"], b["argmin"])
+    h.close()
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_reverse_specialised_rational_and_small_cases(seed):
+    # the adjoint kernels (grad "rev"/"auto") against the oracle's reverse mode and bitwise
+    # against the interpreter's adjoint
+    rng = np.random.default_rng(seed)
+    t = _rational(I.random_small_tape(seed, n=3, ops=60, n_con=2, con_ops=20, window=8))
+    kinds = [0, 1, 2]
+    h = _handle(t, kinds, grad="auto")
+    box = np.array([[-2.0, 2.0], [-1.5, 2.5], [-2.0, 1.0]]) + rng.uniform(-0.3, 0.3, (3, 1))
+    for mode in MODES:
+        _compare(h, t, box, [5, 7, 11], mode, kinds, grad="rev")
+    h.close()
+    if seed == 1:
+        for tape, box, splits in ((I.cubic_tape(), np.array([[-1.0, 2.0]]), [256]),
+                                  (I.tiny(1).tape, I.tiny(1).box, I.tiny(1).splits),
+                                  (I.peaks_tape(), np.array([[-3.0, 3.0], [-3.0, 3.0]]), [40, 37])):
+            h = _handle(tape, grad="rev")
+            _compare(h, tape, box, splits, "both", grad="rev")
+            h.close()
+
+
+def test_reverse_specialised_exp_log_and_mid():
+    t = I.random_small_tape(4, n=4, ops=80, n_con=3, con_ops=25, window=8)
+    h = _handle(t, grad="rev")
+    _compare(h, t, np.array([[-2.0, 2.0]] * 4), [4, 5, 3, 6], "both", grad="rev")
+    h.close()
+    w = I.mid(1)
+    kinds = [0, 1, 1, 1]
+    h = _handle(w.tape, kinds, grad="rev")
+    g = gpu_bound(w.tape, w.box, w.splits, mode="both", grad="rev", handle=h, engine="spec")
+    gi = gpu_bound(w.tape, w.box, w.splits, mode="both", grad="rev", handle=h, engine="interp")
+    S = w.n_sub
+    ks = np.unique(np.concatenate([np.random.default_rng(1).choice(S, 300, replace=False), [0, S - 1]]))
+    o = O.bound(w.tape, w.box, w.splits, mode=O.MODE_BOTH, grad=O.GRAD_REV, ks=ks, nthreads=8, kinds=kinds)
+    sc = scale_of(O.bound(w.tape, w.box, w.splits, mode=O.MODE_NIE, ks=ks, per_sub=False, nthreads=8)["reduced"])
+    exact = not has_transcendental(w.tape)
+    assert_parity(g["per_sub"][:, :, ks], o["per_sub"], exact, sc, "mid adjoint sampled vs oracle")
+    assert_parity(g["per_sub"], gi["per_sub"], exact, sc, "mid adjoint vs interpreter")
+    assert not g["flags"].any()
     h.close()
