@@ -18,8 +18,9 @@ a 400-op objective and two 150-op constraints):
   * adjoint+batched -- reverse-mode adjoint, all nodes in one persistent
                 launch replayed from a HIP graph (staging H2D and result D2H
                 inside the graph),
-and the reverse-mode rate on the mid and 32-variable differentiation
-workloads.  ``value`` is subdomain-bounds/s (one subdomain-bound = the bounds
+each with the interpreter and with the specialised kernels; the forward and
+adjoint rates of both kernel kinds on mid; the adjoint on the 32-variable
+differentiation workload; and the end-to-end branch and bound.  ``value`` is subdomain-bounds/s (one subdomain-bound = the bounds
 of the objective and all constraints on one subdomain).  ``roofline`` relates
 the bounding kernel to the FP64 VALU issue rate; ``cpu_baseline`` times the
 CPU oracle on a bounded sample.
@@ -44,7 +45,7 @@ FP64_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9          # 39.3e12 op/s
 FP64_PUBLISHED_PEAK = 78.6e12
 # HBM bytes per launch of the headline kernel from rocprofv3 counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00,
 # the factors from a 256 MiB copy in the same runs), valid for the kernel and tape they were taken on
-TRAFFIC = {("spec", "aa75c5b416e4faea"): (4504.5 * 2.0 + 5280.0) * 1024}
+TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea"): (4504.5 * 2.0 + 5280.0) * 1024}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 
@@ -60,6 +61,9 @@ def parse():
     ap.add_argument("--bnb-nodes", type=int, default=1000, help="B&B node limit of the e2e comparison (0: skip)")
     ap.add_argument("--engine", choices=["spec", "interp"], default="spec",
                     help="headline kernel: the tape's specialised kernel or the interpreter")
+    ap.add_argument("--grad", choices=["fwd", "rev"], default="fwd",
+                    help="gradient mode of the timed step (the headline configuration is forward mode; "
+                         "rev times the adjoint, for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device-to-device copy, the reference for HBM counters")
     return ap.parse_args()
@@ -99,44 +103,48 @@ def time_calls(launch, steps: int, warmup: int, stream) -> float:
     return e0.elapsed_time(e1) / steps
 
 
-def forms(seed: int, headline_engine: str) -> dict:
+def forms(seed: int, mid_tape) -> dict:
+    """The other kernels and forms.  mid_tape: the headline's tape handle,
+    specialised in both gradient modes."""
     import torch
 
     from paper_2507_20769_amd import inputs as I
     from paper_2507_20769_amd import mvf
     out = {}
     stream = torch.cuda.current_stream()
-    # the headline step with the other kernel
+    # mid: forward and adjoint, interpreter and specialised kernels
     w = I.mid(seed)
+    st = mid_tape.stats()
+    box = torch.tensor(w.box, device="cuda")
+    for grad, ref in (("fwd", st.ref_ops_fwd), ("rev", st.ref_ops_rev)):
+        for engine in ("interp", "spec"):
+            call = mvf.BoundCall(mid_tape, box, w.splits, mode="both", grad=grad, engine=engine)
+            ms = time_calls(call.launch, 20, 2, stream)
+            name = {"fwd": "forward", "rev": "adjoint"}[grad] + {"interp": "_interpreter", "spec": "_specialised"}[engine]
+            out[f"mid_{name}"] = {"subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms,
+                                  "ref_ops_per_subdomain": ref,
+                                  "issue_peak_frac": ref * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
+    # the 32-variable differentiation workload: adjoint, interpreter (its tape is far above the
+    # specialisation size limit)
+    w = I.diff(seed)
     h = mvf.Tape(w.tape)
-    other = "interp" if headline_engine == "spec" else "spec"
-    if other == "spec":
-        h.specialize()
-    call = mvf.BoundCall(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both", grad="fwd", engine=other)
-    ms = time_calls(call.launch, 20, 2, stream)
-    out[f"mid_forward_{'specialised' if other == 'spec' else 'interpreter'}"] = {
-        "subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms,
-        "issue_peak_frac": h.stats().ref_ops_fwd * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
+    st = h.stats()
+    call = mvf.BoundCall(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both", grad="rev")
+    ms = time_calls(call.launch, 4, 1, stream)
+    out["diff_adjoint_interpreter"] = {"subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms,
+                                       "subdomains": w.n_sub, "ref_ops_per_subdomain": st.ref_ops_rev,
+                                       "issue_peak_frac": st.ref_ops_rev * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
     h.close()
-    # reverse mode on mid and on the 32-variable differentiation workload
-    for name, steps in (("mid", 20), ("diff", 4)):
-        w = getattr(I, name)(seed)
-        h = mvf.Tape(w.tape)
-        st = h.stats()
-        call = mvf.BoundCall(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both", grad="rev")
-        ms = time_calls(call.launch, steps, 1, stream)
-        out[f"{name}_adjoint"] = {"subdomain_bounds_per_s": w.n_sub / (ms * 1e-3), "ms": ms, "subdomains": w.n_sub,
-                                  "ref_ops_per_subdomain": st.ref_ops_rev,
-                                  "issue_peak_frac": st.ref_ops_rev * w.n_sub / (ms * 1e-3) / FP64_ISSUE_PEAK}
-    # batch workload: plain forward per node vs adjoint + batched graph
+    # batch workload: plain forward per node vs batched graphs
     bw = I.batch(seed)
     h = mvf.Tape(bw.tape)
     st = h.stats()
     total = int(bw.n_sub.sum())
     boxes = torch.tensor(bw.boxes, device="cuda")
     red_plain = np.empty((len(bw.boxes), bw.tape.n_roots, 2))
-    spec_info = h.specialize()
+    spec_info = h.specialize(grad="auto")
     t_plain = {}
+    same_plain = None
     for engine in ("interp", "spec"):
         calls = [mvf.BoundCall(h, boxes[i], bw.splits[i], mode="both", grad="fwd", engine=engine)
                  for i in range(len(bw.boxes))]
@@ -154,40 +162,56 @@ def forms(seed: int, headline_engine: str) -> dict:
             red_plain[:] = red
         else:
             same_plain = float(np.mean(red == red_plain))   # the two kernels agree bitwise up to libm
-    g = mvf.BatchGraph(h, len(bw.boxes), total, mode="both", grad="rev")
     gs = torch.cuda.Stream()
+    t_graph, red_graph = {}, {}
+    for grad, engine in (("rev", "interp"), ("rev", "spec"), ("fwd", "spec")):
+        tu = mvf.Tuning(grad=0 if grad == "fwd" else 1, chunk=0, grid_blocks=0, best_ms=0.0, sub_per_lane=1,
+                        engine=mvf.MVF_ENGINE[engine])
+        g = mvf.BatchGraph(h, len(bw.boxes), total, mode="both", grad=grad, tuning=tu)
 
-    def batched():
-        g.launch(bw.boxes, bw.splits, stream=gs)
-        gs.synchronize()
-    batched()
-    reps = 5
-    t0 = time.perf_counter()
-    for _ in range(reps):
+        def batched():
+            g.launch(bw.boxes, bw.splits, stream=gs)
+            gs.synchronize()
         batched()
-    t_batched = (time.perf_counter() - t0) / reps
-    red_b, _, status = g.result()
-    # same accuracy: both pass parity with their own oracle mode; report how the two
-    # gradient enclosures compare on the objective lower bound
-    d = red_b[:, 0, 0] - red_plain[:, 0, 0]
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            batched()
+        t_graph[(grad, engine)] = (time.perf_counter() - t0) / reps
+        red_b, _, status = g.result()
+        assert (status == 0).all()
+        red_graph[(grad, engine)] = red_b
+        g.close()
+    # same accuracy: both gradient modes pass parity with their own oracle mode; report how the
+    # two gradient enclosures compare on the objective lower bound
+    d = red_graph[("rev", "spec")][:, 0, 0] - red_plain[:, 0, 0]
     scale = np.maximum(1.0, np.abs(red_plain[:, 0, :]).max(axis=1))
+    best_plain = min(t_plain.values())
     out["batch"] = {
-        "nodes": len(bw.boxes), "subdomains": total,
-        "plain_forward_per_node": {"subdomain_bounds_per_s": total / t_plain["interp"], "s": t_plain["interp"],
-                                   "tangent_chunk": st.tangent_chunk, "kernel": "interpreter"},
+        "nodes": len(bw.boxes), "subdomains": total, "specialisation_compile_s": spec_info["seconds"],
+        "plain_forward_per_node_interpreter": {"subdomain_bounds_per_s": total / t_plain["interp"],
+                                               "s": t_plain["interp"], "tangent_chunk": st.tangent_chunk},
         "plain_forward_per_node_specialised": {"subdomain_bounds_per_s": total / t_plain["spec"],
                                                "s": t_plain["spec"], "tangent_chunk": spec_info["chunk"],
-                                               "compile_s": spec_info["seconds"],
                                                "hull_endpoints_equal_to_interpreter": same_plain},
-        "adjoint_batched_graph": {"subdomain_bounds_per_s": total / t_batched, "s": t_batched,
-                                  "status_ok": bool((status == 0).all())},
-        "speedup_adjoint_batched_vs_plain": t_plain["interp"] / t_batched,
-        "speedup_adjoint_batched_vs_plain_specialised": t_plain["spec"] / t_batched,
+        "adjoint_batched_graph_interpreter": {"subdomain_bounds_per_s": total / t_graph[("rev", "interp")],
+                                              "s": t_graph[("rev", "interp")]},
+        "adjoint_batched_graph_specialised": {"subdomain_bounds_per_s": total / t_graph[("rev", "spec")],
+                                              "s": t_graph[("rev", "spec")],
+                                              "hull_endpoints_equal_to_interpreter":
+                                                  float(np.mean(red_graph[("rev", "spec")] ==
+                                                                red_graph[("rev", "interp")]))},
+        "forward_batched_graph_specialised": {"subdomain_bounds_per_s": total / t_graph[("fwd", "spec")],
+                                              "s": t_graph[("fwd", "spec")]},
+        "speedup_adjoint_batched_vs_plain": best_plain / t_graph[("rev", "spec")],
+        "speedup_adjoint_batched_vs_plain_same_kernel_kind": {
+            "interpreter": t_plain["interp"] / t_graph[("rev", "interp")],
+            "specialised": t_plain["spec"] / t_graph[("rev", "spec")]},
         "objective_lb_adjoint_minus_forward": {"tighter_frac": float(np.mean(d > 0)),
                                                "looser_frac": float(np.mean(d < 0)),
                                                "mean_rel": float(np.mean(d / scale))},
     }
-    g.close()
+    h.close()
     return out
 
 
@@ -234,16 +258,18 @@ def main():
     w = I.mid(args.seed)
     tape = mvf.Tape(w.tape)
     st = tape.stats()
-    spec = tape.specialize() if args.engine == "spec" else None
+    # both gradient modes: the forms below time the adjoint kernels of the same tape
+    spec = tape.specialize(grad="auto") if args.engine == "spec" or not args.no_forms else None
     box = torch.tensor(w.box, dtype=torch.float64, device="cuda")
-    call = mvf.BoundCall(tape, box, w.splits, mode="both", grad="fwd", engine=args.engine)
+    call = mvf.BoundCall(tape, box, w.splits, mode="both", grad=args.grad, engine=args.engine)
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     ms = time_calls(lambda: call.launch(stream), args.steps, args.warmup, stream)
     wall = time.perf_counter() - t0
     S = w.n_sub
     value = S / (ms * 1e-3)
-    achieved = st.ref_ops_fwd * S / (ms * 1e-3)           # algorithmic FP64 ops per second
+    ref_ops = st.ref_ops_fwd if args.grad == "fwd" else st.ref_ops_rev
+    achieved = ref_ops * S / (ms * 1e-3)                  # algorithmic FP64 ops per second
     reduced = call.reduced.cpu().numpy()
 
     out = {
@@ -259,27 +285,30 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "mid", "form": "plain: forward-mode MVF, one launch per node box",
+        "config": {"workload": "mid", "form": "plain: " + ("forward-mode" if args.grad == "fwd" else "adjoint") +
+                   " MVF, one launch per node box",
                    "n_vars": w.tape.n_vars, "tape_ops": w.tape.n_ops(), "roots": w.tape.n_roots,
                    "subdomains": S, "splits": [int(s) for s in w.splits], "seed": args.seed,
                    "tape_hash": w.tape.digest(), "engine": args.engine,
-                   "tangent_chunk": spec["chunk"] if spec else st.tangent_chunk},
+                   "tangent_chunk": spec["chunk"] if args.engine == "spec" else st.tangent_chunk},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": FP64_ISSUE_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / FP64_ISSUE_PEAK,
-                     "traffic": TRAFFIC.get((args.engine, w.tape.digest())),
-                     "kernel": ("mvf_spec_bound" if spec else f"bound_kernel<{st.tangent_chunk},false>") +
+                     "traffic": TRAFFIC.get((args.engine, args.grad, w.tape.digest())),
+                     "kernel": {("spec", "fwd"): "mvf_spec_bound", ("spec", "rev"): "mvf_spec_bound_rev",
+                                ("interp", "fwd"): f"bound_kernel<{st.tangent_chunk},false>",
+                                ("interp", "rev"): "bound_kernel<0,true>"}[(args.engine, args.grad)] +
                                " (+ the 1-block finish kernel inside the timed call)",
-                     "ops_per_subdomain": st.ref_ops_fwd,
+                     "ops_per_subdomain": ref_ops,
                      "frac_of_published_78.6": achieved / FP64_PUBLISHED_PEAK},
         "wall_s": wall,
         "objective_lower_bound": float(reduced[0, 0]),
     }
     if spec:
-        out["specialisation"] = {"compile_s": spec["seconds"], "from_cache": bool(spec["from_cache"]),
-                                 "code_units": spec["code_units"], "code_bytes": spec["code_bytes"],
-                                 "waves_per_simd": spec["waves"]}
+        out["specialisation"] = {"kernels": "tangent mode and adjoint", "compile_s": spec["seconds"],
+                                 "from_cache": bool(spec["from_cache"]), "code_units": spec["code_units"],
+                                 "code_bytes": spec["code_bytes"], "waves_per_simd": spec["waves"]}
     if not args.no_forms:
-        out["forms"] = forms(args.seed, args.engine)
+        out["forms"] = forms(args.seed, tape)
         if args.bnb_nodes > 0:
             out["forms"]["bnb"] = bnb_forms(args.seed, args.bnb_nodes)
     if not args.no_cpu:
