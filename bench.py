@@ -44,9 +44,9 @@ sys.path.insert(0, ROOT)
 FP64_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9          # 39.3e12 op/s
 FP64_PUBLISHED_PEAK = 78.6e12
 # HBM bytes per launch of the headline kernel from rocprofv3 counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00,
-# the factors from a 256 MiB copy in the same runs), valid for the kernel and tape they were taken on
-TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea"): (5491.9 * 2.0 + 7840.0) * 1024,
-           ("spec", "rev", "aa75c5b416e4faea"): (164675.3 * 2.0 + 296373.4) * 1024}
+# the factors from a 256 MiB copy in the same runs), valid only for the kernel build and tape they were
+# taken on: (engine, grad, tape hash) -> bytes
+TRAFFIC = {}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 

@@ -11,7 +11,8 @@
 // and negation is a free source modifier.  Every rounding-sensitive
 // instruction is written as volatile inline asm, so the compiler neither
 // folds it under round-to-nearest assumptions nor moves it across a mode
-// change.  Division and square root start from the compiler's estimate and are
+// change.  Division and square root start from the compiler's correctly
+// rounded estimate, computed in a short round-to-nearest window, and are
 // corrected with exact-sign residual tests (fma rounded down keeps the sign of
 // the exact residual), which yields the correctly rounded-down result.
 //
@@ -116,50 +117,66 @@ __device__ __forceinline__ double succ(double x) {
     return x == -__builtin_inf() ? -kMax : r;
 }
 
-// Correctly rounded-down quotient x / y.
-__device__ __forceinline__ double div_rd(double x, double y) {
-    double q = x / y;                     // estimate (a few ulps at most in any mode)
-    const bool neg = y < 0.0;
-    const double xs = neg ? -x : x, ys = neg ? -y : y;   // now ys > 0
-    if (q == __builtin_inf() && __builtin_isfinite(x) && __builtin_isfinite(y)) q = kMax;
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {      // step down while q * ys > xs
-        double r = ffma_n(q, ys, xs);     // RD(xs - q*ys): negative iff the exact residual is
-        double qd = pred(q);
-        q = r < 0.0 ? qd : q;
-    }
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {      // step up while succ(q) * ys <= xs
-        double q1 = succ(q);
-        double r1 = ffma_n(q1, ys, xs);
-        q = r1 >= 0.0 ? q1 : q;
-    }
-    return q;
+// Round-to-nearest estimates of two quotients (or square roots): the
+// compiler's IEEE division and square root sequences, which are correctly
+// rounded in that mode, run between two mode switches.  The switches take the
+// operands and the estimates as asm operands, so the estimates are computed
+// inside the window and nothing else is.
+__device__ __forceinline__ void div_rn2(double x0, double y0, double x1, double y1, double &q0, double &q1) {
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(y0), "+v"(x1), "+v"(y1));
+    q0 = x0 / y0;
+    q1 = x1 / y1;
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(q0), "+v"(q1));
+}
+__device__ __forceinline__ void sqrt_rn2(double a0, double a1, double &s0, double &s1) {
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(a0), "+v"(a1));
+    s0 = __builtin_sqrt(a0);
+    s1 = __builtin_sqrt(a1);
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(s0), "+v"(s1));
 }
 
-// Correctly rounded-down square root of a >= 0.
-__device__ __forceinline__ double sqrt_rd(double a) {
-    double s = __builtin_sqrt(a);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double r = ffma_n(s, s, a);       // RD(a - s*s)
-        double sd = pred(s);
-        s = r < 0.0 ? sd : s;
-    }
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        double s1 = succ(s);
-        double r1 = ffma_n(s1, s1, a);
-        s = r1 >= 0.0 ? s1 : s;
-    }
-    return s;
+// Correctly rounded-down quotients x0 / y0 and x1 / y1.  Each estimate is
+// within one ulp of the exact quotient t, so RD(t) is the estimate or one of
+// its neighbours: one step down while q * |y| > |x| and one step up while
+// succ(q) * |y| <= |x|, each decided by the sign of the exact residual (an
+// fma rounded down is negative iff the exact residual is).  The two chains
+// are interleaved so each compare-and-select has independent work beside it.
+__device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double y1, double &r0, double &r1) {
+    double q0, q1;
+    div_rn2(x0, y0, x1, y1, q0, q1);
+    const bool n0 = y0 < 0.0, n1 = y1 < 0.0;
+    const double xs0 = n0 ? -x0 : x0, ys0 = n0 ? -y0 : y0;   // now ys > 0
+    const double xs1 = n1 ? -x1 : x1, ys1 = n1 ? -y1 : y1;
+    if (q0 == __builtin_inf() && __builtin_isfinite(x0) && __builtin_isfinite(y0)) q0 = kMax;
+    if (q1 == __builtin_inf() && __builtin_isfinite(x1) && __builtin_isfinite(y1)) q1 = kMax;
+    const double e0 = ffma_n(q0, ys0, xs0), e1 = ffma_n(q1, ys1, xs1);   // RD(xs - q*ys)
+    const double d0 = pred(q0), d1 = pred(q1);
+    q0 = e0 < 0.0 ? d0 : q0;
+    q1 = e1 < 0.0 ? d1 : q1;
+    const double u0 = succ(q0), u1 = succ(q1);
+    const double f0 = ffma_n(u0, ys0, xs0), f1 = ffma_n(u1, ys1, xs1);
+    r0 = f0 >= 0.0 ? u0 : q0;
+    r1 = f1 >= 0.0 ? u1 : q1;
 }
-// -RU(sqrt(b)): the negated correctly rounded-up square root
-__device__ __forceinline__ double sqrt_ru_neg(double b) {
-    double s = sqrt_rd(b);
-    double r = ffma_nn(s, s, b);          // RD(s*s - b) < 0 iff s*s < b
-    double su = succ(s);
-    return -(r < 0.0 ? su : s);
+
+// [RD(sqrt(a)), -RU(sqrt(b))] for a, b >= 0, from round-to-nearest estimates
+// corrected as in div_rd2 (residual a - s*s), the upper end then stepped up
+// unless its square is exact.
+__device__ __forceinline__ void sqrt_rd_ru2(double a, double b, double &lo, double &nh) {
+    double s0, s1;
+    sqrt_rn2(a, b, s0, s1);
+    const double e0 = ffma_n(s0, s0, a), e1 = ffma_n(s1, s1, b);       // RD(a - s*s)
+    const double d0 = pred(s0), d1 = pred(s1);
+    s0 = e0 < 0.0 ? d0 : s0;
+    s1 = e1 < 0.0 ? d1 : s1;
+    const double u0 = succ(s0), u1 = succ(s1);
+    const double f0 = ffma_n(u0, u0, a), f1 = ffma_n(u1, u1, b);
+    s0 = f0 >= 0.0 ? u0 : s0;
+    s1 = f1 >= 0.0 ? u1 : s1;
+    const double g = ffma_nn(s1, s1, b);                               // RD(s*s - b) < 0 iff s*s < b
+    const double su = succ(s1);
+    lo = s0;
+    nh = -(g < 0.0 ? su : s1);
 }
 
 // ---- interval operations on (lo, nh) -------------------------------------
@@ -204,13 +221,23 @@ __device__ __forceinline__ Iv idiv(Iv u, Iv v) {
     const double dl = vpos ? (a >= 0.0 ? d : c) : (b >= 0.0 ? d : c);
     const double nn = vpos ? -b : -a;
     const double dn = vpos ? (b >= 0.0 ? c : d) : (a >= 0.0 ? c : d);
-    return {div_rd(nl, dl), div_rd(nn, dn)};
+    Iv z;
+    div_rd2(nl, dl, nn, dn, z.lo, z.nh);
+    return z;
 }
 
 // 1 / V with 0 not in V: [RD(1/d), RU(1/c)]
-__device__ __forceinline__ Iv irecip(Iv v) { return {div_rd(1.0, -v.nh), div_rd(-1.0, v.lo)}; }
+__device__ __forceinline__ Iv irecip(Iv v) {
+    Iv z;
+    div_rd2(1.0, -v.nh, -1.0, v.lo, z.lo, z.nh);
+    return z;
+}
 
-__device__ __forceinline__ Iv isqrt(Iv u) { return {sqrt_rd(u.lo), sqrt_ru_neg(-u.nh)}; }
+__device__ __forceinline__ Iv isqrt(Iv u) {
+    Iv z;
+    sqrt_rd_ru2(u.lo, -u.nh, z.lo, z.nh);
+    return z;
+}
 
 // 2U (exact up to overflow)
 __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh, u.nh)}; }
@@ -218,8 +245,9 @@ __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh
 // enclosure of 1/(2 sqrt(u)) from Z = sqrt(U); unbounded above when z_lo is 0
 __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
     const Iv t = itwice(z);
-    const double nh = div_rd(-1.0, t.lo);             // branch-free: lanes differ in the sign test
-    return {div_rd(1.0, -t.nh), t.lo <= 0.0 ? -__builtin_inf() : nh};
+    double lo, nh;
+    div_rd2(1.0, -t.nh, -1.0, t.lo, lo, nh);          // branch-free: lanes differ in the sign test
+    return {lo, t.lo <= 0.0 ? -__builtin_inf() : nh};
 }
 
 // exp and log: library value in round-to-nearest, widened by two ulps per side
@@ -257,7 +285,11 @@ __device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
 }
 
 // U / k for k > 0
-__device__ __forceinline__ Iv idivk(Iv u, double k) { return {div_rd(u.lo, k), div_rd(u.nh, k)}; }
+__device__ __forceinline__ Iv idivk(Iv u, double k) {
+    Iv z;
+    div_rd2(u.lo, k, u.nh, k, z.lo, z.nh);
+    return z;
+}
 
 // ---- slot file (GPR index mode) -------------------------------------------
 #define MVF_SB 128
