@@ -63,9 +63,19 @@ extern "C" {
  *   CONST a = index into consts[] (finite)
  *   ADD SUB MUL DIV  z = node a (op) node b
  *   SQR SQRT EXP LOG z = op(node a)
+ *   TANH SIN COS     z = op(node a)  (the activation of the paper's ANN
+ *                    workloads and the trigonometric functions of its test
+ *                    problems, Sec. 4; intrinsic functions of Sec. 3.2)
+ * Interval extensions: + - * / sqrt correctly rounded outward; exp, log,
+ * tanh, sin and cos take the library value in round-to-nearest widened
+ * outward (2 ulps for exp and log, 4 for tanh, sin and cos; tanh, sin, cos
+ * clamped to [-1, 1]); sin and cos reach +-1 where the argument interval may
+ * contain an extremum (2 k pi + pi/2 ... tested in outward-rounded interval
+ * arithmetic with a two-double enclosure of pi), and are [-1, 1] on
+ * intervals of width 6.28 or more.
  */
 enum { MVF_VAR = 0, MVF_CONST = 1, MVF_ADD = 2, MVF_SUB = 3, MVF_MUL = 4, MVF_DIV = 5,
-       MVF_SQR = 6, MVF_SQRT = 7, MVF_EXP = 8, MVF_LOG = 9 };
+       MVF_SQR = 6, MVF_SQRT = 7, MVF_EXP = 8, MVF_LOG = 9, MVF_TANH = 10, MVF_SIN = 11, MVF_COS = 12 };
 
 typedef struct { int32_t op, a, b; } mvf_node;
 typedef struct mvf_tape mvf_tape;

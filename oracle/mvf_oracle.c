@@ -34,6 +34,12 @@
  *   * f(m(X))       evaluated as an interval at degenerate [c_i,c_i];
  *   * exp/log       libm result in round-to-nearest, widened by two ulps on
  *                   each side (exp lower end clamped at 0);
+ *   * tanh/sin/cos  libm result in round-to-nearest widened by four ulps on
+ *                   each side, clamped to [-1, 1]; sin and cos take +-1 where
+ *                   the argument interval may contain an extremum (the
+ *                   interval (X - c) / [2pi] contains an integer, in outward
+ *                   rounding with pi enclosed by two doubles), and are
+ *                   [-1, 1] when RU(hi - lo) >= 6.28;
  *   * derivatives   the tangent and adjoint rules written next to each op
  *                   below (each is an interval inclusion of the true
  *                   derivative); division by V uses the reciprocal interval
@@ -53,7 +59,8 @@
 
 #pragma STDC FENV_ACCESS ON
 
-enum { OP_VAR = 0, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_SQR, OP_SQRT, OP_EXP, OP_LOG };
+enum { OP_VAR = 0, OP_CONST, OP_ADD, OP_SUB, OP_MUL, OP_DIV, OP_SQR, OP_SQRT, OP_EXP, OP_LOG, OP_TANH, OP_SIN,
+       OP_COS };
 enum { MODE_NIE = 0, MODE_MVF = 1, MODE_BOTH = 2 };
 enum { GRAD_FWD = 0, GRAD_REV = 1 };
 /* root kinds: the objective or an unconstrained function, g <= 0, h = 0 (Sec. 3.1, the NLP) */
@@ -162,6 +169,45 @@ static ivl isqrt(ivl u) { return I(rnd_sqrt(RD, u.lo), rnd_sqrt(RU, u.hi)); }
 static ivl iexp(ivl u) { return I(fmax(0.0, dn2(exp(u.lo))), up2(exp(u.hi))); }
 static ivl ilog(ivl u) { return I(dn2(log(u.lo)), up2(log(u.hi))); }
 
+static double dn4(double x) { return dn2(dn2(x)); }
+static double up4(double x) { return up2(up2(x)); }
+
+/* tanh is increasing with values in (-1, 1) */
+static ivl itanh(ivl u) { return I(fmax(-1.0, dn4(tanh(u.lo))), fmin(1.0, up4(tanh(u.hi)))); }
+
+/* pi lies between these neighbouring doubles */
+#define PI_LO 3.141592653589793
+#define PI_HI 3.1415926535897936
+
+/* can X contain c + 2 k pi for an integer k?  T = (X - C) / [2 pi] in outward
+ * rounding; true when T contains an integer or is not finite */
+static int may_contain(ivl x, ivl c) {
+    ivl t = idiv(isub(x, c), I(2.0 * PI_LO, 2.0 * PI_HI));
+    if (!isfinite(t.lo) || !isfinite(t.hi)) return 1;
+    return ceil(t.lo) <= t.hi;
+}
+
+/* sin over [a, b]: the endpoint values, and +-1 where an extremum may lie
+ * inside; the whole range [-1, 1] from width 6.28 on */
+static ivl isin(ivl u) {
+    double sa = sin(u.lo), sb = sin(u.hi);
+    double lo = fmin(dn4(sa), dn4(sb)), hi = fmax(up4(sa), up4(sb));
+    if (may_contain(u, I(PI_LO / 2, PI_HI / 2))) hi = 1.0;          /* pi/2 + 2 k pi */
+    if (may_contain(u, I(-PI_HI / 2, -PI_LO / 2))) lo = -1.0;       /* -pi/2 + 2 k pi */
+    if (!(rnd_sub(RU, u.hi, u.lo) < 6.28)) { lo = -1.0; hi = 1.0; }
+    return I(fmax(-1.0, lo), fmin(1.0, hi));
+}
+/* cos: maxima at 2 k pi, minima at pi + 2 k pi */
+static ivl icos(ivl u) {
+    double ca = cos(u.lo), cb = cos(u.hi);
+    double lo = fmin(dn4(ca), dn4(cb)), hi = fmax(up4(ca), up4(cb));
+    if (may_contain(u, I(0.0, 0.0))) hi = 1.0;
+    if (may_contain(u, I(PI_LO, PI_HI))) lo = -1.0;
+    if (!(rnd_sub(RU, u.hi, u.lo) < 6.28)) { lo = -1.0; hi = 1.0; }
+    return I(fmax(-1.0, lo), fmin(1.0, hi));
+}
+static ivl ineg(ivl u) { return I(-u.hi, -u.lo); }
+
 /* 2*U, exact up to overflow */
 static ivl itwice(ivl u) { return I(rnd_add(RD, u.lo, u.lo), rnd_add(RU, u.hi, u.hi)); }
 
@@ -185,6 +231,9 @@ void orc_interval_op(int op, const double *u, const double *v, double *z) {
     case OP_SQRT: Z = isqrt(U); break;
     case OP_EXP: Z = iexp(U); break;
     case OP_LOG: Z = ilog(U); break;
+    case OP_TANH: Z = itanh(U); break;
+    case OP_SIN: Z = isin(U); break;
+    case OP_COS: Z = icos(U); break;
     default: Z = I(NAN, NAN);
     }
     z[0] = Z.lo; z[1] = Z.hi;
@@ -254,6 +303,9 @@ static int eval_values(const orc_tape *t, const ivl *X, ivl *val) {
             if (U.lo <= 0) { bad = 1; val[i] = I(-INFINITY, INFINITY); }
             else val[i] = ilog(U);
             break;
+        case OP_TANH: val[i] = itanh(U); break;
+        case OP_SIN: val[i] = isin(U); break;
+        case OP_COS: val[i] = icos(U); break;
         default: bad = 1;
         }
     }
@@ -308,6 +360,18 @@ static int eval_tangents(const orc_tape *t, const ivl *X, ivl *val, ivl *tan) {
         case OP_LOG:   /* dU * (1/U) */
             R = irecip(U);
             for (int j = 0; j < n; ++j) dz[j] = imul(du[j], R);
+            break;
+        case OP_TANH:  /* (1 - Z^2) * dU */
+            R = isub(I(1, 1), isqr(Z));
+            for (int j = 0; j < n; ++j) dz[j] = imul(R, du[j]);
+            break;
+        case OP_SIN:   /* cos(U) * dU */
+            R = icos(U);
+            for (int j = 0; j < n; ++j) dz[j] = imul(R, du[j]);
+            break;
+        case OP_COS:   /* -sin(U) * dU */
+            R = ineg(isin(U));
+            for (int j = 0; j < n; ++j) dz[j] = imul(R, du[j]);
             break;
         }
     }
@@ -365,6 +429,15 @@ static void reverse_sweep(const orc_tape *t, const uint8_t *mask, const ivl *val
             break;
         case OP_LOG:   /* ub += zb*(1/U) */
             acc_to(t, nd->a, imul(zb, irecip(val[nd->a])), adj, G);
+            break;
+        case OP_TANH:  /* ub += zb*(1 - Z^2) */
+            acc_to(t, nd->a, imul(zb, isub(I(1, 1), isqr(val[i]))), adj, G);
+            break;
+        case OP_SIN:   /* ub += zb*cos(U) */
+            acc_to(t, nd->a, imul(zb, icos(val[nd->a])), adj, G);
+            break;
+        case OP_COS:   /* ub += zb*(-sin(U)) */
+            acc_to(t, nd->a, imul(zb, ineg(isin(val[nd->a]))), adj, G);
             break;
         }
     }

@@ -26,7 +26,7 @@ GCC_FLAGS = ["-O2", "-std=c11", "-Wall", "-frounding-math", "-ffp-contract=off",
 MODE_NIE, MODE_MVF, MODE_BOTH = 0, 1, 2
 GRAD_FWD, GRAD_REV = 0, 1
 FREE, INEQ, EQ = 0, 1, 2
-ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG = 2, 3, 4, 5, 6, 7, 8, 9
+ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG, TANH, SIN, COS = 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12
 
 
 def build(force: bool = False) -> str:

@@ -267,13 +267,78 @@ __device__ __forceinline__ Iv ilog(Iv u) {
     return {pred(pred(ll)), pred(pred(-lh))};
 }
 
+// tanh, sin and cos: the library value of both endpoints in round-to-nearest
+// (mode switches tied to the operands and results), widened by four ulps
+enum : int { LIB_TANH = 0, LIB_SIN = 1, LIB_COS = 2 };
+template <int F>
+__device__ __forceinline__ void lib2(double &x0, double &x1) {
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(x1));
+    if constexpr (F == LIB_TANH) {
+        x0 = tanh(x0);
+        x1 = tanh(x1);
+    } else if constexpr (F == LIB_SIN) {
+        x0 = sin(x0);
+        x1 = sin(x1);
+    } else {
+        x0 = cos(x0);
+        x1 = cos(x1);
+    }
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(x0), "+v"(x1));
+}
+__device__ __forceinline__ double pred4(double x) { return pred(pred(pred(pred(x)))); }
+
+// tanh is increasing with values in (-1, 1)
+__device__ __forceinline__ Iv itanh(Iv u) {
+    double a = u.lo, b = -u.nh;
+    lib2<LIB_TANH>(a, b);
+    return {fmax_(pred4(a), -1.0), fmax_(pred4(-b), -1.0)};
+}
+// pi lies between these neighbouring doubles
+constexpr double kPiLo = 3.141592653589793, kPiHi = 3.1415926535897936;
+
+// Can U contain c + 2 k pi for an integer k?  T = (U - C) / [2 pi] in outward
+// rounding; true when T contains an integer or is not finite (so a "no" is
+// rigorous and a "yes" at worst loosens the bound).
+__device__ __forceinline__ bool may_contain(Iv u, Iv c) {
+    const Iv t = idiv(isub(u, c), Iv{2.0 * kPiLo, -2.0 * kPiHi});
+    const double lo = t.lo, hi = -t.nh;
+    return !(__builtin_isfinite(lo) && __builtin_isfinite(hi)) || __builtin_ceil(lo) <= hi;
+}
+
+// sin or cos over U: the endpoint values widened by four ulps, +-1 where an
+// extremum may lie inside (sin: maxima at pi/2 + 2 k pi, minima at
+// -pi/2 + 2 k pi; cos: maxima at 2 k pi, minima at pi + 2 k pi), the whole
+// [-1, 1] from a width of 6.28 on; branch-free (lanes differ)
+template <int F>
+__device__ __forceinline__ Iv itrig(Iv u) {
+    double a = u.lo, b = -u.nh;
+    lib2<F>(a, b);
+    double lo = fmin_(pred4(a), pred4(b)), nh = fmin_(pred4(-a), pred4(-b));
+    const Iv cmax = F == LIB_SIN ? Iv{kPiLo / 2, -kPiHi / 2} : Iv{0.0, -0.0};
+    const Iv cmin = F == LIB_SIN ? Iv{-kPiHi / 2, kPiLo / 2} : Iv{kPiLo, -kPiHi};
+    const bool hi1 = may_contain(u, cmax), lo1 = may_contain(u, cmin);
+    const bool full = !(-fadd(u.lo, u.nh) < 6.28);             // RU(hi - lo) >= 6.28 (or NaN)
+    nh = hi1 || full ? -1.0 : nh;
+    lo = lo1 || full ? -1.0 : lo;
+    return {fmax_(lo, -1.0), fmax_(nh, -1.0)};
+}
+__device__ __forceinline__ Iv isin(Iv u) { return itrig<LIB_SIN>(u); }
+__device__ __forceinline__ Iv icos(Iv u) { return itrig<LIB_COS>(u); }
+
+// -U = [-hi, -lo]: the two stored endpoints trade places (exact)
+__device__ __forceinline__ Iv ineg(Iv u) { return {u.nh, u.lo}; }
+
+// local derivative enclosures: 1 - Z^2 for Z = tanh(U); cos(U); -sin(U)
+__device__ __forceinline__ Iv itanh_deriv(Iv z) { return isub(Iv{1.0, -1.0}, isqr(z)); }
+__device__ __forceinline__ Iv isin_deriv(Iv u) { return icos(u); }
+__device__ __forceinline__ Iv icos_deriv(Iv u) { return ineg(isin(u)); }
+
 // ---- constant-operand forms ---------------------------------------------
 // Each equals the general operation with a point interval [k, k] (k != 0)
 // bit for bit, up to the sign of zero endpoints: the general hull's other
 // candidates are never smaller, by monotonicity of rounding.
 
-// -U = [-hi, -lo]: the two stored endpoints trade places (exact)
-__device__ __forceinline__ Iv ineg(Iv u) { return {u.nh, u.lo}; }
+
 
 // U * k for k > 0
 __device__ __forceinline__ Iv imulk(Iv u, double k) { return {fmul(u.lo, k), fmul(u.nh, k)}; }

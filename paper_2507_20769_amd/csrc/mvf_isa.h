@@ -30,8 +30,12 @@ enum : uint32_t {
     I_MULKN = 14,     // U * (-k)   (k stored as its magnitude)
     I_DIVK = 15,      // U / k      (k > 0); operand b indexes the enclosure of 1/k
     I_DIVKN = 16,     // U / (-k)   (k stored as its magnitude)
-    I_NOPS = 17,
+    I_TANH = 17, I_SIN = 18, I_COS = 19,   // the tape's TANH, SIN, COS
+    I_NOPS = 20,
 };
+
+// unary functions with a local derivative interval: sqr sqrt exp log tanh sin cos
+constexpr bool is_unary_fn(uint32_t op) { return (op >= I_SQR && op <= I_LOG) || (op >= I_TANH && op <= I_COS); }
 // Operand kinds.  A result whose only consumer is the next instruction goes
 // to slot 0, which the allocator keeps for such short-lived values (its
 // adjoint in the reverse sweep lands in slot 0 the same way); K_PREV is not
@@ -67,14 +71,14 @@ constexpr bool is_reg_kind(uint32_t k) { return k == K_SLOT || k == K_PREV; }
 
 // Interval records one instruction leaves on the reverse-mode tape: the local
 // partials its adjoint rule needs (operand values of a product, 1/V and Z of a
-// quotient, 2U, 1/(2Z), Z, 1/U).  Variable and constant operands are not
+// quotient, 2U, 1/(2Z), Z, 1/U, 1 - Z^2, cos U, -sin U).  Variable and constant operands are not
 // recorded (they are known again in the reverse sweep), nor are the partials
 // of the constant-operand forms.
 // Order within an instruction: U then V for a product, 1/V then Z for a quotient.
 constexpr uint32_t n_records(uint32_t op, uint32_t ak, uint32_t bk) {
     return op == I_MUL ? (is_reg_kind(ak) && bk != K_CONST) + (is_reg_kind(bk) && ak != K_CONST)
          : op == I_DIV ? 1u + (bk != K_CONST)
-         : (op >= I_SQR && op <= I_LOG) ? (ak != K_CONST ? 1u : 0u) : 0u;
+         : is_unary_fn(op) ? (ak != K_CONST ? 1u : 0u) : 0u;
 }
 
 }  // namespace mvf

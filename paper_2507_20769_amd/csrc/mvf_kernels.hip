@@ -260,7 +260,7 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
             }
             break;
         }
-        case I_SQR: case I_SQRT: case I_EXP: case I_LOG: {
+        case I_SQR: case I_SQRT: case I_EXP: case I_LOG: case I_TANH: case I_SIN: case I_COS: {
             Iv D = kZero;                               // local derivative
             if (I.op == I_SQR) {
                 Z[0] = isqr(U);
@@ -272,10 +272,19 @@ __device__ Iv run_program(const Ctx &X, int begin, int len, int res_slot, int c0
             } else if (I.op == I_EXP) {
                 Z[0] = iexp(U);
                 D = Z[0];
-            } else {
+            } else if (I.op == I_LOG) {
                 bad |= U.lo <= 0.0 ? 1u : 0u;
                 Z[0] = ilog(U);
                 if constexpr (C > 0 || TAPE) D = irecip(U);
+            } else if (I.op == I_TANH) {
+                Z[0] = itanh(U);
+                if constexpr (C > 0 || TAPE) D = itanh_deriv(Z[0]);
+            } else if (I.op == I_SIN) {
+                Z[0] = isin(U);
+                if constexpr (C > 0 || TAPE) D = isin_deriv(U);
+            } else {
+                Z[0] = icos(U);
+                if constexpr (C > 0 || TAPE) D = icos_deriv(U);
             }
             if constexpr (TAPE) {
                 if (I.ak != K_CONST) X.rec[(rp++) * X.rec_stride] = make_double2(D.lo, D.nh);
@@ -405,7 +414,7 @@ __device__ void reverse_sweep(const Ctx &X, int begin, int len, int64_t n_rec) {
             if (I.bk != K_CONST) contribute(X, I.bk, I.b, ib, true, imul(T, Z));
             break;
         }
-        case I_SQR: case I_SQRT: case I_EXP: case I_LOG:
+        case I_SQR: case I_SQRT: case I_EXP: case I_LOG: case I_TANH: case I_SIN: case I_COS:
             if (I.ak != K_CONST) {
                 const Iv R = ld_rec(X, --rp);
                 contribute(X, I.ak, I.a, ia, false, imul(zb, R));

@@ -134,6 +134,9 @@ class PassWriter {
             case I_SQRT:
             case I_EXP:
             case I_LOG:
+            case I_TANH:
+            case I_SIN:
+            case I_COS:
                 if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, "imul(" + zb + ", q" + pc + ")");
                 break;
             case I_ADDK:
@@ -272,7 +275,10 @@ class PassWriter {
         case I_SQR:
         case I_SQRT:
         case I_EXP:
-        case I_LOG: {
+        case I_LOG:
+        case I_TANH:
+        case I_SIN:
+        case I_COS: {
             const std::string tu = "u" + std::to_string(pc), D = "q" + std::to_string(pc);
             decl.push_back("Iv " + tu + ";");
             s += tu + " = " + U + "; ";
@@ -286,9 +292,18 @@ class PassWriter {
             } else if (I.op == I_EXP) {
                 s += z + " = iexp(" + tu + ");";
                 dexpr = z;
-            } else {
+            } else if (I.op == I_LOG) {
                 s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; " + z + " = ilog(" + tu + ");";
                 dexpr = "irecip(" + tu + ")";
+            } else if (I.op == I_TANH) {
+                s += z + " = itanh(" + tu + ");";
+                dexpr = "itanh_deriv(" + z + ")";
+            } else if (I.op == I_SIN) {
+                s += z + " = isin(" + tu + ");";
+                dexpr = "isin_deriv(" + tu + ")";
+            } else {
+                s += z + " = icos(" + tu + ");";
+                dexpr = "icos_deriv(" + tu + ")";
             }
             if (C > 0 || tape) {
                 decl.push_back("Iv " + D + ";");

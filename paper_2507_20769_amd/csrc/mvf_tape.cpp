@@ -22,7 +22,12 @@ namespace {
 
 bool is_leaf(int op) { return op == MVF_VAR || op == MVF_CONST; }
 bool is_binary(int op) { return op >= MVF_ADD && op <= MVF_DIV; }
-bool is_unary(int op) { return op >= MVF_SQR && op <= MVF_LOG; }
+bool is_unary(int op) { return (op >= MVF_SQR && op <= MVF_LOG) || (op >= MVF_TANH && op <= MVF_COS); }
+
+// instruction opcode of a tape op (the general forms; constant-operand forms are chosen later)
+uint32_t instr_op(int op) {
+    return op == MVF_TANH ? I_TANH : op == MVF_SIN ? I_SIN : op == MVF_COS ? I_COS : (uint32_t)op;
+}
 
 // Reference FP64 op counts (value, per tangent component, adjoint) of one
 // instruction; interval products use the four-endpoint form, a constant
@@ -41,6 +46,11 @@ void ref_cost(int op, bool a_const, bool b_const, int *val, int *tan, int *adj) 
     case MVF_SQR: *val = 5; *tan = 14; *adj = 18; return;
     case MVF_SQRT: *val = 2; *tan = 14; *adj = 18; return;
     case MVF_EXP: case MVF_LOG: *val = 2; *tan = 14; *adj = 16; return;
+    // tanh: two library values and the clamp, then 1 - Z^2 (7 ops) once per op
+    case MVF_TANH: *val = 11; *tan = 14; *adj = 16; return;
+    // sin, cos: two library values, two extremum tests (a subtraction and a
+    // quotient each) and the clamp, then the derivative (the other function) once
+    case MVF_SIN: case MVF_COS: *val = 28; *tan = 14; *adj = 16; return;
     default: *val = 0; *tan = 0; *adj = 0;
     }
 }
@@ -76,7 +86,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
     if (n_consts < 0 || (n_consts > 0 && !consts)) return fail(err, MVF_EINVAL, "bad constant array");
     for (int i = 0; i < n_nodes; ++i) {
         const mvf_node &nd = nodes[i];
-        if (nd.op < MVF_VAR || nd.op > MVF_LOG) return fail(err, MVF_ETAPE, "node %ld: bad opcode %ld", i, nd.op);
+        if (nd.op < MVF_VAR || nd.op > MVF_COS) return fail(err, MVF_ETAPE, "node %ld: bad opcode %ld", i, nd.op);
         if (nd.op == MVF_VAR && (nd.a < 0 || nd.a >= n_vars))
             return fail(err, MVF_ETAPE, "node %ld: variable index %ld out of range", i, nd.a);
         if (nd.op == MVF_CONST) {
@@ -195,7 +205,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             else { d = take(); slot_of[i] = d; }
 
             // constant-operand forms: the other operand moves to position a
-            uint32_t op = (uint32_t)nd.op;
+            uint32_t op = instr_op(nd.op);
             double k = a_const && !b_const ? ka : kb;
             const bool one_const = bin && (a_const != b_const);
             if (one_const) {

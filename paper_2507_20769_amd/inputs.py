@@ -56,8 +56,8 @@ from typing import List, Sequence, Tuple
 
 import numpy as np
 
-VAR, CONST, ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG = range(10)
-OP_NAMES = ["VAR", "CONST", "ADD", "SUB", "MUL", "DIV", "SQR", "SQRT", "EXP", "LOG"]
+VAR, CONST, ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG, TANH, SIN, COS = range(13)
+OP_NAMES = ["VAR", "CONST", "ADD", "SUB", "MUL", "DIV", "SQR", "SQRT", "EXP", "LOG", "TANH", "SIN", "COS"]
 NODE_DTYPE = np.dtype([("op", "<i4"), ("a", "<i4"), ("b", "<i4")])
 
 _OP_DRAW = [(ADD, .20), (SUB, .15), (MUL, .25), (DIV, .08), (SQR, .12), (SQRT, .07), (LOG, .07), (EXP, .06)]
@@ -92,7 +92,7 @@ class Tape:
 
     def op_histogram(self) -> dict:
         ops = self.nodes["op"]
-        return {OP_NAMES[k]: int(np.count_nonzero(ops == k)) for k in range(10)}
+        return {OP_NAMES[k]: int(np.count_nonzero(ops == k)) for k in range(len(OP_NAMES))}
 
 
 class TapeBuilder:
@@ -114,6 +114,16 @@ class TapeBuilder:
     def const(self, v: float) -> int:
         self.consts.append(float(v))
         return self.add(CONST, len(self.consts) - 1)
+
+    def pow(self, x: int, k: int) -> int:
+        """x**k for an integer k >= 1, expanded by binary powering into sqr and mul nodes
+        (the tape has no power node: its interval extension is that of the expansion)."""
+        assert k >= 1
+        if k == 1:
+            return x
+        h = self.pow(x, k // 2)
+        h2 = self.add(SQR, h)
+        return self.add(MUL, h2, x) if k % 2 else h2
 
     def build(self) -> Tape:
         nodes = np.array(self.nodes, dtype=NODE_DTYPE)
@@ -151,6 +161,12 @@ def eval_points_np(tape: Tape, x: np.ndarray) -> np.ndarray:
                 v = np.exp(vals[a])
             elif op == LOG:
                 v = np.log(vals[a])
+            elif op == TANH:
+                v = np.tanh(vals[a])
+            elif op == SIN:
+                v = np.sin(vals[a])
+            elif op == COS:
+                v = np.cos(vals[a])
             else:
                 raise ValueError(op)
             vals.append(v)
@@ -530,3 +546,50 @@ def random_points(seed: int, box: np.ndarray, count: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     lo, hi = box[:, 0], box[:, 1]
     return lo + (hi - lo) * rng.random((count, box.shape[0]))
+
+
+# ----------------------------------------------------------------------------
+# ANN-shaped tapes (the paper's tanh-network workloads, Sec. 4.1 and 4.3)
+# ----------------------------------------------------------------------------
+
+def _dense_tanh(tb: TapeBuilder, rng: np.random.Generator, inputs: List[int], width: int) -> List[int]:
+    """One hidden layer: tanh(W x + b) per neuron, weights U[-1,1]/sqrt(fan-in), biases U[-0.5,0.5]."""
+    scale = 1.0 / np.sqrt(len(inputs))
+    out = []
+    for _ in range(width):
+        acc = tb.const(float(rng.uniform(-0.5, 0.5)))
+        for x in inputs:
+            acc = tb.add(ADD, acc, tb.add(MUL, tb.const(float(rng.uniform(-1.0, 1.0) * scale)), x))
+        out.append(tb.add(TANH, acc))
+    return out
+
+
+def ann_tape(seed: int = 1, n_in: int = 4, widths: Sequence[int] = (16, 16)) -> Tape:
+    """A seeded feed-forward tanh network (inputs -> hidden tanh layers -> one linear
+    output) as the objective, and one trigonometric inequality constraint
+    sum_i sin(x_i) cos(x_{i+1}) - 0.5 <= 0.  Weights are drawn, not trained: the
+    paper's trained networks are not public."""
+    rng = np.random.default_rng(seed)
+    tb = TapeBuilder(n_in)
+    xs = [tb.var(i) for i in range(n_in)]
+    h = xs
+    for w in widths:
+        h = _dense_tanh(tb, rng, h, w)
+    scale = 1.0 / np.sqrt(len(h))
+    out = tb.const(float(rng.uniform(-0.5, 0.5)))
+    for x in h:
+        out = tb.add(ADD, out, tb.add(MUL, tb.const(float(rng.uniform(-1.0, 1.0) * scale)), x))
+    tb.roots.append(out)
+    xs = [tb.var(i) for i in range(n_in)]
+    g = tb.const(-0.5)
+    for i in range(n_in):
+        g = tb.add(ADD, g, tb.add(MUL, tb.add(SIN, xs[i]), tb.add(COS, xs[(i + 1) % n_in])))
+    tb.roots.append(g)
+    return tb.build()
+
+
+def ann(seed: int = 1) -> Workload:
+    """4 inputs on [-2, 2]^4, two hidden tanh layers of 16, a sin/cos constraint, 16^4 subdomains."""
+    t = ann_tape(seed)
+    return Workload("ann", t, np.array([[-2.0, 2.0]] * 4), np.array([16, 16, 16, 16], dtype=np.int32),
+                    "tanh network 4-16-16-1 and a sin/cos constraint, [-2,2]^4, 16^4 subdomains")

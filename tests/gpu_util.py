@@ -6,8 +6,10 @@ from paper_2507_20769_amd import inputs as I
 
 
 def has_transcendental(tape) -> bool:
+    """Whether the tape calls a library function (exp log tanh sin cos): parity is then
+    within 1e-12 of the root's scale, the two sides calling different libms."""
     ops = tape.nodes["op"]
-    return bool(np.any((ops == I.EXP) | (ops == I.LOG)))
+    return bool(np.any(np.isin(ops, [I.EXP, I.LOG, I.TANH, I.SIN, I.COS])))
 
 
 def gpu_bound(tape, box, splits, mode="both", grad="fwd", per_sub=True, flags=True, handle=None, engine="auto"):

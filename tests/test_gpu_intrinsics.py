@@ -1,0 +1,114 @@
+"""GPU parity of tanh, sin and cos: the interpreter and the specialised
+kernels, in tangent mode and with the adjoint, against the oracle (within
+1e-12 of each root's scale: the two sides call different libms; the
+extremum tests of sin and cos are bitwise the same on both sides), on a
+trigonometric tape, on tanh networks and on the ANN workload at full size
+(sampled), plus point evaluation and the VJP."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_20769_amd import inputs as I
+
+from gpu_util import assert_parity, gpu_bound, scale_of
+
+pytestmark = pytest.mark.gpu
+
+GRADS = {"fwd": O.GRAD_FWD, "rev": O.GRAD_REV}
+
+
+def _trig_tape():
+    # f = tanh(x0 * x1) + sin(3 x0) * cos(x1),  g = cos(x0) - x1
+    V, C = I.VAR, I.CONST
+    nodes = [(V, 0, -1), (V, 1, -1), (C, 0, -1), (I.MUL, 0, 1), (I.TANH, 3, -1), (I.MUL, 2, 0), (I.SIN, 5, -1),
+             (I.COS, 1, -1), (I.MUL, 6, 7), (I.ADD, 4, 8), (I.COS, 0, -1), (I.SUB, 10, 1)]
+    return I.Tape(np.array(nodes, dtype=I.NODE_DTYPE), np.array([3.0]), np.array([9, 11], dtype=np.int32), 2)
+
+
+def _cases():
+    yield "trig", _trig_tape(), np.array([[-1.0, 2.0], [-2.0, 1.5]]), [37, 29]
+    yield "trig, wide", _trig_tape(), np.array([[-40.0, 30.0], [-9.0, 11.0]]), [13, 11]      # periods inside
+    yield "tanh net", I.ann_tape(3, n_in=3, widths=(8, 6)), np.array([[-2.0, 2.0], [-1.0, 3.0], [-3.0, 1.0]]), [5, 7, 9]
+
+
+@pytest.mark.parametrize("grad", ["fwd", "rev"])
+def test_interpreter_and_specialised_kernels_match_the_oracle(grad):
+    from paper_2507_20769_amd import mvf
+    for name, tape, box, splits in _cases():
+        h = mvf.Tape(tape)
+        h.set_root_kinds([0] + [1] * (tape.n_roots - 1))
+        h.specialize(grad="auto")
+        o = O.bound(tape, box, splits, mode=O.MODE_BOTH, grad=GRADS[grad], nthreads=8,
+                    kinds=[0] + [1] * (tape.n_roots - 1))
+        sc = scale_of(O.bound(tape, box, splits, mode=O.MODE_NIE, per_sub=False, nthreads=8)["reduced"])
+        for engine in ("interp", "spec"):
+            print(f"[case] {name} grad={grad} engine={engine}", flush=True)
+            g = gpu_bound(tape, box, splits, mode="both", grad=grad, handle=h, engine=engine)
+            assert_parity(g["per_sub"], o["per_sub"], False, sc, f"{name} {engine} per_sub")
+            assert_parity(g["reduced"], o["reduced"], False, sc, f"{name} {engine} reduced")
+            assert np.array_equal(g["flags"].astype(np.uint32), o["flags"])
+            assert_parity(g["extra"], o["extra"], False, max(sc), f"{name} {engine} extra")
+        h.close()
+
+
+def test_nie_mode_and_extremum_decisions_are_exact():
+    # NIE bounds of sin/cos reach +-1 exactly where the oracle's do: the extremum tests use
+    # the same outward-rounded arithmetic on both sides
+    from paper_2507_20769_amd import mvf
+    tape = _trig_tape()
+    box = np.array([[-40.0, 30.0], [-9.0, 11.0]])
+    splits = [61, 47]
+    g = gpu_bound(tape, box, splits, mode="nie")
+    o = O.bound(tape, box, splits, mode=O.MODE_NIE, nthreads=8)
+    assert np.array_equal(g["per_sub"][1] == 1.0, o["per_sub"][1] == 1.0)     # g = cos(x0) - x1: x1 exact
+    h = mvf.Tape(tape)
+    h.specialize()
+    gs = gpu_bound(tape, box, splits, mode="nie", handle=h, engine="spec")
+    assert np.array_equal(np.abs(gs["per_sub"]) == 1.0, np.abs(g["per_sub"]) == 1.0)
+    h.close()
+
+
+def test_ann_workload_full_size_sampled():
+    from paper_2507_20769_amd import mvf
+    w = I.ann(1)
+    h = mvf.Tape(w.tape)
+    h.specialize(grad="auto")
+    S = w.n_sub
+    ks = np.unique(np.concatenate([np.random.default_rng(5).choice(S, 200, replace=False), [0, S - 1]]))
+    sc = scale_of(O.bound(w.tape, w.box, w.splits, mode=O.MODE_NIE, ks=ks, per_sub=False, nthreads=8)["reduced"])
+    for grad in ("fwd", "rev"):
+        o = O.bound(w.tape, w.box, w.splits, mode=O.MODE_BOTH, grad=GRADS[grad], ks=ks, nthreads=8)
+        for engine in ("interp", "spec"):
+            print(f"[case] ann grad={grad} engine={engine}", flush=True)
+            g = gpu_bound(w.tape, w.box, w.splits, mode="both", grad=grad, handle=h, engine=engine)
+            assert_parity(g["per_sub"][:, :, ks], o["per_sub"], False, sc, f"ann {grad} {engine}")
+            assert not g["flags"].any()
+    h.close()
+
+
+def test_points_and_vjp_on_a_tanh_network():
+    import torch
+    from paper_2507_20769_amd import mvf
+    tape = I.ann_tape(4, n_in=3, widths=(7, 5))
+    h = mvf.Tape(tape)
+    rng = np.random.default_rng(6)
+    x = rng.uniform(-2, 2, (300, 3))
+    gout = rng.normal(size=(300, tape.n_roots))
+    f = mvf.eval_points(h, torch.tensor(x, device="cuda"))
+    gx = mvf.vjp_points(h, torch.tensor(x, device="cuda"), torch.tensor(gout, device="cuda"))
+    torch.cuda.synchronize()
+    fo = O.eval_points(tape, x)
+    go = O.vjp_points(tape, x, gout)
+    sc = np.maximum(np.abs(fo).max(), 1.0)
+    assert_parity(f.cpu().numpy(), fo, False, sc, "eval")
+    assert_parity(gx.cpu().numpy(), go, False, np.maximum(np.abs(go).max(), 1.0), "vjp")
+    # the VJP encloses central differences of sum_r gout_r f_r
+    h_ = 1e-6
+    for j in range(3):
+        xp, xm = x.copy(), x.copy()
+        xp[:, j] += h_
+        xm[:, j] -= h_
+        fd = ((I.eval_points_np(tape, xp) - I.eval_points_np(tape, xm)) * gout).sum(axis=1) / (2 * h_)
+        gj = gx.cpu().numpy()[:, j]
+        assert np.all(gj[:, 0] - 1e-5 <= fd) and np.all(fd <= gj[:, 1] + 1e-5)
+    h.close()

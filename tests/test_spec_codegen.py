@@ -25,10 +25,18 @@ def _every_form():
     return _tape(nodes, [1.5, -0.75, 2.0], [21, 1, 3], 2)
 
 
-@pytest.mark.parametrize("name", ["cubic", "every form", "tiny", "random"])
+def _trig():
+    V = I.VAR
+    nodes = [(V, 0, -1), (V, 1, -1), (I.CONST, 0, -1), (I.MUL, 0, 1), (I.TANH, 3, -1), (I.MUL, 2, 0),
+             (I.SIN, 5, -1), (I.COS, 1, -1), (I.MUL, 6, 7), (I.ADD, 4, 8), (I.COS, 0, -1), (I.SUB, 10, 1)]
+    return _tape(nodes, [3.0], [9, 11], 2)
+
+
+@pytest.mark.parametrize("name", ["cubic", "every form", "tiny", "random", "trig"])
 def test_generated_source_compiles(name):
     tape = {"cubic": I.cubic_tape, "every form": _every_form, "tiny": lambda: I.tiny(1).tape,
-            "random": lambda: I.random_small_tape(5, n=4, ops=60, n_con=2, con_ops=20, window=8)}[name]()
+            "random": lambda: I.random_small_tape(5, n=4, ops=60, n_con=2, con_ops=20, window=8),
+            "trig": _trig}[name]()
     st = mvf.check(tape)
     info = mvf.spec_check(tape)
     n = tape.n_vars
@@ -60,3 +68,13 @@ def test_bad_options_and_size_limit():
     with pytest.raises(mvf.MVFError) as e:
         mvf.spec_check(I.e2e_tape(1))
     assert e.value.code == -3
+
+
+def test_both_gradient_modes_compile_and_are_counted():
+    t = _trig()
+    st = mvf.check(t)
+    for grad, extra in (("fwd", None), ("rev", 2), ("auto", None)):
+        info = mvf.spec_check(t, grad=grad)
+        passes = -(-t.n_vars // info["chunk"])
+        want = st.n_instr * (2 + (passes if grad != "rev" else 0) + (2 if grad != "fwd" else 0))
+        assert info["code_units"] == want and info["grad"] == {"fwd": 0, "rev": 1, "auto": 2}[grad]
