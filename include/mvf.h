@@ -216,6 +216,30 @@ int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
                    int32_t n_vars, const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt,
                    mvf_spec_info *info);
 
+/* ---- constraint propagation ------------------------------------------
+ * Forward-backward bound tightening (FBBT) of node boxes, the bound
+ * tightening the paper reports compatible with its method (Sec. 4.3): per
+ * box, the interval of every live DAG node (forward; a violated domain gives
+ * [-inf, inf] and no narrowing through that node), the roots cut to their
+ * feasible ranges (inequality roots <= 0, equality roots = 0, the objective
+ * <= ub), then in descending node order each operand intersected with the
+ * outward-rounded inverse of its operation (backward: + - * / by the other
+ * operand, skipping divisions by intervals that contain 0; +-sqrt for sqr;
+ * squares for sqrt; the padded log for exp, exp for log, atanh for tanh;
+ * sin and cos only checked against [-1, 1]), and each variable met with its
+ * variable nodes.  Rounds repeat this on the tightened box.  One lane per
+ * box; the root kinds come from mvf_tape_set_root_kinds.
+ *   boxes, out  device [N][n][2]; out receives the tightened boxes
+ *   status      device [N]: 0, or 1 where the box is proven infeasible (then
+ *               out is undefined)
+ *   ub          the objective's upper bound, +inf for none
+ *   rounds      1..64
+ *   workspace   device scratch of mvf_fbbt_workspace() bytes
+ */
+int mvf_fbbt_workspace(const mvf_tape *tape, int64_t n_boxes, size_t *bytes);
+int mvf_fbbt(const mvf_tape *tape, int64_t n_boxes, const double *boxes, double ub, int32_t rounds, double *out,
+             int32_t *status, void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ---- tuning ----------------------------------------------------------- */
 typedef struct mvf_tuning {
     int32_t grad;             /* MVF_GRAD_FWD or MVF_GRAD_REV; other values: keep the call's choice */
@@ -380,6 +404,10 @@ typedef struct {
     int32_t mode, grad;           /* MVF_MODE_*, MVF_GRAD_* of the bounding calls */
     const struct mvf_tuning *tuning;   /* NULL or the batched launches' tuning */
     int32_t split_rule;           /* MVF_SPLITS_* of each node's partition */
+    int32_t fbbt_rounds;          /* 0: off; k >= 1: each taken node's box is first tightened by
+                                     mvf_fbbt with k rounds and the objective cut at the current
+                                     upper bound; a box proven infeasible is dropped (it holds no
+                                     feasible point better than the upper bound) */
 } mvf_bnb_options;
 
 typedef struct {

@@ -17,7 +17,10 @@ open are fixed as follows (the library's driver makes the same ones):
 * prune when lower >= upper - gap; branch by bisecting the widest variable
   (ties to the lower index) at RN(0.5 * (lo + hi));
 * stop when upper - (least open lower bound) <= gap, or after max_nodes
-  bounded nodes; `batch` nodes are taken per round.
+  taken nodes; `batch` nodes are taken per round;
+* with fbbt_rounds > 0 the taken boxes are first tightened by the oracle's
+  FBBT with the objective cut at the current upper bound; a box proven
+  infeasible is dropped and counts as a taken node.
 """
 from __future__ import annotations
 
@@ -29,7 +32,8 @@ from oracle import oracle as O
 
 
 def solve(tape, box, kinds=None, max_nodes: int = 1000, gap: float = 1e-4, budget: int = 4096,
-          mode: int = O.MODE_BOTH, grad: int = O.GRAD_FWD, batch: int = 1, nthreads: int = 8) -> dict:
+          mode: int = O.MODE_BOTH, grad: int = O.GRAD_FWD, batch: int = 1, nthreads: int = 8,
+          fbbt_rounds: int = 0) -> dict:
     box = np.array(box, dtype=np.float64)
     ub = np.inf
     counter = 0
@@ -54,6 +58,14 @@ def solve(tape, box, kinds=None, max_nodes: int = 1000, gap: float = 1e-4, budge
             take.append((lb, nid, b))
         if not take:
             continue
+        if fbbt_rounds > 0:
+            # tighten the taken boxes (objective cut at the current ub); drop those proven to
+            # hold no feasible point below ub
+            tb, st = O.fbbt(tape, np.stack([b for _, _, b in take]), kinds=kinds, ub=ub, rounds=fbbt_rounds)
+            nodes += int(np.count_nonzero(st))
+            take = [(lb, nid, tb[q]) for q, (lb, nid, b) in enumerate(take) if st[q] == 0]
+            if not take:
+                continue
         results = []
         for lb, nid, b in take:
             splits, count = O.adaptive_splits(b[:, 1] - b[:, 0], budget)

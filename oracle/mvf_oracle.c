@@ -829,3 +829,169 @@ int64_t orc_adaptive_splits(int n, const double *widths, int64_t budget, int32_t
     }
     return count;
 }
+
+/* ------------------------------------------------------------------------ */
+/* constraint propagation (forward-backward bound tightening, FBBT)          */
+/* ------------------------------------------------------------------------ */
+
+/* The bound tightening the paper reports compatible with its method
+ * (Sec. 4.3, "bound tightening"): intervals of every live node on the box
+ * (forward), the roots cut to their feasible ranges (g <= 0, h = 0, and the
+ * objective <= ub), then in descending node order each operand intersected
+ * with the outward-rounded inverse of its operation (backward); the box
+ * shrinks to the intersection of its variables' nodes.  An empty
+ * intersection proves the box infeasible.
+ *
+ * Forward, per op: the bounding extension of the op, except on a violated
+ * domain (0 in a divisor, a negative sqrt argument, a non-positive log
+ * argument), where the node is [-inf, +inf] (no information).
+ * Backward, z = op(u, v), each result intersected with the current operand:
+ *   add  U &= Z - V, then V &= Z - U        sub  U &= Z + V, then V &= U - Z
+ *   mul  U &= Z / V if 0 not in V, then V &= Z / U if 0 not in U
+ *   div  U &= Z * V, then V &= U / Z if 0 not in Z
+ *   sqr  R = sqrt(Z & [0, inf)):  U &= R if lo(U) >= 0, -R if hi(U) <= 0,
+ *        else [-hi(R), hi(R)]
+ *   sqrt Z &= [0, inf), U &= sqr(Z)         exp  Z &= [0, inf), U &= log(Z)
+ *        (the padded log; -inf below for lo(Z) = 0)
+ *   log  U &= exp(Z)                         tanh Z &= [-1, 1], U &= atanh(Z)
+ *        (libm in round-to-nearest widened by four ulps; +-inf at +-1)
+ *   sin, cos  only the check that Z meets [-1, 1] (not monotone)
+ * The inverse of an op is skipped where its own forward value carried no
+ * information (a violated domain).  Rounds repeat forward and backward on
+ * the tightened box. */
+
+#define ORC_MAX_VARS 64
+
+static ivl imeet(ivl a, ivl b) { return I(fmax(a.lo, b.lo), fmin(a.hi, b.hi)); }
+static int iempty(ivl a) { return !(a.lo <= a.hi); }
+
+static ivl iatanh(ivl z) {
+    double lo = z.lo <= -1.0 ? -INFINITY : dn4(atanh(z.lo));
+    double hi = z.hi >= 1.0 ? INFINITY : up4(atanh(z.hi));
+    return I(lo, hi);
+}
+
+/* returns 1 when the box is proven infeasible; out receives the tightened box */
+static int fbbt_box(const orc_tape *t, const int32_t *kinds, const double *box, double ub, int rounds,
+                    double *out, ivl *val, uint8_t *info) {
+    const int n = t->n_vars;
+    ivl X[ORC_MAX_VARS];
+    for (int j = 0; j < n; ++j) X[j] = I(box[2 * j], box[2 * j + 1]);
+    for (int round = 0; round < rounds; ++round) {
+        /* forward */
+        for (int i = 0; i < t->n_nodes; ++i) {
+            info[i] = 1;
+            if (!t->live[i]) { val[i] = I(0, 0); continue; }
+            const orc_node *nd = &t->nodes[i];
+            ivl U = nd->op >= OP_ADD ? val[nd->a] : I(0, 0);
+            ivl V = (nd->op >= OP_ADD && nd->op <= OP_DIV) ? val[nd->b] : I(0, 0);
+            switch (nd->op) {
+            case OP_VAR: val[i] = X[nd->a]; break;
+            case OP_CONST: val[i] = I(t->consts[nd->a], t->consts[nd->a]); break;
+            case OP_ADD: val[i] = iadd(U, V); break;
+            case OP_SUB: val[i] = isub(U, V); break;
+            case OP_MUL: val[i] = imul(U, V); break;
+            case OP_DIV:
+                if (V.lo <= 0 && V.hi >= 0) { info[i] = 0; val[i] = I(-INFINITY, INFINITY); }
+                else val[i] = idiv(U, V);
+                break;
+            case OP_SQR: val[i] = isqr(U); break;
+            case OP_SQRT:
+                if (U.lo < 0) { info[i] = 0; val[i] = I(-INFINITY, INFINITY); }
+                else val[i] = isqrt(U);
+                break;
+            case OP_EXP: val[i] = iexp(U); break;
+            case OP_LOG:
+                if (U.lo <= 0) { info[i] = 0; val[i] = I(-INFINITY, INFINITY); }
+                else val[i] = ilog(U);
+                break;
+            case OP_TANH: val[i] = itanh(U); break;
+            case OP_SIN: val[i] = isin(U); break;
+            case OP_COS: val[i] = icos(U); break;
+            }
+        }
+        /* the roots' feasible ranges */
+        for (int r = 0; r < t->n_roots; ++r) {
+            ivl *z = &val[t->roots[r]];
+            if (kinds && kinds[r] == ORC_INEQ) *z = imeet(*z, I(-INFINITY, 0.0));
+            else if (kinds && kinds[r] == ORC_EQ) *z = imeet(*z, I(0.0, 0.0));
+            else if (r == 0 && ub < INFINITY) *z = imeet(*z, I(-INFINITY, ub));
+        }
+        /* backward */
+        for (int i = t->n_nodes - 1; i >= 0; --i) {
+            if (!t->live[i]) continue;
+            if (iempty(val[i])) return 1;
+            const orc_node *nd = &t->nodes[i];
+            if (nd->op < OP_ADD || !info[i]) continue;
+            ivl Z = val[i], *U = &val[nd->a], *V = nd->op <= OP_DIV ? &val[nd->b] : NULL, R;
+            switch (nd->op) {
+            case OP_ADD: *U = imeet(*U, isub(Z, *V)); *V = imeet(*V, isub(Z, *U)); break;
+            case OP_SUB: *U = imeet(*U, iadd(Z, *V)); *V = imeet(*V, isub(*U, Z)); break;
+            case OP_MUL:
+                if (!(V->lo <= 0 && V->hi >= 0)) *U = imeet(*U, idiv(Z, *V));
+                if (!iempty(*U) && !(U->lo <= 0 && U->hi >= 0)) *V = imeet(*V, idiv(Z, *U));
+                break;
+            case OP_DIV:
+                *U = imeet(*U, imul(Z, *V));
+                if (!(Z.lo <= 0 && Z.hi >= 0)) *V = imeet(*V, idiv(*U, Z));
+                break;
+            case OP_SQR:
+                Z = imeet(Z, I(0.0, INFINITY));
+                if (iempty(Z)) return 1;
+                R = isqrt(Z);
+                if (U->lo >= 0) *U = imeet(*U, R);
+                else if (U->hi <= 0) *U = imeet(*U, I(-R.hi, -R.lo));
+                else *U = imeet(*U, I(-R.hi, R.hi));
+                break;
+            case OP_SQRT:
+                Z = imeet(Z, I(0.0, INFINITY));
+                if (iempty(Z)) return 1;
+                *U = imeet(*U, isqr(Z));
+                break;
+            case OP_EXP:
+                Z = imeet(Z, I(0.0, INFINITY));
+                if (iempty(Z)) return 1;
+                if (Z.hi <= 0) return 1;                 /* exp > 0 */
+                R = I(Z.lo <= 0 ? -INFINITY : dn2(log(Z.lo)), up2(log(Z.hi)));
+                *U = imeet(*U, R);
+                break;
+            case OP_LOG: *U = imeet(*U, iexp(Z)); break;
+            case OP_TANH:
+                Z = imeet(Z, I(-1.0, 1.0));
+                if (iempty(Z)) return 1;
+                *U = imeet(*U, iatanh(Z));
+                break;
+            case OP_SIN: case OP_COS:
+                if (iempty(imeet(Z, I(-1.0, 1.0)))) return 1;
+                break;
+            }
+            if (iempty(*U) || (nd->op <= OP_DIV && iempty(*V))) return 1;
+        }
+        /* the box: every variable node of variable j narrows X_j */
+        for (int i = 0; i < t->n_nodes; ++i)
+            if (t->live[i] && t->nodes[i].op == OP_VAR) X[t->nodes[i].a] = imeet(X[t->nodes[i].a], val[i]);
+        for (int j = 0; j < n; ++j)
+            if (iempty(X[j])) return 1;
+    }
+    for (int j = 0; j < n; ++j) { out[2 * j] = X[j].lo; out[2 * j + 1] = X[j].hi; }
+    return 0;
+}
+
+/* FBBT of N boxes; status[b] = 1 where a box is proven infeasible (out then undefined) */
+int orc_fbbt(const orc_node *nodes, int32_t n_nodes, const double *consts, int32_t n_vars, const int32_t *roots,
+             int32_t n_roots, const int32_t *kinds, int64_t N, const double *boxes, double ub, int32_t rounds,
+             double *out, int32_t *status) {
+    fesetround(FE_TONEAREST);
+    orc_tape t;
+    tape_init(&t, nodes, n_nodes, consts, n_vars, roots, n_roots);
+    ivl *val = malloc(sizeof(ivl) * ((size_t)n_nodes + 1));
+    uint8_t *info = malloc((size_t)n_nodes + 1);
+    for (int64_t b = 0; b < N; ++b)
+        status[b] = fbbt_box(&t, kinds, boxes + (size_t)b * n_vars * 2, ub, rounds, out + (size_t)b * n_vars * 2,
+                             val, info);
+    free(val);
+    free(info);
+    tape_free(&t);
+    fesetround(FE_TONEAREST);
+    return 0;
+}

@@ -59,6 +59,8 @@ def lib():
             L.orc_nie_boxes.argtypes = tape + [i64, P, P, P]
             L.orc_gradient_boxes.restype = ctypes.c_int
             L.orc_gradient_boxes.argtypes = tape + [i64, P, i32, ctypes.c_int, P, P]
+            L.orc_fbbt.restype = ctypes.c_int
+            L.orc_fbbt.argtypes = tape + [P, i64, P, ctypes.c_double, i32, P, P]
             L.orc_eval_points.restype = ctypes.c_int
             L.orc_eval_points.argtypes = tape + [i64, P, P]
             L.orc_vjp_points.restype = ctypes.c_int
@@ -157,6 +159,21 @@ def gradient_boxes(tape, boxes, root: int, grad: int = GRAD_FWD):
     flags = np.zeros(B, dtype=np.uint32)
     lib().orc_gradient_boxes(*targs, B, _p(boxes), root, grad, _p(G), _p(flags))
     return G, flags
+
+
+def fbbt(tape, boxes, kinds=None, ub: float = np.inf, rounds: int = 1):
+    """Forward-backward bound tightening of boxes [N, n, 2]: (tightened boxes, status [N],
+    1 where a box is proven infeasible)."""
+    keep, targs = _tape_args(tape)
+    boxes = np.ascontiguousarray(boxes, dtype=np.float64)
+    if boxes.ndim == 2:
+        boxes = boxes[None]
+    N = boxes.shape[0]
+    k = None if kinds is None else np.ascontiguousarray(kinds, dtype=np.int32)
+    out = np.zeros_like(boxes)
+    st = np.zeros(N, dtype=np.int32)
+    lib().orc_fbbt(*targs, None if k is None else _p(k), N, _p(boxes), float(ub), int(rounds), _p(out), _p(st))
+    return out, st
 
 
 def eval_points(tape, x):

@@ -23,6 +23,10 @@ struct mvf_tape {
     int device = 0;
     int n_cu = 256;
     uint32_t ineq_mask = 0, eq_mask = 0;   // constraint roots (mvf_tape_set_root_kinds)
+    DagNode *d_nodes = nullptr;             // the DAG itself, for bound tightening
+    int32_t *d_roots = nullptr;
+    double *d_consts = nullptr;
+    int32_t n_nodes = 0;
     hipModule_t spec_mod = nullptr;         // specialised kernels (mvf_tape_specialize)
     hipFunction_t spec_fn[2] = {nullptr, nullptr};        // single box: [0] tangent mode, [1] adjoint
     hipFunction_t spec_batch_fn[2] = {nullptr, nullptr};  // batched
@@ -451,6 +455,27 @@ int mvf_tape_create(const mvf_node *nodes, int32_t n_nodes, const double *consts
     if (e != hipSuccess) { delete t; return set_err(MVF_ENOMEM, "hipMalloc of the program failed"); }
     e = hipMemcpy(t->d_prog, t->C.instr.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) { hipFree(t->d_prog); delete t; return hip_err(e, "hipMemcpy program"); }
+    // the DAG with its live nodes (in some root's cone), for bound tightening
+    std::vector<DagNode> dag(n_nodes);
+    std::vector<uint8_t> live(n_nodes, 0);
+    for (int r = 0; r < n_roots; ++r) live[roots[r]] = 1;
+    for (int i = n_nodes - 1; i >= 0; --i) {
+        dag[i] = DagNode{nodes[i].op, nodes[i].a, nodes[i].b, live[i]};
+        if (!live[i] || nodes[i].op == MVF_VAR || nodes[i].op == MVF_CONST) continue;
+        live[nodes[i].a] = 1;
+        if (nodes[i].op <= MVF_DIV) live[nodes[i].b] = 1;
+    }
+    for (int i = 0; i < n_nodes; ++i) dag[i].live = live[i];
+    t->n_nodes = n_nodes;
+    const size_t nc = std::max<int32_t>(n_consts, 1);
+    if (hipMalloc(&t->d_nodes, (size_t)n_nodes * sizeof(DagNode)) != hipSuccess ||
+        hipMalloc(&t->d_roots, (size_t)n_roots * 4) != hipSuccess || hipMalloc(&t->d_consts, nc * 8) != hipSuccess ||
+        hipMemcpy(t->d_nodes, dag.data(), (size_t)n_nodes * sizeof(DagNode), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(t->d_roots, roots, (size_t)n_roots * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (n_consts > 0 && hipMemcpy(t->d_consts, consts, (size_t)n_consts * 8, hipMemcpyHostToDevice) != hipSuccess)) {
+        mvf_tape_destroy(t);
+        return set_err(MVF_ENOMEM, "device copy of the DAG failed");
+    }
     *out = t;
     return MVF_OK;
 }
@@ -465,6 +490,9 @@ int mvf_tape_destroy(mvf_tape *t) {
     if (!t) return MVF_OK;
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     if (t->d_prog) hipFree(t->d_prog);
+    hipFree(t->d_nodes);
+    hipFree(t->d_roots);
+    hipFree(t->d_consts);
     delete t;
     return MVF_OK;
 }
@@ -542,6 +570,45 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     }
     hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
     if (e != hipSuccess) return hip_err(e, "launch_bound");
+    return MVF_OK;
+}
+
+int mvf_fbbt_workspace(const mvf_tape *t, int64_t n_boxes, size_t *bytes) {
+    if (!t || !bytes || n_boxes < 0) return set_err(MVF_EINVAL, "bad argument");
+    const int64_t stride = (n_boxes + 63) / 64 * 64;
+    *bytes = std::max<size_t>((size_t)2 * t->n_nodes * stride * 16, 16);
+    return MVF_OK;
+}
+
+int mvf_fbbt(const mvf_tape *t, int64_t n_boxes, const double *boxes, double ub, int32_t rounds, double *out,
+             int32_t *status, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    if (!t || n_boxes < 0 || (n_boxes > 0 && (!boxes || !out || !status || !workspace)))
+        return set_err(MVF_EINVAL, "bad argument");
+    if (rounds < 1 || rounds > 64) return set_err(MVF_EINVAL, "rounds outside [1, 64]");
+    if (ub != ub) return set_err(MVF_EINVAL, "ub is NaN");
+    size_t need = 0;
+    mvf_fbbt_workspace(t, n_boxes, &need);
+    if (workspace_bytes < need) return set_err(MVF_EINVAL, "workspace too small");
+    FbbtArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.nodes = t->d_nodes;
+    A.consts = t->d_consts;
+    A.roots = t->d_roots;
+    A.n_nodes = t->n_nodes;
+    A.n = t->C.n_vars;
+    A.m = (int32_t)t->C.roots.size();
+    A.rounds = rounds;
+    A.ineq_mask = t->ineq_mask;
+    A.eq_mask = t->eq_mask;
+    A.ub = ub;
+    A.N = n_boxes;
+    A.boxes = boxes;
+    A.out = out;
+    A.status = status;
+    A.val = static_cast<double2 *>(workspace);
+    A.stride = (n_boxes + 63) / 64 * 64;
+    hipError_t e = launch_fbbt(A, stream);
+    if (e != hipSuccess) return hip_err(e, "fbbt kernel");
     return MVF_OK;
 }
 

@@ -11,8 +11,9 @@
 // the point pass of the mean value form evaluates anyway.
 //
 // Two launch forms: one mvf_bound call per node (plain), or the K best open
-// nodes per replay of a captured batched graph.  The driver is a client of the
-// public C ABI only.
+// nodes per replay of a captured batched graph.  Optionally each taken node's
+// box is first tightened by constraint propagation (mvf_fbbt; the bound
+// tightening of Sec. 4.3).  The driver is a client of the public C ABI only.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -45,7 +46,8 @@ struct Later {
 extern "C" int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_options *opt, mvf_bnb_result *res,
                              hipStream_t stream) {
     if (!tape || !box || !opt || !res) return set_error(MVF_EINVAL, "null argument");
-    if (opt->max_nodes < 1 || opt->nodes_per_launch < 1 || opt->subdomains_per_node < 1 || !(opt->abs_gap >= 0))
+    if (opt->max_nodes < 1 || opt->nodes_per_launch < 1 || opt->subdomains_per_node < 1 || !(opt->abs_gap >= 0) ||
+        opt->fbbt_rounds < 0 || opt->fbbt_rounds > 64)
         return set_error(MVF_EINVAL, "options out of range");
     mvf_tape_stats st;
     int rc = mvf_tape_stats_get(tape, &st);
@@ -66,6 +68,11 @@ extern "C" int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_op
     double *d_box = nullptr, *d_red = nullptr, *d_ex = nullptr, *p_box = nullptr, *p_ex = nullptr;
     void *d_ws = nullptr;
     size_t ws_bytes = 0;
+    // bound tightening of the taken nodes: device boxes in/out, status, scratch, pinned staging
+    double *d_fb_in = nullptr, *d_fb_out = nullptr, *p_fb = nullptr;
+    int32_t *d_fb_st = nullptr, *p_fb_st = nullptr;
+    void *d_fb_ws = nullptr;
+    size_t fb_ws = 0;
     auto cleanup = [&]() {
         if (g) mvf_batch_graph_destroy(g);
         hipFree(d_box);
@@ -74,7 +81,24 @@ extern "C" int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_op
         hipFree(d_ws);
         hipHostFree(p_box);
         hipHostFree(p_ex);
+        hipFree(d_fb_in);
+        hipFree(d_fb_out);
+        hipFree(d_fb_st);
+        hipFree(d_fb_ws);
+        hipHostFree(p_fb);
+        hipHostFree(p_fb_st);
     };
+    if (opt->fbbt_rounds > 0) {
+        mvf_fbbt_workspace(tape, K, &fb_ws);
+        if (hipMalloc(&d_fb_in, (size_t)K * n * 16) != hipSuccess ||
+            hipMalloc(&d_fb_out, (size_t)K * n * 16) != hipSuccess || hipMalloc(&d_fb_st, (size_t)K * 4) != hipSuccess ||
+            hipMalloc(&d_fb_ws, fb_ws) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&p_fb), (size_t)K * n * 16, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void **>(&p_fb_st), (size_t)K * 4, hipHostMallocDefault) != hipSuccess) {
+            cleanup();
+            return set_error(MVF_ENOMEM, "bound tightening buffers");
+        }
+    }
     if (K > 1) {
         rc = mvf_batch_graph_create(tape, K, (int64_t)K * opt->subdomains_per_node, opt->mode, opt->grad,
                                     opt->tuning, stream, &g);
@@ -117,6 +141,30 @@ extern "C" int mvf_bnb_solve(mvf_tape *tape, const double *box, const mvf_bnb_op
             take.push_back(std::move(nd));
         }
         if (take.empty()) continue;
+        if (opt->fbbt_rounds > 0) {
+            // tighten the taken boxes; drop those proven to hold no feasible point below ub
+            const int tc = (int)take.size();
+            for (int q = 0; q < tc; ++q) std::memcpy(p_fb + (size_t)q * n * 2, take[q].box.data(), (size_t)n * 16);
+            rc = hipMemcpyAsync(d_fb_in, p_fb, (size_t)tc * n * 16, hipMemcpyHostToDevice, stream) == hipSuccess
+                     ? MVF_OK : set_error(MVF_EHIP, "hipMemcpyAsync");
+            if (rc == MVF_OK)
+                rc = mvf_fbbt(tape, tc, d_fb_in, ub, opt->fbbt_rounds, d_fb_out, d_fb_st, d_fb_ws, fb_ws, stream);
+            if (rc == MVF_OK &&
+                (hipMemcpyAsync(p_fb, d_fb_out, (size_t)tc * n * 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                 hipMemcpyAsync(p_fb_st, d_fb_st, (size_t)tc * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+                 hipStreamSynchronize(stream) != hipSuccess))
+                rc = set_error(MVF_EHIP, "bound tightening copies");
+            if (rc != MVF_OK) { cleanup(); return rc; }
+            std::vector<Node> kept;
+            for (int q = 0; q < tc; ++q) {
+                if (p_fb_st[q]) continue;
+                std::memcpy(take[q].box.data(), p_fb + (size_t)q * n * 2, (size_t)n * 16);
+                kept.push_back(std::move(take[q]));
+            }
+            nodes += tc - (int64_t)kept.size();
+            take.swap(kept);
+            if (take.empty()) continue;
+        }
         const int cnt = (int)take.size();
         for (int q = 0; q < cnt; ++q) {
             for (int i = 0; i < n; ++i) widths[i] = take[q].box[2 * i + 1] - take[q].box[2 * i];

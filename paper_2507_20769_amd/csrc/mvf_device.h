@@ -267,9 +267,10 @@ __device__ __forceinline__ Iv ilog(Iv u) {
     return {pred(pred(ll)), pred(pred(-lh))};
 }
 
-// tanh, sin and cos: the library value of both endpoints in round-to-nearest
-// (mode switches tied to the operands and results), widened by four ulps
-enum : int { LIB_TANH = 0, LIB_SIN = 1, LIB_COS = 2 };
+// tanh, sin, cos (and atanh, for bound tightening): the library value of both
+// endpoints in round-to-nearest (mode switches tied to the operands and
+// results), widened by four ulps by the callers
+enum : int { LIB_TANH = 0, LIB_SIN = 1, LIB_COS = 2, LIB_ATANH = 3 };
 template <int F>
 __device__ __forceinline__ void lib2(double &x0, double &x1) {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(x1));
@@ -279,6 +280,9 @@ __device__ __forceinline__ void lib2(double &x0, double &x1) {
     } else if constexpr (F == LIB_SIN) {
         x0 = sin(x0);
         x1 = sin(x1);
+    } else if constexpr (F == LIB_ATANH) {
+        x0 = atanh(x0);
+        x1 = atanh(x1);
     } else {
         x0 = cos(x0);
         x1 = cos(x1);

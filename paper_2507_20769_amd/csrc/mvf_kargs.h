@@ -96,6 +96,25 @@ struct PointsArgs {
 struct PointsKArgs {
     PointsArgs P;
 };
+// Forward-backward bound tightening of many boxes (one lane per box).
+struct DagNode {
+    int32_t op, a, b, live;  // tape node; live: in some root's cone
+};
+struct FbbtArgs {
+    const DagNode *nodes;
+    const double *consts;
+    const int32_t *roots;
+    int32_t n_nodes, n, m, rounds;
+    uint32_t ineq_mask, eq_mask;
+    double ub;               // objective upper bound (+inf: none)
+    int64_t N;
+    const double *boxes;     // [N][n][2]
+    double *out;             // [N][n][2]
+    int32_t *status;         // [N]: 1 = proven infeasible
+    double2 *val;            // scratch [n_nodes][stride]
+    int64_t stride;
+};
+
 #if defined(__HIPCC__) || defined(__HIPCC_RTC__)
 template <typename BA>     // BatchArgs in any address space
 __device__ __forceinline__ int node_count(const BA &A) { return A.n_nodes_dev ? *A.n_nodes_dev : A.n_nodes_val; }

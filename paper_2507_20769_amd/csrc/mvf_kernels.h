@@ -15,6 +15,8 @@ hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev
                         hipStream_t stream);
 // Step 3 across the workgroups of a single-box launch (per-block partials -> reduced, argmin, extra)
 hipError_t launch_finish(const BoxArgs &B, int grid, int m, hipStream_t stream);
+// forward-backward bound tightening, one lane per box
+hipError_t launch_fbbt(const FbbtArgs &A, hipStream_t stream);
 hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool rev, int grid, size_t lds,
                         int max_nodes, hipStream_t stream);
 // the batched launch's plan kernel and per-node finish kernel (around any persistent bounding kernel)

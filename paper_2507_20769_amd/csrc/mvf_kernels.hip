@@ -1037,6 +1037,190 @@ static hipError_t allow_lds(K kernel) {
                                (int)(LDS_BUDGET - 1024));
 }
 
+// ---------------------------------------------------------------------------
+// constraint propagation (forward-backward bound tightening) of node boxes
+// ---------------------------------------------------------------------------
+//
+// The bound tightening the paper reports compatible with its method (Sec.
+// 4.3): one lane per box walks the tape's DAG forward (the bounding interval
+// extension of every live node; a violated domain gives [-inf, inf] and marks
+// the node as carrying no information), cuts the roots to their feasible
+// ranges (g <= 0, h = 0, objective <= ub), then backward in descending node
+// order intersects each operand with the outward-rounded inverse of its
+// operation, and finally meets every variable with its variable nodes.  An
+// empty intersection proves the box infeasible.  Rounds repeat on the
+// tightened box.  Node intervals live in global scratch [node][lane], the
+// no-information marks in the rows after them.
+namespace dev {
+
+__device__ __forceinline__ Iv imeet(Iv a, Iv b) { return {fmax_(a.lo, b.lo), fmax_(a.nh, b.nh)}; }
+__device__ __forceinline__ bool iempty(Iv a) { return !(a.lo <= -a.nh); }
+__device__ __forceinline__ bool has_zero(Iv a) { return a.lo <= 0.0 && a.nh <= 0.0; }
+
+// returns 1 when the box is proven infeasible (X then undefined)
+__device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
+    constexpr double inf = __builtin_inf();
+    const Iv nonneg = {0.0, -inf}, unit = {-1.0, -1.0};
+    for (int round = 0; round < A.rounds; ++round) {
+        // forward
+        for (int i = 0; i < A.n_nodes; ++i) {
+            const DagNode nd = A.nodes[i];
+            if (!nd.live) continue;
+            const Iv U = nd.op >= MVF_ADD ? Iv{val[(int64_t)nd.a * A.stride].x, val[(int64_t)nd.a * A.stride].y} : kZero;
+            const Iv V = nd.op >= MVF_ADD && nd.op <= MVF_DIV
+                             ? Iv{val[(int64_t)nd.b * A.stride].x, val[(int64_t)nd.b * A.stride].y} : kZero;
+            Iv Z = kZero;
+            int info = 1;
+            switch (nd.op) {
+            case MVF_VAR: Z = X[nd.a]; break;
+            case MVF_CONST: Z = Iv{A.consts[nd.a], -A.consts[nd.a]}; break;
+            case MVF_ADD: Z = iadd(U, V); break;
+            case MVF_SUB: Z = isub(U, V); break;
+            case MVF_MUL: Z = imul(U, V); break;
+            case MVF_DIV:
+                if (has_zero(V)) { info = 0; Z = Iv{-inf, -inf}; } else Z = idiv(U, V);
+                break;
+            case MVF_SQR: Z = isqr(U); break;
+            case MVF_SQRT:
+                if (U.lo < 0.0) { info = 0; Z = Iv{-inf, -inf}; } else Z = isqrt(U);
+                break;
+            case MVF_EXP: Z = iexp(U); break;
+            case MVF_LOG:
+                if (U.lo <= 0.0) { info = 0; Z = Iv{-inf, -inf}; } else Z = ilog(U);
+                break;
+            case MVF_TANH: Z = itanh(U); break;
+            case MVF_SIN: Z = isin(U); break;
+            default: Z = icos(U); break;
+            }
+            val[(int64_t)i * A.stride] = make_double2(Z.lo, Z.nh);
+            val[((int64_t)A.n_nodes + i) * A.stride].x = info ? 1.0 : 0.0;    // rows n_nodes..: the marks
+        }
+        // the roots' feasible ranges
+        for (int r = 0; r < A.m; ++r) {
+            double2 &z = val[(int64_t)A.roots[r] * A.stride];
+            Iv c = {-inf, -inf};
+            if ((A.ineq_mask >> r) & 1u) c = Iv{-inf, -0.0};
+            else if ((A.eq_mask >> r) & 1u) c = Iv{0.0, -0.0};
+            else if (r == 0 && A.ub < inf) c = Iv{-inf, -A.ub};
+            const Iv m = imeet(Iv{z.x, z.y}, c);
+            z = make_double2(m.lo, m.nh);
+        }
+        // backward
+        for (int i = A.n_nodes - 1; i >= 0; --i) {
+            const DagNode nd = A.nodes[i];
+            if (!nd.live) continue;
+            const double2 zv = val[(int64_t)i * A.stride];
+            Iv Z = {zv.x, zv.y};
+            if (iempty(Z)) return 1;
+            if (nd.op < MVF_ADD || val[((int64_t)A.n_nodes + i) * A.stride].x == 0.0) continue;
+            double2 &us = val[(int64_t)nd.a * A.stride];
+            Iv U = {us.x, us.y};
+            const bool bin = nd.op <= MVF_DIV;
+            Iv V = kZero;
+            if (bin) {
+                const double2 vs = val[(int64_t)nd.b * A.stride];
+                V = Iv{vs.x, vs.y};
+            }
+            switch (nd.op) {
+            // operands a and b may be one node: the second narrowing then starts from the first
+            case MVF_ADD:
+                U = imeet(U, isub(Z, V));
+                if (nd.a == nd.b) V = U;
+                V = imeet(V, isub(Z, U));
+                if (nd.a == nd.b) U = V;
+                break;
+            case MVF_SUB:
+                U = imeet(U, iadd(Z, V));
+                if (nd.a == nd.b) V = U;
+                V = imeet(V, isub(U, Z));
+                if (nd.a == nd.b) U = V;
+                break;
+            case MVF_MUL:
+                if (!has_zero(V)) U = imeet(U, idiv(Z, V));
+                if (nd.a == nd.b) V = U;
+                if (!iempty(U) && !has_zero(U)) V = imeet(V, idiv(Z, U));
+                if (nd.a == nd.b) U = V;
+                break;
+            case MVF_DIV:
+                U = imeet(U, imul(Z, V));
+                if (nd.a == nd.b) V = U;
+                if (!has_zero(Z)) V = imeet(V, idiv(U, Z));
+                if (nd.a == nd.b) U = V;
+                break;
+            case MVF_SQR: {
+                Z = imeet(Z, nonneg);
+                if (iempty(Z)) return 1;
+                const Iv R = isqrt(Z);
+                if (U.lo >= 0.0) U = imeet(U, R);
+                else if (U.nh >= 0.0) U = imeet(U, ineg(R));
+                else U = imeet(U, Iv{R.nh, R.nh});
+                break;
+            }
+            case MVF_SQRT:
+                Z = imeet(Z, nonneg);
+                if (iempty(Z)) return 1;
+                U = imeet(U, isqr(Z));
+                break;
+            case MVF_EXP:
+                Z = imeet(Z, nonneg);
+                if (iempty(Z) || -Z.nh <= 0.0) return 1;    // exp > 0
+                U = imeet(U, ilog(Z));
+                break;
+            case MVF_LOG: U = imeet(U, iexp(Z)); break;
+            case MVF_TANH: {
+                Z = imeet(Z, unit);
+                if (iempty(Z)) return 1;
+                double a = Z.lo, b = -Z.nh;
+                lib2<LIB_ATANH>(a, b);
+                const Iv R = {Z.lo <= -1.0 ? -inf : pred4(a), Z.nh <= -1.0 ? -inf : pred4(-b)};
+                U = imeet(U, R);
+                break;
+            }
+            default:     // sin, cos: only the range check
+                if (iempty(imeet(Z, unit))) return 1;
+                break;
+            }
+            if (iempty(U) || (bin && iempty(V))) return 1;
+            us = make_double2(U.lo, U.nh);
+            if (bin) val[(int64_t)nd.b * A.stride] = make_double2(V.lo, V.nh);
+        }
+        // the box
+        for (int i = 0; i < A.n_nodes; ++i) {
+            const DagNode nd = A.nodes[i];
+            if (!nd.live || nd.op != MVF_VAR) continue;
+            const double2 v = val[(int64_t)i * A.stride];
+            X[nd.a] = imeet(X[nd.a], Iv{v.x, v.y});
+        }
+        for (int j = 0; j < A.n; ++j)
+            if (iempty(X[j])) return 1;
+    }
+    return 0;
+}
+
+}  // namespace dev
+
+__global__ __launch_bounds__(64) void fbbt_kernel(FbbtArgs A) {
+    using namespace dev;
+    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (b >= A.N) return;
+    Iv X[MVF_MAX_VARS];
+    for (int j = 0; j < A.n; ++j) X[j] = Iv{A.boxes[(b * A.n + j) * 2], -A.boxes[(b * A.n + j) * 2 + 1]};
+    mode_round_down();
+    const uint32_t bad = fbbt_lane(A, A.val + b, X);
+    mode_round_nearest();
+    A.status[b] = (int32_t)bad;
+    for (int j = 0; j < A.n; ++j) {
+        A.out[(b * A.n + j) * 2] = bad ? 0.0 : X[j].lo;
+        A.out[(b * A.n + j) * 2 + 1] = bad ? 0.0 : -X[j].nh;
+    }
+}
+
+hipError_t launch_fbbt(const FbbtArgs &A, hipStream_t stream) {
+    if (A.N == 0) return hipSuccess;
+    hipLaunchKernelGGL(fbbt_kernel, dim3((unsigned)((A.N + 63) / 64)), dim3(64), 0, stream, A);
+    return hipGetLastError();
+}
+
 #define MVF_DISPATCH(C_, REV_, CALL)                            \
     do {                                                        \
         if (REV_) {                                             \

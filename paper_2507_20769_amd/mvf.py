@@ -55,7 +55,8 @@ class Tuning(ctypes.Structure):
 class BnbOptions(ctypes.Structure):
     _fields_ = [("max_nodes", ctypes.c_int32), ("nodes_per_launch", ctypes.c_int32),
                 ("subdomains_per_node", ctypes.c_int64), ("abs_gap", ctypes.c_double), ("mode", ctypes.c_int32),
-                ("grad", ctypes.c_int32), ("tuning", ctypes.c_void_p), ("split_rule", ctypes.c_int32)]
+                ("grad", ctypes.c_int32), ("tuning", ctypes.c_void_p), ("split_rule", ctypes.c_int32),
+                ("fbbt_rounds", ctypes.c_int32)]
 
 
 class BnbResult(ctypes.Structure):
@@ -104,7 +105,7 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
            "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check", "mvf_splits",
-           "mvf_autotune_splits"]
+           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace"]
 
 
 def lib():
@@ -144,6 +145,10 @@ def lib():
             i64 = ctypes.c_int64
             L.mvf_adaptive_splits.restype = i64
             L.mvf_adaptive_splits.argtypes = [i32, P, i64, P]
+            L.mvf_fbbt_workspace.restype = ctypes.c_int
+            L.mvf_fbbt_workspace.argtypes = [P, i64, ctypes.POINTER(ctypes.c_size_t)]
+            L.mvf_fbbt.restype = ctypes.c_int
+            L.mvf_fbbt.argtypes = [P, i64, P, ctypes.c_double, i32, P, P, P, ctypes.c_size_t, P]
             L.mvf_splits.restype = i64
             L.mvf_splits.argtypes = [i32, i32, P, i64, P]
             L.mvf_autotune_splits.restype = ctypes.c_int
@@ -375,6 +380,27 @@ def autotune_splits(tape: Tape, boxes, budget: int, mode: str = "both", grad: st
     if rc != 0:
         raise MVFError(rc, "mvf_autotune_splits")
     return ("adaptive", "doubling")[rule.value], [better[0], better[1]]
+
+
+def fbbt(tape: Tape, boxes, ub: float = float("inf"), rounds: int = 1, stream=None):
+    """Forward-backward bound tightening of boxes (device float64 [N, n, 2]).
+    Returns (tightened boxes [N, n, 2], status [N] int32, 1 = proven infeasible)."""
+    import torch
+    b = boxes.contiguous()
+    assert b.dtype == torch.float64 and b.is_cuda and b.dim() == 3 and b.shape[1:] == (tape.n_vars, 2)
+    N = int(b.shape[0])
+    ws = ctypes.c_size_t()
+    rc = lib().mvf_fbbt_workspace(tape.handle, N, ctypes.byref(ws))
+    if rc != 0:
+        raise MVFError(rc, "mvf_fbbt_workspace")
+    work = torch.empty(int(ws.value), dtype=torch.uint8, device=b.device)
+    out = torch.empty_like(b)
+    st = torch.empty(max(N, 1), dtype=torch.int32, device=b.device)
+    rc = lib().mvf_fbbt(tape.handle, N, b.data_ptr(), float(ub), int(rounds), out.data_ptr(), st.data_ptr(),
+                        work.data_ptr(), work.numel(), _stream_ptr(stream))
+    if rc != 0:
+        raise MVFError(rc, "mvf_fbbt")
+    return out, st[:N]
 
 
 class BatchCall:
@@ -625,7 +651,8 @@ def point_function(tape: Tape, x):
 # ---------------------------------------------------------------------------
 def bnb_solve(tape: Tape, box, max_nodes: int = 1000, gap: float = 1e-4, budget: int = 4096,
               nodes_per_launch: int = 1, mode: str = "both", grad: str = "fwd",
-              tuning: Optional[Tuning] = None, stream=None, split_rule: str = "adaptive") -> dict:
+              tuning: Optional[Tuning] = None, stream=None, split_rule: str = "adaptive",
+              fbbt_rounds: int = 0) -> dict:
     """Spatial B&B with GPU subdomain bounding (synchronous).  box: host [n, 2].
 
     Root kinds come from Tape.set_root_kinds.  Returns dict(lower, upper,
@@ -633,7 +660,8 @@ def bnb_solve(tape: Tape, box, max_nodes: int = 1000, gap: float = 1e-4, budget:
     b = np.ascontiguousarray(box, dtype=np.float64)
     assert b.shape == (tape.n_vars, 2)
     opt = BnbOptions(int(max_nodes), int(nodes_per_launch), int(budget), float(gap), MVF_MODE[mode], MVF_GRAD[grad],
-                     ctypes.addressof(tuning) if tuning is not None else None, SPLIT_RULES[split_rule])
+                     ctypes.addressof(tuning) if tuning is not None else None, SPLIT_RULES[split_rule],
+                     int(fbbt_rounds))
     res = BnbResult()
     rc = lib().mvf_bnb_solve(tape.handle, b.ctypes.data_as(ctypes.c_void_p), ctypes.byref(opt), ctypes.byref(res),
                              _stream_ptr(stream))

@@ -58,3 +58,22 @@ def test_node_limit_and_batches():
     assert r["status"] == 1 and r["nodes"] == 20
     rb = bnb.solve(t, box, kinds=[O.FREE, O.INEQ], max_nodes=20, gap=0.0, budget=64, batch=4)
     assert rb["nodes"] == 20 and rb["lower"] <= rb["upper"]
+
+
+def test_bound_tightening_keeps_the_bracket_and_saves_nodes():
+    # min -x s.t. x - 0.5 <= 0 on [0, 1]: tightening cuts the box to [0, 0.5] at the root
+    nodes = [(I.VAR, 0, -1), (I.CONST, 0, -1), (I.CONST, 1, -1), (I.MUL, 0, 1), (I.SUB, 0, 2)]
+    t = I.Tape(np.array(nodes, dtype=I.NODE_DTYPE), np.array([-1.0, 0.5]), np.array([3, 4], dtype=np.int32), 1)
+    plain = bnb.solve(t, [[0.0, 1.0]], kinds=[O.FREE, O.INEQ], max_nodes=2000, gap=1e-4, budget=16)
+    tight = bnb.solve(t, [[0.0, 1.0]], kinds=[O.FREE, O.INEQ], max_nodes=2000, gap=1e-4, budget=16, fbbt_rounds=2)
+    for r in (plain, tight):
+        assert r["status"] == 0 and r["lower"] <= -0.5 <= r["upper"] and r["upper"] - r["lower"] <= 1e-4
+    assert tight["nodes"] <= plain["nodes"]
+    # a random constrained problem: the certified bracket holds with tightening too
+    t = I.random_small_tape(41, n=3, ops=40, n_con=1, con_ops=12, window=6)
+    g = np.linspace(-2.0, 2.0, 41)
+    pts = np.stack(np.meshgrid(g, g, g), axis=-1).reshape(-1, 3)
+    v = I.eval_points_np(t, pts)
+    best = v[v[:, 1] <= 0, 0].min()
+    r = bnb.solve(t, [[-2.0, 2.0]] * 3, kinds=[O.FREE, O.INEQ], max_nodes=60, gap=0.0, budget=64, fbbt_rounds=2)
+    assert r["lower"] <= best
