@@ -228,8 +228,10 @@ def bnb_forms(seed: int, max_nodes: int) -> dict:
     box = np.array([[-3.0, 3.0]] * tape.n_vars)
     out = {"problem": "e2e", "n_vars": tape.n_vars, "roots": tape.n_roots, "subdomains_per_node": 1 << 16,
            "max_nodes": max_nodes, "abs_gap": 1e-4}
-    for name, k, grad in (("plain_forward_per_node", 1, "fwd"), ("adjoint_batched_graph", 16, "rev")):
-        r = mvf.bnb_solve(h, box, max_nodes=max_nodes, gap=1e-4, budget=1 << 16, nodes_per_launch=k, grad=grad)
+    for name, k, grad, fb in (("plain_forward_per_node", 1, "fwd", 0), ("adjoint_batched_graph", 16, "rev", 0),
+                              ("adjoint_batched_graph_with_bound_tightening", 16, "rev", 2)):
+        r = mvf.bnb_solve(h, box, max_nodes=max_nodes, gap=1e-4, budget=1 << 16, nodes_per_launch=k, grad=grad,
+                          fbbt_rounds=fb)
         out[name] = {"nodes_per_s": r["nodes"] / r["seconds"], "subdomain_bounds_per_s": r["subdomains"] / r["seconds"],
                      "seconds": r["seconds"], "nodes": r["nodes"], "lower": r["lower"], "upper": r["upper"],
                      "gap": r["upper"] - r["lower"], "status": r["status"], "launches": r["launches"]}
