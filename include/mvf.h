@@ -218,7 +218,8 @@ int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
 
 /* ---- constraint propagation ------------------------------------------
  * Forward-backward bound tightening (FBBT) of node boxes, the bound
- * tightening the paper reports compatible with its method (Sec. 4.3): per
+ * tightening the paper reports compatible with its method (constraint
+ * propagation, Sec. 3.2; its effect, Sec. 4.3): per
  * box, the interval of every live DAG node (forward; a violated domain gives
  * [-inf, inf] and no narrowing through that node), the roots cut to their
  * feasible ranges (inequality roots <= 0, equality roots = 0, the objective

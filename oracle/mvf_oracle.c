@@ -835,7 +835,7 @@ int64_t orc_adaptive_splits(int n, const double *widths, int64_t budget, int32_t
 /* ------------------------------------------------------------------------ */
 
 /* The bound tightening the paper reports compatible with its method
- * (Sec. 4.3, "bound tightening"): intervals of every live node on the box
+ * (Sec. 3.2; its effect, Sec. 4.3): intervals of every live node on the box
  * (forward), the roots cut to their feasible ranges (g <= 0, h = 0, and the
  * objective <= ub), then in descending node order each operand intersected
  * with the outward-rounded inverse of its operation (backward); the box

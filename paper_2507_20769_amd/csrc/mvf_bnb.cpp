@@ -12,8 +12,8 @@
 //
 // Two launch forms: one mvf_bound call per node (plain), or the K best open
 // nodes per replay of a captured batched graph.  Optionally each taken node's
-// box is first tightened by constraint propagation (mvf_fbbt; the bound
-// tightening of Sec. 4.3).  The driver is a client of the public C ABI only.
+// box is first tightened by constraint propagation (mvf_fbbt; the constraint
+// propagation of Sec. 3.2 and 4.3).  The driver is a client of the public C ABI only.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
