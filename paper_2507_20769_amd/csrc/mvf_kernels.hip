@@ -1042,7 +1042,8 @@ static hipError_t allow_lds(K kernel) {
 // ---------------------------------------------------------------------------
 //
 // The bound tightening the paper reports compatible with its method
-// (constraint propagation, Sec. 3.2; its effect, Sec. 4.3): one lane per box walks the tape's DAG forward (the bounding interval
+// (constraint propagation, Sec. 3.2; its effect, Sec. 4.3): one lane per box
+// walks the tape's DAG forward (the bounding interval
 // extension of every live node; a violated domain gives [-inf, inf] and marks
 // the node as carrying no information), cuts the roots to their feasible
 // ranges (g <= 0, h = 0, objective <= ub), then backward in descending node
