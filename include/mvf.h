@@ -105,6 +105,8 @@ typedef struct {
     int32_t max_records;      /* reverse-mode tape records per subdomain (largest root program) */
     int64_t ref_ops_fwd;      /* reference FP64 op count per subdomain, forward mode */
     int64_t ref_ops_rev;      /* reference FP64 op count per subdomain, reverse mode */
+    int64_t ref_ops_fwd_sparse;   /* forward mode without the structurally zero tangent components
+                                     (what the specialised kernels compute) */
 } mvf_tape_stats;
 int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
                    int32_t n_vars, const int32_t *roots, int32_t n_roots, mvf_tape_stats *stats);
@@ -186,7 +188,13 @@ int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stre
  * run time with hiprtc for the current device and keeps the loaded module in
  * the tape.  Each operation is the one the interpreter performs, in the same
  * order, so the bounds are bitwise identical; no instruction is decoded or
- * dispatched at run time.  Compilation takes seconds to a minute,
+ * dispatched at run time.  Tangent components that are structurally zero (a
+ * node that does not depend on the component's variable) are neither stored
+ * nor computed: with finite enclosures this changes at most the sign of zero
+ * endpoints; where a dense product of such a zero with an enclosure unbounded
+ * on both sides would give NaN, the exact zero is kept.  The default chunk is
+ * the largest whose live values and nonzero components (estimated per pass)
+ * stay within about 100 intervals.  Compilation takes seconds to a minute,
  * about linear in the generated size (code_units = sum over roots of program
  * length x passes, the adjoint counting two); MVF_ELIMIT above max_code.  With use_cache the code
  * object is kept under $MVF_SPEC_CACHE (default ~/.cache/mvf_spec; "off"

@@ -119,6 +119,7 @@ void fill_stats(const Compiled &C, mvf_tape_stats *st) {
     st->max_records = C.max_rec;
     st->ref_ops_fwd = C.ref_fwd;
     st->ref_ops_rev = C.ref_rev;
+    st->ref_ops_fwd_sparse = C.ref_fwd_sparse;
 }
 
 TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {

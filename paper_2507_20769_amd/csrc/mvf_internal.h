@@ -34,7 +34,7 @@ struct Compiled {
     int32_t max_rec = 0;             // largest record count of a root program
     int32_t chunk = 0;               // tangent components per forward pass (set by the library)
     int32_t spill = 0;               // LDS spill slots per lane at that chunk
-    int64_t ref_fwd = 0, ref_rev = 0;
+    int64_t ref_fwd = 0, ref_rev = 0, ref_fwd_sparse = 0;
 };
 
 // Records the message returned by mvf_last_error() and returns code.

@@ -9,8 +9,9 @@
 // a time, MVF = [f(c)] + sum_i G_i (X_i - c_i) intersected with the NIE.  The
 // generator walks the same instructions (with their constant-operand forms and
 // slot-0 forwarding) and emits, per instruction, the calls the interpreter
-// makes for that opcode and operand kinds; slots become variables.  Only the
-// decode, the dispatch and the slot-file moves disappear.
+// makes for that opcode and operand kinds; slots become variables.  The
+// decode, the dispatch and the slot-file moves disappear, and so does the
+// arithmetic on structurally zero tangent components.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -60,6 +61,30 @@ std::string lit(double x) {               // exact double literal
     char buf[64];
     std::snprintf(buf, sizeof buf, "%a", x);
     return buf;
+}
+
+// Tangent components that are structurally zero (the node does not depend on
+// the component's variable) are carried as the literal kZero and cost nothing:
+// a sum with zero is the other operand, a difference from zero its negation,
+// and a product with zero is zero.  Where every enclosure involved is finite
+// this is exactly the dense computation (endpoint products with zero are
+// zeros; only the signs of zero endpoints may differ); a dense product of a
+// zero component with an enclosure that is unbounded on both sides would be
+// NaN where the exact derivative, zero, is kept here.
+bool is_zero(const std::string &x) { return x == "kZero"; }
+std::string add_tan(const std::string &x, const std::string &y) {
+    if (is_zero(x)) return y;
+    if (is_zero(y)) return x;
+    return "iadd(" + x + ", " + y + ")";
+}
+std::string sub_tan(const std::string &x, const std::string &y) {
+    if (is_zero(y)) return x;
+    if (is_zero(x)) return "ineg(" + y + ")";
+    return "isub(" + x + ", " + y + ")";
+}
+// f(x) for a product or scaling of x: zero stays zero
+std::string scale_tan(const std::string &x, const std::string &pre, const std::string &post) {
+    return is_zero(x) ? x : pre + x + post;
 }
 
 // One pass over one root program.  C == 0: values only, variables at the
@@ -226,12 +251,8 @@ class PassWriter {
         const std::string z = "v" + std::to_string(pc);
         std::string s;                                   // the statements of this instruction
         std::vector<std::string> Z(C, "kZero");
-        auto at_hit = [&](int h, const std::string &fz) {   // fz(x) with x = current component
-            if (h < 0) return;
-            std::string e = fz;
-            for (size_t p; (p = e.find("@")) != std::string::npos;) e.replace(p, 1, Z[h]);
-            Z[h] = e;
-        };
+        auto hit_add = [&](int h, const std::string &x) { if (h >= 0) Z[h] = add_tan(Z[h], x); };
+        auto hit_sub = [&](int h, const std::string &x) { if (h >= 0) Z[h] = sub_tan(Z[h], x); };
         const std::string k = lit(I.k);
         switch (I.op) {
         case I_ADD:
@@ -239,17 +260,18 @@ class PassWriter {
             const bool add = I.op == I_ADD;
             s += z + " = " + (add ? "iadd(" : "isub(") + U + ", " + V + ");";
             if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
-            if (bd) for (int t = 0; t < C; ++t) Z[t] = std::string(add ? "iadd(" : "isub(") + Z[t] + ", " + B[t] + ")";
-            at_hit(ha, "iadd(@, kOne)");
-            at_hit(hb, add ? "iadd(@, kOne)" : "isub(@, kOne)");
+            if (bd) for (int t = 0; t < C; ++t) Z[t] = add ? add_tan(Z[t], B[t]) : sub_tan(Z[t], B[t]);
+            hit_add(ha, "kOne");
+            if (add) hit_add(hb, "kOne");
+            else hit_sub(hb, "kOne");
             break;
         }
         case I_MUL:
             s += z + " = imul(" + U + ", " + V + ");";
-            if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul(" + V + ", " + A[t] + ")";
-            if (bd) for (int t = 0; t < C; ++t) Z[t] = "iadd(" + Z[t] + ", imul(" + U + ", " + B[t] + "))";
-            at_hit(ha, "iadd(@, " + V + ")");
-            at_hit(hb, "iadd(@, " + U + ")");
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = scale_tan(A[t], "imul(" + V + ", ", ")");
+            if (bd) for (int t = 0; t < C; ++t) Z[t] = add_tan(Z[t], scale_tan(B[t], "imul(" + U + ", ", ")"));
+            hit_add(ha, V);
+            hit_add(hb, U);
             break;
         case I_DIV: {
             const std::string tv = "b" + std::to_string(pc);
@@ -264,11 +286,10 @@ class PassWriter {
             if (C > 0) {
                 const std::string R = "r" + std::to_string(pc);
                 if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
-                if (bd) for (int t = 0; t < C; ++t) Z[t] = "isub(" + Z[t] + ", imul(" + z + ", " + B[t] + "))";
-                at_hit(ha, "iadd(@, kOne)");
-                at_hit(hb, "isub(@, " + z + ")");
-                if (ad || bd || ha >= 0 || hb >= 0)
-                    for (int t = 0; t < C; ++t) Z[t] = "imul(" + Z[t] + ", " + R + ")";
+                if (bd) for (int t = 0; t < C; ++t) Z[t] = sub_tan(Z[t], scale_tan(B[t], "imul(" + z + ", ", ")"));
+                hit_add(ha, "kOne");
+                hit_sub(hb, z);
+                for (int t = 0; t < C; ++t) Z[t] = scale_tan(Z[t], "imul(", ", " + R + ")");
             }
             break;
         }
@@ -310,7 +331,7 @@ class PassWriter {
                 s += " " + D + " = " + dexpr + ";";
             }
             if (C > 0) {
-                if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul(" + D + ", " + A[t] + ")";
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = scale_tan(A[t], "imul(" + D + ", ", ")");
                 if (ha >= 0) Z[ha] = D;
             }
             break;
@@ -325,7 +346,7 @@ class PassWriter {
             if (I.op == I_ADDK) s += z + " = Iv{fadd(" + tu + ".lo, " + k + "), fsub(" + tu + ".nh, " + k + ")};";
             else if (ks) s += z + " = Iv{fadd(" + k + ", " + tu + ".nh), fsub(" + tu + ".lo, " + k + ")};";
             else s += z + " = " + tu + ";";
-            if (ad) for (int t = 0; t < C; ++t) Z[t] = ks ? "ineg(" + A[t] + ")" : A[t];
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = ks ? scale_tan(A[t], "ineg(", ")") : A[t];
             if (ha >= 0) Z[ha] = ks ? "ineg(kOne)" : "kOne";
             break;
         }
@@ -334,7 +355,7 @@ class PassWriter {
             const bool ng = I.op == I_MULKN;
             auto sg = [&](const std::string &x) { return ng ? "ineg(" + x + ")" : x; };
             s += z + " = imulk(" + sg(U) + ", " + k + ");";
-            if (ad) for (int t = 0; t < C; ++t) Z[t] = "imulk(" + sg(A[t]) + ", " + k + ")";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : "imulk(" + sg(A[t]) + ", " + k + ")";
             if (ha >= 0) Z[ha] = "imulk(" + sg("kOne") + ", " + k + ")";
             break;
         }
@@ -344,7 +365,7 @@ class PassWriter {
             s += z + " = idivk(" + sg(U) + ", " + k + ");";
             if (C > 0) {
                 const std::string R = aux_literal(P.instr.at(I.b));
-                if (ad) for (int t = 0; t < C; ++t) Z[t] = "imul_pos(" + sg(A[t]) + ", " + R + ")";
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : "imul_pos(" + sg(A[t]) + ", " + R + ")";
                 if (ha >= 0) Z[ha] = "imul_pos(" + sg("kOne") + ", " + R + ")";
             }
             break;
@@ -353,6 +374,10 @@ class PassWriter {
         decl.push_back("Iv " + z + ";");
         std::vector<std::string> tn(C);
         for (int t = 0; t < C; ++t) {
+            if (is_zero(Z[t])) {
+                tn[t] = Z[t];
+                continue;
+            }
             tn[t] = "g" + std::to_string(pc) + "_" + std::to_string(t);
             decl.push_back("Iv " + tn[t] + ";");
             s += " " + tn[t] + " = " + Z[t] + ";";
@@ -390,8 +415,10 @@ void write_adjoint(std::string &out, const Compiled &P, int r, const std::string
     out += "    return " + val + ";\n}\n";
 }
 
-// a pass as a function: C == 0 returns the value; C > 0 also writes G[0..C)
-void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool point, const std::string &name) {
+// a pass as a function: C == 0 returns the value; C > 0 also writes G[0..C).
+// Returns which components of the root's gradient are structurally zero.
+std::vector<bool> write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool point,
+                             const std::string &name) {
     std::vector<std::string> decl, body, tan;
     std::string val;
     PassWriter(P, r, C, c0, point).emit(decl, body, val, tan);
@@ -400,8 +427,69 @@ void write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool 
     out += ") {\n";
     for (const auto &d : decl) out += "    " + d + "\n";
     write_guarded(out, body);
-    for (int t = 0; t < C; ++t) out += "    G[" + std::to_string(t) + "] = " + tan[t] + ";\n";
+    std::vector<bool> zero(C);
+    for (int t = 0; t < C; ++t) {
+        out += "    G[" + std::to_string(t) + "] = " + tan[t] + ";\n";
+        zero[t] = is_zero(tan[t]);
+    }
     out += "    return " + val + ";\n}\n";
+    return zero;
+}
+
+// Peak number of intervals a tangent pass over components cmask keeps live:
+// every value from its instruction to its last read (the root's to the end),
+// each with its structurally nonzero components in the pass.
+int peak_live(const Compiled &P, const RootProg &rp, uint64_t cmask) {
+    const int len = rp.len;
+    std::vector<uint64_t> dep(len);                       // variables the value of instruction pc depends on
+    std::vector<int> last(len, -1), prod(std::max(rp.n_slots, 1) + 1, -1);
+    auto operand = [&](uint32_t kind, uint32_t a, int pc) -> uint64_t {
+        if (kind == K_VAR) return a < 64 ? 1ull << a : 0;
+        if (kind != K_SLOT || a >= prod.size() || prod[a] < 0) return 0;
+        last[prod[a]] = pc;
+        return dep[prod[a]];
+    };
+    for (int pc = 0; pc < len; ++pc) {
+        const Dec I = decode(P.instr[rp.begin + pc]);
+        uint64_t m = operand(I.ak, I.a, pc);
+        if (I.op <= I_DIV) m |= operand(I.bk, I.b, pc);
+        dep[pc] = m;
+        if (I.d >= prod.size()) prod.resize(I.d + 1, -1);
+        prod[I.d] = pc;
+    }
+    if (rp.result_slot >= 0 && (size_t)rp.result_slot < prod.size() && prod[rp.result_slot] >= 0)
+        last[prod[rp.result_slot]] = len;
+    std::vector<int> delta(len + 2, 0);                   // live intervals: + at the definition, - after the last read
+    for (int pc = 0; pc < len; ++pc) {
+        const int w = 1 + __builtin_popcountll(dep[pc] & cmask);
+        delta[pc] += w;
+        delta[std::max(last[pc], pc) + 1] -= w;
+    }
+    int cur = 0, peak = 0;
+    for (int pc = 0; pc < len; ++pc) peak = std::max(peak, cur += delta[pc]);
+    return peak;
+}
+
+// Default tangent chunk: the fewest passes whose live intervals stay near the
+// register file (values recomputed per pass cost more than a few spills, a
+// register file overflowing into scratch costs more than an extra pass).
+constexpr int LIVE_LIMIT = 100;     // intervals (4 VGPRs each)
+
+int default_chunk(const Compiled &P) {
+    const int n = P.n_vars;
+    for (int passes = 1; passes <= n; ++passes) {
+        const int c = (n + passes - 1) / passes;
+        if (passes > 1 && c == (n + passes - 2) / (passes - 1)) continue;   // same chunk as one pass fewer
+        int peak = 0;
+        for (const auto &rp : P.roots)
+            for (int c0 = 0; c0 < n; c0 += c) {
+                const int cw = std::min(c, n - c0);
+                const uint64_t cmask = (cw >= 64 ? ~0ull : ((1ull << cw) - 1)) << c0;
+                peak = std::max(peak, peak_live(P, rp, cmask));
+            }
+        if (peak <= LIVE_LIMIT) return c;
+    }
+    return 1;
 }
 
 }  // namespace
@@ -412,10 +500,7 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     if (grad < MVF_GRAD_FWD || grad > MVF_GRAD_AUTO) return set_error(MVF_EINVAL, "bad grad");
     const bool fwd = grad != MVF_GRAD_REV, rev = grad != MVF_GRAD_FWD;
     int c = opt && opt->chunk > 0 ? opt->chunk : 0;
-    if (c == 0) {
-        const int passes = (n + 2) / 3;
-        c = (n + passes - 1) / passes;
-    }
+    if (c == 0) c = fwd ? default_chunk(P) : 1;
     if (c < 1 || c > n) return set_error(MVF_EINVAL, "chunk out of range [1, n]");
     const int passes = (n + c - 1) / c;
     int64_t u = 0;     // point and value passes, tangent passes, the adjoint's value pass and sweep
@@ -443,13 +528,16 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
     s += "constexpr int N_VARS = " + std::to_string(n) + ", N_ROOTS = " + std::to_string(m) + ";\n";
     s += "template <bool REV>\n__device__ uint32_t lane(const SpecLane &L, int mode, bool go, const LaneOut &o, "
          "FeasTrack &F);\n";
+    std::vector<std::vector<bool>> zero(m, std::vector<bool>(n));     // structurally zero gradient components
     for (int r = 0; r < m; ++r) {
         write_pass(s, P, r, 0, 0, true, "point_" + std::to_string(r));
         write_pass(s, P, r, 0, 0, false, "value_" + std::to_string(r));
         if (fwd)
-            for (int c0 = 0; c0 < n; c0 += chunk)
-                write_pass(s, P, r, std::min(chunk, n - c0), c0, false,
-                           "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
+            for (int c0 = 0; c0 < n; c0 += chunk) {
+                const auto z = write_pass(s, P, r, std::min(chunk, n - c0), c0, false,
+                                          "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
+                for (size_t t = 0; t < z.size(); ++t) zero[r][c0 + t] = z[t];
+            }
         if (rev) write_adjoint(s, P, r, "adjoint_" + std::to_string(r));
     }
     if (rev) {
@@ -490,9 +578,10 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
             s += "            {\n                Iv G[" + std::to_string(c) + "];\n";
             s += "                const Iv v = tangent_" + R + "_" + std::to_string(c0) + "(L, go, bad, G);\n";
             if (c0 == 0) s += "                nie = v;\n";
-            for (int t = 0; t < c; ++t)
-                s += "                acc = iadd(acc, imul(G[" + std::to_string(t) + "], spec_dx(L, " +
-                     std::to_string(c0 + t) + ")));\n";
+            for (int t = 0; t < c; ++t)      // a zero component adds nothing
+                if (!zero[r][c0 + t])
+                    s += "                acc = iadd(acc, imul(G[" + std::to_string(t) + "], spec_dx(L, " +
+                         std::to_string(c0 + t) + ")));\n";
             s += "            }\n";
         }
         s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";

@@ -66,6 +66,33 @@ void recip_enclosure(double k, double *lo, double *hi) {
     else { *lo = q; *hi = std::nextafter(q, INFINITY); }
 }
 
+// Tangent cost of one node summed over the components it depends on, in the
+// units of ref_cost: what the forward mode does when structurally zero
+// components are skipped (a sum with a zero component is the other term, a
+// product with a variable's unit component the other factor).
+int64_t sparse_tan_cost(const mvf_node *nodes, const mvf_node &nd, const std::vector<uint64_t> &dep) {
+    const bool bin = is_binary(nd.op);
+    const int ao = nodes[nd.a].op, bo = bin ? nodes[nd.b].op : -1;
+    const bool konst = ao == MVF_CONST || bo == MVF_CONST;
+    const uint64_t da = dep[nd.a], db = bin ? dep[nd.b] : 0;
+    int64_t c = 0;
+    for (uint64_t u = da | db; u; u &= u - 1) {
+        const uint64_t j = u & (~u + 1);
+        const bool a = (da & j) != 0, b = (db & j) != 0;
+        switch (nd.op) {
+        case MVF_ADD: case MVF_SUB: c += a && b ? 2 : 0; break;
+        case MVF_MUL:
+            c += konst ? 2 : (a && ao != MVF_VAR ? 14 : 0) + (b && bo != MVF_VAR ? 14 : 0) + (a && b ? 2 : 0);
+            break;
+        case MVF_DIV:
+            c += bo == MVF_CONST ? 2 : (b && bo != MVF_VAR ? 14 : 0) + (a && b ? 2 : 0) + 14;
+            break;
+        default: c += ao == MVF_VAR ? 0 : 14;      // the derivative times the component
+        }
+    }
+    return c;
+}
+
 int fail(std::string *err, int code, const char *fmt, long a = 0, long b = 0) {
     if (err) {
         char buf[256];
@@ -106,7 +133,16 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
     std::vector<uint8_t> in_cone(n_nodes), in_regs(n_nodes);
     std::vector<int32_t> slot_of(n_nodes, -1), last_use(n_nodes, -1), uses(n_nodes, 0);
     std::vector<double> aux;            // reciprocal enclosures of constant divisors, (lo, -hi) pairs
-    int64_t sum_val = 0, sum_tan = 0, sum_adj = 0, n_ops = 0;
+    int64_t sum_val = 0, sum_tan = 0, sum_adj = 0, n_ops = 0, sum_tan_sparse = 0, combine_sparse = 0;
+    // variables each node depends on: its structurally nonzero tangent components
+    std::vector<uint64_t> dep(n_nodes, 0);
+    for (int i = 0; i < n_nodes; ++i) {
+        const mvf_node &nd = nodes[i];
+        if (nd.op == MVF_VAR) dep[i] = nd.a < 64 ? 1ull << nd.a : 0;
+        else if (is_binary(nd.op)) dep[i] = dep[nd.a] | dep[nd.b];
+        else if (is_unary(nd.op)) dep[i] = dep[nd.a];
+    }
+    for (int r = 0; r < n_roots; ++r) combine_sparse += 16 * __builtin_popcountll(dep[roots[r]]) + 2;
 
     // Programs 0 .. m-1 compute one root each (bounding, gradients of one root);
     // program m is the union of all root cones with every root kept live to
@@ -247,6 +283,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
                 int cv, ct, ca;
                 ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
                 sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
+                sum_tan_sparse += sparse_tan_cost(nodes, nd, dep);
                 if (nd.op == MVF_SQR || nd.op == MVF_SQRT) sum_val += 2;   // 2U or 1/(2Z), once per op
             }
         }
@@ -332,6 +369,7 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
     const int64_t n = n_vars, m = n_roots;
     C.ref_fwd = sum_val + n * sum_tan + 2 * n_ops + m * (16 * n + 2) + 10 * n;
     C.ref_rev = sum_val + sum_adj + 2 * n_ops + m * (16 * n + 2) + 10 * n;
+    C.ref_fwd_sparse = sum_val + sum_tan_sparse + 2 * n_ops + combine_sparse + 10 * n;
     *out = std::move(C);
     return MVF_OK;
 }

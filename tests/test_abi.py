@@ -64,6 +64,23 @@ def test_valid_tapes_compile_and_report_costs():
     assert mvf.check(I.mid(1).tape).tangent_chunk >= 1
 
 
+def test_sparse_forward_op_count():
+    # f = x0 * x1, n = 2.  Dense: value 14, tangents 2 x 30, 2 per op, combine 16 n + 2, 10 n
+    # -> 130.  Without structurally zero components each component of the product is the
+    # other variable's enclosure (x0's unit component times x1): no tangent arithmetic -> 70.
+    st = mvf.check(_tape([(I.VAR, 0, -1), (I.VAR, 1, -1), (I.MUL, 0, 1)], [], [2], 2))
+    assert (st.ref_ops_fwd, st.ref_ops_fwd_sparse) == (130, 70)
+    # g = exp(x0) + x1 * x1 (n = 3, x2 unused): dense 2 + 14 + 2 + 3 x (14 + 30 + 2) + 3 x 2 + 50 + 30;
+    # sparse: exp's component 0 is its derivative itself (0), the product's component 1 the sum of
+    # the two unit terms (2), the sum has no component in both terms (0), combine over 2 components
+    st = mvf.check(_tape([(I.VAR, 0, -1), (I.VAR, 1, -1), (I.EXP, 0, -1), (I.MUL, 1, 1), (I.ADD, 2, 3)], [], [4], 3))
+    assert st.ref_ops_fwd == 2 + 14 + 2 + 3 * (14 + 30 + 2) + 3 * 2 + 50 + 30
+    assert st.ref_ops_fwd_sparse == 2 + 14 + 2 + 2 + 3 * 2 + 34 + 30
+    for w in (I.tiny(1), I.mid(1), I.ann(1)):
+        st = mvf.check(w.tape)
+        assert 0 < st.ref_ops_fwd_sparse <= st.ref_ops_fwd
+
+
 def test_leaf_roots_compile():
     st = mvf.check(_tape([(I.VAR, 0, -1), (I.CONST, 0, -1)], [2.5], [0, 1], 1))
     assert st.n_instr == 2

@@ -32,6 +32,53 @@ def _trig():
     return _tape(nodes, [3.0], [9, 11], 2)
 
 
+def _deps(tape):
+    """Variables each node depends on, as bit masks."""
+    dep = []
+    for op, a, b in zip(tape.nodes["op"], tape.nodes["a"], tape.nodes["b"]):
+        if op == I.VAR:
+            dep.append(1 << int(a))
+        elif op == I.CONST:
+            dep.append(0)
+        else:
+            dep.append(dep[a] | (dep[b] if op in (I.ADD, I.SUB, I.MUL, I.DIV) else 0))
+    return dep
+
+
+def _peak_live(tape, root, cmask, dep):
+    """Intervals a tangent pass keeps live: each operation's value from its node to its last
+    reader (the root's to the end) with its structurally nonzero components in cmask."""
+    ops, A, B = tape.nodes["op"], tape.nodes["a"], tape.nodes["b"]
+    cone, stack = set(), [int(root)]
+    while stack:
+        x = stack.pop()
+        if x not in cone:
+            cone.add(x)
+            if ops[x] >= I.ADD:
+                stack.append(int(A[x]))
+            if ops[x] in (I.ADD, I.SUB, I.MUL, I.DIV):
+                stack.append(int(B[x]))
+    order = sorted(x for x in cone if ops[x] not in (I.VAR, I.CONST))
+    last = {int(root): len(tape.nodes)}
+    for x in order:
+        for y in ([A[x], B[x]] if ops[x] in (I.ADD, I.SUB, I.MUL, I.DIV) else [A[x]]):
+            last[int(y)] = max(last.get(int(y), -1), x)
+    return max((sum(1 + bin(dep[y] & cmask).count("1") for y in order if y <= x and last.get(y, y) >= x)
+                for x in order), default=1)
+
+
+def _default_chunk(tape, limit=100):
+    """The fewest tangent passes whose live intervals stay within the limit."""
+    n, dep = tape.n_vars, _deps(tape)
+    for passes in range(1, n + 1):
+        c = -(-n // passes)
+        peak = max(_peak_live(tape, r, ((1 << min(c, n - c0)) - 1) << c0, dep)
+                   for r in tape.roots for c0 in range(0, n, c))
+        if peak <= limit:
+            return c
+    return 1
+
+
 @pytest.mark.parametrize("name", ["cubic", "every form", "tiny", "random", "trig"])
 def test_generated_source_compiles(name):
     tape = {"cubic": I.cubic_tape, "every form": _every_form, "tiny": lambda: I.tiny(1).tape,
@@ -40,10 +87,42 @@ def test_generated_source_compiles(name):
     st = mvf.check(tape)
     info = mvf.spec_check(tape)
     n = tape.n_vars
-    passes = (n + 2) // 3
-    assert info["chunk"] == (n + passes - 1) // passes
+    assert info["chunk"] == _default_chunk(tape) == n        # small live sets: one pass
     assert info["code_units"] == st.n_instr * (2 + -(-n // info["chunk"]))
     assert info["code_bytes"] > 0 and info["from_cache"] == 0 and info["waves"] == 2
+
+
+def test_default_chunk_follows_the_live_set():
+    # mid's live set fits one pass of all six components; the tanh network's dense layers
+    # keep 16 values with 4 components each live, so it takes two passes of two.  The plan
+    # (chunk and size) is made before the size limit refuses the tape.
+    for tape, want in ((I.mid(1).tape, 6), (I.ann(1).tape, 2)):
+        assert _default_chunk(tape) == want
+        with pytest.raises(mvf.MVFError):
+            mvf.spec_check(tape, grad="fwd", max_code=10)
+        units = mvf.check(tape).n_instr * (2 + -(-tape.n_vars // want))
+        assert f"{units} instruction-passes" in mvf.lib().mvf_last_error().decode()
+
+
+def test_structurally_zero_components_are_not_computed(tmp_path, monkeypatch):
+    # f = x0 x1 + sqr(x2) depends on every variable, g = exp(x0) only on x0: g's tangent pass
+    # hands back exact zeros for x1 and x2 and the MVF combine of g skips them
+    V = I.VAR
+    t = _tape([(V, 0, -1), (V, 1, -1), (V, 2, -1), (I.MUL, 0, 1), (I.SQR, 2, -1), (I.ADD, 3, 4),
+               (I.EXP, 0, -1)], [], [5, 6], 3)
+    dump = tmp_path / "g.hip"
+    monkeypatch.setenv("MVF_SPEC_DUMP", str(dump))
+    info = mvf.spec_check(t, grad="fwd")
+    assert info["chunk"] == 3
+    src = dump.read_text()
+    funcs = {f.split("(")[0].split()[-1]: f for f in src.split("__device__")[1:]}
+    g_pass = funcs["tangent_1_0"]
+    assert "G[1] = kZero;" in g_pass and "G[2] = kZero;" in g_pass and "G[0] = kZero;" not in g_pass
+    lane = funcs["lane<false>"]
+    root1 = lane[lane.index("tangent_1_0"):]
+    assert "spec_dx(L, 0)" in root1 and "spec_dx(L, 1)" not in root1 and "spec_dx(L, 2)" not in root1
+    f_pass = funcs["tangent_0_0"]
+    assert "kZero;" not in f_pass.split("return")[0].split("G[0]")[-1]       # f: no zero component
 
 
 def test_chunk_and_waves_options():
