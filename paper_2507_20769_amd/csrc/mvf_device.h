@@ -135,48 +135,51 @@ __device__ __forceinline__ void sqrt_rn2(double a0, double a1, double &s0, doubl
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(s0), "+v"(s1));
 }
 
-// Correctly rounded-down quotients x0 / y0 and x1 / y1.  Each estimate is
-// within one ulp of the exact quotient t, so RD(t) is the estimate or one of
-// its neighbours: one step down while q * |y| > |x| and one step up while
-// succ(q) * |y| <= |x|, each decided by the sign of the exact residual (an
-// fma rounded down is negative iff the exact residual is).  The two chains
-// are interleaved so each compare-and-select has independent work beside it.
+// x with its sign flipped where y is negative (x * sign(y), exact): two
+// 32-bit logic operations on the high words instead of two selects
+__device__ __forceinline__ double flip_by(double x, double y) {
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x), yb = __builtin_bit_cast(uint64_t, y);
+    return __builtin_bit_cast(double, xb ^ (yb & 0x8000000000000000ull));
+}
+__device__ __forceinline__ double ffma_n_abs(double a, double b, double c) {   // RD(-a*|b| + c)
+    double r;
+    asm volatile("v_fma_f64 %0, -%1, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+// next double below a finite x (fadd_s rounds down; +inf stays +inf)
+__device__ __forceinline__ double pred_finite(double x) { return fadd_s(x, -kTiny); }
+
+// Correctly rounded-down quotients x0 / y0 and x1 / y1 (y != 0).  The
+// estimate q is the correctly rounded-to-nearest quotient, so no double lies
+// strictly between q and the exact quotient t: RD(t) is q when q <= t and the
+// predecessor of q otherwise.  q > t exactly when the residual x*sign(y) -
+// q*|y| is negative, and an fma rounded down keeps the sign of the exact
+// residual.  A finite quotient that overflows to +inf in round-to-nearest
+// rounds down to the largest finite double.  The two chains are interleaved
+// so each compare-and-select has independent work beside it.
 __device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double y1, double &r0, double &r1) {
     double q0, q1;
     div_rn2(x0, y0, x1, y1, q0, q1);
-    const bool n0 = y0 < 0.0, n1 = y1 < 0.0;
-    const double xs0 = n0 ? -x0 : x0, ys0 = n0 ? -y0 : y0;   // now ys > 0
-    const double xs1 = n1 ? -x1 : x1, ys1 = n1 ? -y1 : y1;
-    if (q0 == __builtin_inf() && __builtin_isfinite(x0) && __builtin_isfinite(y0)) q0 = kMax;
-    if (q1 == __builtin_inf() && __builtin_isfinite(x1) && __builtin_isfinite(y1)) q1 = kMax;
-    const double e0 = ffma_n(q0, ys0, xs0), e1 = ffma_n(q1, ys1, xs1);   // RD(xs - q*ys)
-    const double d0 = pred(q0), d1 = pred(q1);
-    q0 = e0 < 0.0 ? d0 : q0;
-    q1 = e1 < 0.0 ? d1 : q1;
-    const double u0 = succ(q0), u1 = succ(q1);
-    const double f0 = ffma_n(u0, ys0, xs0), f1 = ffma_n(u1, ys1, xs1);
-    r0 = f0 >= 0.0 ? u0 : q0;
-    r1 = f1 >= 0.0 ? u1 : q1;
+    if (q0 == __builtin_inf() && __builtin_isfinite(x0)) q0 = kMax;
+    if (q1 == __builtin_inf() && __builtin_isfinite(x1)) q1 = kMax;
+    const double e0 = ffma_n_abs(q0, y0, flip_by(x0, y0)), e1 = ffma_n_abs(q1, y1, flip_by(x1, y1));
+    const double d0 = pred_finite(q0), d1 = pred_finite(q1);
+    r0 = e0 < 0.0 ? d0 : q0;
+    r1 = e1 < 0.0 ? d1 : q1;
 }
 
-// [RD(sqrt(a)), -RU(sqrt(b))] for a, b >= 0, from round-to-nearest estimates
-// corrected as in div_rd2 (residual a - s*s), the upper end then stepped up
-// unless its square is exact.
+// [RD(sqrt(a)), -RU(sqrt(b))] for a, b >= 0 from the correctly rounded-to-
+// nearest roots s: the lower end is s, or its predecessor when s*s > a; the
+// upper end s, or its successor when s*s < b (residual signs as in div_rd2).
 __device__ __forceinline__ void sqrt_rd_ru2(double a, double b, double &lo, double &nh) {
     double s0, s1;
     sqrt_rn2(a, b, s0, s1);
-    const double e0 = ffma_n(s0, s0, a), e1 = ffma_n(s1, s1, b);       // RD(a - s*s)
-    const double d0 = pred(s0), d1 = pred(s1);
-    s0 = e0 < 0.0 ? d0 : s0;
-    s1 = e1 < 0.0 ? d1 : s1;
-    const double u0 = succ(s0), u1 = succ(s1);
-    const double f0 = ffma_n(u0, u0, a), f1 = ffma_n(u1, u1, b);
-    s0 = f0 >= 0.0 ? u0 : s0;
-    s1 = f1 >= 0.0 ? u1 : s1;
-    const double g = ffma_nn(s1, s1, b);                               // RD(s*s - b) < 0 iff s*s < b
-    const double su = succ(s1);
-    lo = s0;
-    nh = -(g < 0.0 ? su : s1);
+    const double e0 = ffma_n(s0, s0, a);                               // RD(a - s*s)
+    const double g = ffma_nn(s1, s1, b);                               // RD(s*s - b)
+    const double d0 = pred_finite(s0);
+    const double u1 = -pred_finite(-s1);
+    lo = e0 < 0.0 ? d0 : s0;
+    nh = -(g < 0.0 ? u1 : s1);
 }
 
 // ---- interval operations on (lo, nh) -------------------------------------
