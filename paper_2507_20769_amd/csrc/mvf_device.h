@@ -229,6 +229,14 @@ __device__ __forceinline__ Iv idiv(Iv u, Iv v) {
     return z;
 }
 
+// U / V for V > 0: the selection idiv makes for a positive denominator
+__device__ __forceinline__ Iv idiv_pos(Iv u, Iv v) {
+    const double a = u.lo, b = -u.nh, c = v.lo, d = -v.nh;
+    Iv z;
+    div_rd2(a, a >= 0.0 ? d : c, -b, b >= 0.0 ? c : d, z.lo, z.nh);
+    return z;
+}
+
 // 1 / V with 0 not in V: [RD(1/d), RU(1/c)]
 __device__ __forceinline__ Iv irecip(Iv v) {
     Iv z;

@@ -105,6 +105,7 @@ class PassWriter {
         slot_val.assign(std::max(rp.n_slots, 1) + 1, "");
         slot_tan.assign(slot_val.size(), std::vector<std::string>());
         slot_prod.assign(slot_val.size(), -1);
+        slot_nn.assign(slot_val.size(), 0);
         for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) instr(pc, decl, body);
         const int rs = rp.result_slot;
         val = slot_val.at(rs);
@@ -144,15 +145,15 @@ class PassWriter {
                 contribute(I.bk, I.b, st.pb, ib, I.op == I_SUB, zb);
                 break;
             case I_MUL:
-                if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, "imul(" + zb + ", " + st.V + ")");
-                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, false, "imul(" + zb + ", " + st.U + ")");
+                if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, mul_by(zb, st.V, st.nv, false));
+                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, false, mul_by(zb, st.U, st.nu, false));
                 break;
             case I_DIV: {
                 const std::string T = "t" + pc;
                 decl.push_back("Iv " + T + ";");
-                s += T + " = imul(" + zb + ", r" + pc + "); ";
+                s += T + " = " + mul_by(zb, "r" + pc, st.nv, false) + "; ";
                 contribute(I.ak, I.a, st.pa, ia, false, T);
-                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, true, "imul(" + T + ", v" + pc + ")");
+                if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, true, mul_by(T, "v" + pc, st.nz, false));
                 break;
             }
             case I_SQR:
@@ -162,7 +163,8 @@ class PassWriter {
             case I_TANH:
             case I_SIN:
             case I_COS:
-                if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, "imul(" + zb + ", q" + pc + ")");
+                if (I.ak != K_CONST)
+                    contribute(I.ak, I.a, st.pa, ia, false, mul_by(zb, "q" + pc, nonneg_deriv(I, st.nu), false));
                 break;
             case I_ADDK:
             case I_KSUB:
@@ -190,11 +192,13 @@ class PassWriter {
     std::vector<std::string> slot_val;
     std::vector<std::vector<std::string>> slot_tan;
     std::vector<int> slot_prod;                  // instruction that wrote the slot's current value
+    std::vector<char> slot_nn;                   // the slot's value is nonnegative (see nonneg_result)
     struct Step {
         int pc;
         Dec I;
         std::string U, V, aux;                   // operand value expressions; 1/k enclosure of a DIVK
         int pa, pb;                              // producers of slot operands
+        bool nu, nv, nz;                         // operands and result known nonnegative
     };
     std::vector<Step> steps;
 
@@ -203,7 +207,38 @@ class PassWriter {
             slot_val.resize(s + 1);
             slot_tan.resize(s + 1);
             slot_prod.resize(s + 1, -1);
+            slot_nn.resize(s + 1, 0);
         }
+    }
+
+    // Sign facts known at generation time.  A value is "nonnegative" when every
+    // enclosure of it has lo >= 0 on every subdomain whose bounds are kept: a
+    // subdomain where a domain test fails (a denominator enclosing 0, a sqrt or
+    // log argument below 0) is flagged and its bounds are discarded.
+    bool nonneg(uint32_t kind, uint32_t a, double k) const {
+        if (kind == K_SLOT) return a < slot_nn.size() && slot_nn[a];
+        if (kind == K_CONST) return k >= 0.0;
+        return false;
+    }
+    static bool nonneg_result(const Dec &I, bool nu, bool nv) {
+        switch (I.op) {
+        case I_ADD: case I_MUL: case I_DIV: return nu && nv;
+        case I_SQR: case I_SQRT: case I_EXP: return true;
+        case I_ADDK: case I_MULK: return nu && I.k >= 0.0;
+        case I_DIVK: return nu;                   // k > 0
+        case I_LOAD: return nu;
+        default: return false;
+        }
+    }
+    // the derivative factor of a unary op is nonnegative where the bounds are kept
+    static bool nonneg_deriv(const Dec &I, bool nu) {
+        return I.op == I_SQRT || I.op == I_EXP || I.op == I_LOG || I.op == I_TANH || (I.op == I_SQR && nu);
+    }
+    // U * R, one-sided when R is known nonnegative (the extreme products then
+    // come from U's endpoints alone: the same result up to the signs of zeros)
+    static std::string mul_by(const std::string &u, const std::string &r, bool r_nn, bool r_first = true) {
+        if (r_nn) return "imul_pos(" + u + ", " + r + ")";
+        return r_first ? "imul(" + r + ", " + u + ")" : "imul(" + u + ", " + r + ")";
     }
 
     static std::string aux_literal(const Instr &aux) {
@@ -242,9 +277,11 @@ class PassWriter {
         int ha = -1, hb = -1;
         fetch(I.ak, I.a, I.k, U, A, ad, ha);
         if (I.op <= I_DIV) fetch(I.bk, I.b, I.k, V, B, bd, hb);
+        const bool nu = nonneg(I.ak, I.a, I.k), nv = I.op <= I_DIV && nonneg(I.bk, I.b, I.k);
+        const bool nz = nonneg_result(I, nu, nv);
         if (tape) {
             Step st{pc, I, U, V, "", I.ak == K_SLOT ? slot_prod.at(I.a) : -1,
-                    I.op <= I_DIV && I.bk == K_SLOT ? slot_prod.at(I.b) : -1};
+                    I.op <= I_DIV && I.bk == K_SLOT ? slot_prod.at(I.b) : -1, nu, nv, nz};
             if (I.op == I_DIVK || I.op == I_DIVKN) st.aux = aux_literal(P.instr.at(I.b));
             steps.push_back(st);
         }
@@ -267,9 +304,9 @@ class PassWriter {
             break;
         }
         case I_MUL:
-            s += z + " = imul(" + U + ", " + V + ");";
-            if (ad) for (int t = 0; t < C; ++t) Z[t] = scale_tan(A[t], "imul(" + V + ", ", ")");
-            if (bd) for (int t = 0; t < C; ++t) Z[t] = add_tan(Z[t], scale_tan(B[t], "imul(" + U + ", ", ")"));
+            s += z + " = " + (nv ? mul_by(U, V, true) : nu ? mul_by(V, U, true) : "imul(" + U + ", " + V + ")") + ";";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : mul_by(A[t], V, nv);
+            if (bd) for (int t = 0; t < C; ++t) Z[t] = add_tan(Z[t], is_zero(B[t]) ? B[t] : mul_by(B[t], U, nu));
             hit_add(ha, V);
             hit_add(hb, U);
             break;
@@ -277,7 +314,7 @@ class PassWriter {
             const std::string tv = "b" + std::to_string(pc);
             decl.push_back("Iv " + tv + ";");
             s += tv + " = " + V + "; bad |= (" + tv + ".lo <= 0.0 && " + tv + ".nh <= 0.0) ? 1u : 0u; ";
-            s += z + " = idiv(" + U + ", " + tv + ");";
+            s += z + " = " + (nv ? "idiv_pos(" : "idiv(") + U + ", " + tv + ");";
             if (C > 0 || tape) {
                 const std::string R = "r" + std::to_string(pc);
                 decl.push_back("Iv " + R + ";");
@@ -286,10 +323,11 @@ class PassWriter {
             if (C > 0) {
                 const std::string R = "r" + std::to_string(pc);
                 if (ad) for (int t = 0; t < C; ++t) Z[t] = A[t];
-                if (bd) for (int t = 0; t < C; ++t) Z[t] = sub_tan(Z[t], scale_tan(B[t], "imul(" + z + ", ", ")"));
+                if (bd)
+                    for (int t = 0; t < C; ++t) Z[t] = sub_tan(Z[t], is_zero(B[t]) ? B[t] : mul_by(B[t], z, nz));
                 hit_add(ha, "kOne");
                 hit_sub(hb, z);
-                for (int t = 0; t < C; ++t) Z[t] = scale_tan(Z[t], "imul(", ", " + R + ")");
+                for (int t = 0; t < C; ++t) Z[t] = is_zero(Z[t]) ? Z[t] : mul_by(Z[t], R, nv, false);
             }
             break;
         }
@@ -331,7 +369,8 @@ class PassWriter {
                 s += " " + D + " = " + dexpr + ";";
             }
             if (C > 0) {
-                if (ad) for (int t = 0; t < C; ++t) Z[t] = scale_tan(A[t], "imul(" + D + ", ", ")");
+                const bool dn = nonneg_deriv(I, nu);
+                if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : mul_by(A[t], D, dn);
                 if (ha >= 0) Z[ha] = D;
             }
             break;
@@ -387,6 +426,7 @@ class PassWriter {
         slot_val[I.d] = z;
         slot_tan[I.d] = tn;
         slot_prod[I.d] = pc;
+        slot_nn[I.d] = nz;
     }
 };
 
