@@ -364,6 +364,43 @@ __device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
     return {fmin_(fmul(u.lo, r.lo), fmul_n(u.lo, r.nh)), fmin_(fmul(u.nh, r.lo), fmul_n(u.nh, r.nh))};
 }
 
+// Two independent products with their instructions interleaved: each
+// operation of one product is followed by the same operation of the other,
+// so no instruction waits on the one just before it.  The results are those
+// of imul (and imul_pos) on each pair.
+__device__ __forceinline__ void imul2(Iv u, Iv v, Iv w, Iv x, Iv &r, Iv &s) {
+    const double a0 = fmul(u.lo, v.lo), b0 = fmul(w.lo, x.lo);
+    const double c0 = fmul_n(u.lo, v.lo), d0 = fmul_n(w.lo, x.lo);
+    const double a1 = fmul_n(u.lo, v.nh), b1 = fmul_n(w.lo, x.nh);
+    const double c1 = fmul(u.lo, v.nh), d1 = fmul(w.lo, x.nh);
+    double lo = fmin_(a0, a1), lo2 = fmin_(b0, b1);
+    double nh = fmin_(c0, c1), nh2 = fmin_(d0, d1);
+    const double a2 = fmul_n(u.nh, v.lo), b2 = fmul_n(w.nh, x.lo);
+    const double c2 = fmul(u.nh, v.lo), d2 = fmul(w.nh, x.lo);
+    lo = fmin_(lo, a2);
+    lo2 = fmin_(lo2, b2);
+    nh = fmin_(nh, c2);
+    nh2 = fmin_(nh2, d2);
+    const double a3 = fmul(u.nh, v.nh), b3 = fmul(w.nh, x.nh);
+    const double c3 = fmul_n(u.nh, v.nh), d3 = fmul_n(w.nh, x.nh);
+    lo = fmin_(lo, a3);
+    lo2 = fmin_(lo2, b3);
+    nh = fmin_(nh, c3);
+    nh2 = fmin_(nh2, d3);
+    r = {lo, nh};
+    s = {lo2, nh2};
+}
+__device__ __forceinline__ void imul_pos2(Iv u, Iv r, Iv w, Iv q, Iv &a, Iv &b) {
+    const double p0 = fmul(u.lo, r.lo), p1 = fmul(w.lo, q.lo);
+    const double p2 = fmul_n(u.lo, r.nh), p3 = fmul_n(w.lo, q.nh);
+    const double p4 = fmul(u.nh, r.lo), p5 = fmul(w.nh, q.lo);
+    const double p6 = fmul_n(u.nh, r.nh), p7 = fmul_n(w.nh, q.nh);
+    const double l0 = fmin_(p0, p2), l1 = fmin_(p1, p3);
+    const double n0 = fmin_(p4, p6), n1 = fmin_(p5, p7);
+    a = {l0, n0};
+    b = {l1, n1};
+}
+
 // U / k for k > 0
 __device__ __forceinline__ Iv idivk(Iv u, double k) {
     Iv z;

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <cctype>
 #include <chrono>
 #include <cinttypes>
 #include <cstdio>
@@ -86,6 +87,129 @@ std::string sub_tan(const std::string &x, const std::string &y) {
 std::string scale_tan(const std::string &x, const std::string &pre, const std::string &post) {
     return is_zero(x) ? x : pre + x + post;
 }
+
+// The statements of one instruction (its tangent components, and a product's
+// value) as trees of interval calls.  Products that do not depend on each
+// other are emitted two at a time (imul2, imul_pos2: the same operations,
+// interleaved); the rest follow in dependence order.  Only the order of the
+// instructions changes, not the arithmetic.
+class Scheduler {
+  public:
+    Scheduler(std::string prefix, std::vector<std::string> &decl) : pre(std::move(prefix)), decl(decl) {}
+
+    void add(const std::string &target, const std::string &expr) {
+        size_t i = 0;
+        roots.emplace_back(target, parse(expr, i));
+    }
+
+    std::string emit() {
+        std::vector<int> depth(pool.size(), -1);
+        int maxd = 0;
+        for (const auto &r : roots) maxd = std::max(maxd, depth_of(r.second, depth));
+        out.assign(pool.size(), "");
+        for (const auto &r : roots)
+            if (is_op(r.second)) out[r.second] = r.first;
+        std::string s;
+        for (int d = 1; d <= maxd; ++d) {
+            int pend[2] = {-1, -1};                  // an unpaired imul, imul_pos
+            for (size_t k = 0; k < pool.size(); ++k) {
+                if (depth[k] != d || !is_op((int)k)) continue;
+                const int kind = pool[k].fn == "imul" ? 0 : pool[k].fn == "imul_pos" ? 1 : -1;
+                if (kind < 0) {
+                    s += " " + name((int)k) + " = " + pool[k].fn + "(" + text(pool[k].args[0]) + ", " +
+                         text(pool[k].args[1]) + ");";
+                    continue;
+                }
+                if (pend[kind] < 0) {
+                    pend[kind] = (int)k;
+                    continue;
+                }
+                const Expr &a = pool[pend[kind]], &b = pool[k];
+                s += std::string(" ") + (kind == 0 ? "imul2(" : "imul_pos2(") + text(a.args[0]) + ", " +
+                     text(a.args[1]) + ", " + text(b.args[0]) + ", " + text(b.args[1]) + ", " + name(pend[kind]) +
+                     ", " + name((int)k) + ");";
+                pend[kind] = -1;
+            }
+            for (int kind = 0; kind < 2; ++kind)
+                if (pend[kind] >= 0)
+                    s += " " + name(pend[kind]) + " = " + pool[pend[kind]].fn + "(" + text(pool[pend[kind]].args[0]) +
+                         ", " + text(pool[pend[kind]].args[1]) + ");";
+        }
+        for (const auto &r : roots)
+            if (!is_op(r.second)) s += " " + r.first + " = " + text(r.second) + ";";
+        return s;
+    }
+
+  private:
+    struct Expr {
+        std::string fn;                          // a scheduled call, or "" for a leaf
+        std::string leaf;
+        std::vector<int> args;
+    };
+    std::string pre;
+    std::vector<std::string> &decl;
+    std::vector<Expr> pool;
+    std::vector<std::pair<std::string, int>> roots;
+    std::vector<std::string> out;                 // result names of the emitted calls
+    int n_tmp = 0;
+
+    bool is_op(int k) const { return !pool[k].fn.empty() && pool[k].fn != "ineg"; }
+    static bool scheduled(const std::string &f) {
+        return f == "imul" || f == "imul_pos" || f == "iadd" || f == "isub" || f == "imulk" || f == "ineg";
+    }
+    static void skip(const std::string &e, size_t &i) {
+        while (i < e.size() && e[i] == ' ') ++i;
+    }
+    int parse(const std::string &e, size_t &i) {
+        skip(e, i);
+        const size_t start = i;
+        size_t j = i;
+        while (j < e.size() && (std::isalnum((unsigned char)e[j]) || e[j] == '_')) ++j;
+        if (j < e.size() && e[j] == '(' && scheduled(e.substr(i, j - i))) {
+            Expr x;
+            x.fn = e.substr(i, j - i);
+            i = j + 1;
+            for (;;) {
+                x.args.push_back(parse(e, i));
+                skip(e, i);
+                if (e[i++] == ')') break;        // else ','
+            }
+            pool.push_back(x);
+            return (int)pool.size() - 1;
+        }
+        int dep = 0;                             // a leaf: up to a ',' or ')' outside brackets
+        for (i = start; i < e.size(); ++i) {
+            const char c = e[i];
+            if (c == '(' || c == '{') ++dep;
+            else if ((c == ')' || c == '}') && dep > 0) --dep;
+            else if (dep == 0 && (c == ',' || c == ')')) break;
+        }
+        size_t end = i;
+        while (end > start && e[end - 1] == ' ') --end;
+        Expr x;
+        x.leaf = e.substr(start, end - start);
+        pool.push_back(x);
+        return (int)pool.size() - 1;
+    }
+    int depth_of(int k, std::vector<int> &depth) {
+        if (depth[k] >= 0) return depth[k];
+        int d = 0;
+        for (int a : pool[k].args) d = std::max(d, depth_of(a, depth));
+        return depth[k] = pool[k].fn.empty() ? 0 : pool[k].fn == "ineg" ? d : d + 1;
+    }
+    std::string name(int k) {
+        if (out[k].empty()) {
+            out[k] = pre + std::to_string(n_tmp++);
+            decl.push_back("Iv " + out[k] + ";");
+        }
+        return out[k];
+    }
+    std::string text(int k) {
+        if (pool[k].fn.empty()) return pool[k].leaf;
+        if (pool[k].fn == "ineg") return "ineg(" + text(pool[k].args[0]) + ")";
+        return name(k);
+    }
+};
 
 // One pass over one root program.  C == 0: values only, variables at the
 // centre (point) or over the subdomain; C > 0: values and the tangent
@@ -288,6 +412,7 @@ class PassWriter {
         const std::string z = "v" + std::to_string(pc);
         std::string s;                                   // the statements of this instruction
         std::vector<std::string> Z(C, "kZero");
+        std::string zexpr;                               // a product's value, scheduled with the components
         auto hit_add = [&](int h, const std::string &x) { if (h >= 0) Z[h] = add_tan(Z[h], x); };
         auto hit_sub = [&](int h, const std::string &x) { if (h >= 0) Z[h] = sub_tan(Z[h], x); };
         const std::string k = lit(I.k);
@@ -304,7 +429,7 @@ class PassWriter {
             break;
         }
         case I_MUL:
-            s += z + " = " + (nv ? mul_by(U, V, true) : nu ? mul_by(V, U, true) : "imul(" + U + ", " + V + ")") + ";";
+            zexpr = nv ? mul_by(U, V, true) : nu ? mul_by(V, U, true) : "imul(" + U + ", " + V + ")";
             if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : mul_by(A[t], V, nv);
             if (bd) for (int t = 0; t < C; ++t) Z[t] = add_tan(Z[t], is_zero(B[t]) ? B[t] : mul_by(B[t], U, nu));
             hit_add(ha, V);
@@ -412,6 +537,8 @@ class PassWriter {
         }
         decl.push_back("Iv " + z + ";");
         std::vector<std::string> tn(C);
+        Scheduler sch("h" + std::to_string(pc) + "_", decl);
+        if (!zexpr.empty()) sch.add(z, zexpr);
         for (int t = 0; t < C; ++t) {
             if (is_zero(Z[t])) {
                 tn[t] = Z[t];
@@ -419,8 +546,9 @@ class PassWriter {
             }
             tn[t] = "g" + std::to_string(pc) + "_" + std::to_string(t);
             decl.push_back("Iv " + tn[t] + ";");
-            s += " " + tn[t] + " = " + Z[t] + ";";
+            sch.add(tn[t], Z[t]);
         }
+        s += sch.emit();
         body.push_back(s);
         ensure(I.d);
         slot_val[I.d] = z;
