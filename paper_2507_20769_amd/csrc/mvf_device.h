@@ -261,7 +261,7 @@ __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
     return {lo, t.lo <= 0.0 ? -__builtin_inf() : nh};
 }
 
-// exp and log: library value in round-to-nearest, widened by two ulps per side
+// exp: library value in round-to-nearest, widened by two ulps per side
 __device__ __forceinline__ Iv iexp(Iv u) {
     double xl = u.lo, xh = -u.nh;
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(xl), "+v"(xh));
@@ -270,12 +270,74 @@ __device__ __forceinline__ Iv iexp(Iv u) {
     double lo = pred(pred(el));
     return {lo > 0.0 ? lo : 0.0, pred(pred(-eh))};
 }
+
+// a*b + c with the constant c read from scalar registers, in the current
+// rounding mode (plain asm: ordered only by its operands)
+__device__ __forceinline__ double fma_vs(double a, double b, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+    return r;
+}
+__device__ __forceinline__ double fma_ks(double a, double k, double c) {    // one scalar source per instruction
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(k), "s"(c));
+    return r;
+}
+
+// Natural logarithm in round-to-nearest arithmetic (inside a round-to-nearest
+// window), written out from the series of atanh:
+//   x = m 2^e with m in [sqrt(1/2), sqrt(2)), f = m - 1 (exact), s = f/(1+m),
+//   |s| <= 0.1716, w = s^2, log m = 2 atanh s = 2s + 2s w Q(w) with
+//   Q(w) = sum_{k=1..10} w^(k-1)/(2k+1) (the omitted tail is below 2^-60 of
+//   log m), and log x = (e ln2_hi + 2s) + (2s w Q(w) + e ln2_lo), where
+//   ln2_hi has 42 significant bits so that e ln2_hi is exact for every
+//   exponent.
+// Error (u = 2^-53): s carries at most 2u relative error (1 + m and the
+// quotient are rounded), 2s is exact, 2s w Q(w) is at most 0.01 |2s| with
+// about 12u relative error, and each of the three sums rounds once.  Since
+// |2s| <= |log m| <= 0.347 and |log x| >= 0.346 whenever e != 0, the result is
+// within 7u |log x| of log x (log 1 = 0 exactly).  0 gives -inf, +inf gives
+// +inf, negative or NaN arguments NaN.
+__device__ __forceinline__ double log_rn(double x) {
+    constexpr double kLn2Hi = 0x1.62e42fefa3800p-1, kLn2Lo = 0x1.ef35793c76730p-45;
+    constexpr double kSqrtHalf = 0x1.6a09e667f3bcdp-1;
+    int e;
+    double m = __builtin_frexp(x, &e);
+    if (m < kSqrtHalf) {
+        m += m;
+        --e;
+    }
+    const double f = m - 1.0;
+    const double s = f / (1.0 + m);
+    const double s2 = s + s;
+    const double w = s * s;
+    double q = fma_ks(w, 1.0 / 21, 1.0 / 19);
+    q = fma_vs(q, w, 1.0 / 17);
+    q = fma_vs(q, w, 1.0 / 15);
+    q = fma_vs(q, w, 1.0 / 13);
+    q = fma_vs(q, w, 1.0 / 11);
+    q = fma_vs(q, w, 1.0 / 9);
+    q = fma_vs(q, w, 1.0 / 7);
+    q = fma_vs(q, w, 1.0 / 5);
+    q = fma_vs(q, w, 1.0 / 3);
+    const double de = (double)e;
+    const double t = __builtin_fma(s2 * w, q, de * kLn2Lo);
+    const double r = __builtin_fma(de, kLn2Hi, s2) + t;
+    const double special = x == 0.0 ? -__builtin_inf() : x == __builtin_inf() ? x : __builtin_nan("");
+    return x > 0.0 && x < __builtin_inf() ? r : special;     // selects, no branch
+}
+
+// log: log_rn of both ends, each widened outward by 2^-48 of its magnitude
+// (32u, more than the 7u error bound) with the widening rounded outward too
 __device__ __forceinline__ Iv ilog(Iv u) {
     double xl = u.lo, xh = -u.nh;
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(xl), "+v"(xh));
-    double ll = log(xl), lh = log(xh);
+    double ll = log_rn(xl), lh = log_rn(xh);
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(ll), "+v"(lh));
-    return {pred(pred(ll)), pred(pred(-lh))};
+    double lo, nh;
+    asm volatile("v_fma_f64 %0, -|%1|, %2, %1" : "=v"(lo) : "v"(ll), "s"(0x1p-48));          // RD(l - |l| 2^-48)
+    asm volatile("v_fma_f64 %0, -|%1|, %2, -%1" : "=v"(nh) : "v"(lh), "s"(0x1p-48));         // RD(-h - |h| 2^-48)
+    return {ll == __builtin_inf() ? kMax : lo, nh};
 }
 
 // tanh, sin, cos (and atanh, for bound tightening): the library value of both

@@ -112,3 +112,34 @@ def test_points_and_vjp_on_a_tanh_network():
         gj = gx.cpu().numpy()[:, j]
         assert np.all(gj[:, 0] - 1e-5 <= fd) and np.all(fd <= gj[:, 1] + 1e-5)
     h.close()
+
+
+def test_log_enclosures_contain_high_precision_values():
+    # the device logarithm (series of atanh, widened by 2^-48 of the value on each side)
+    # against 60-digit decimal logarithms: every enclosure contains log x and is at most
+    # 2^-45 |log x| wide; log 1 is exactly [0, 0]
+    import decimal
+    import torch
+    from paper_2507_20769_amd import mvf
+    decimal.getcontext().prec = 60
+    rng = np.random.default_rng(31)
+    sqrt_half = float.fromhex("0x1.6a09e667f3bcdp-1")          # the reduction's boundary
+    xs = np.concatenate([10.0 ** rng.uniform(-307, 308, 3000), rng.uniform(0.3, 1.7, 3000),
+                         1.0 + rng.uniform(-1e-6, 1e-6, 500),
+                         [1.0, np.nextafter(1.0, 2.0), np.nextafter(1.0, 0.0), 0.5, 2.0, sqrt_half,
+                          np.nextafter(sqrt_half, 0.0), 2 * sqrt_half, 5e-324, 1e-310,
+                          np.finfo(np.float64).max, 0.70710678, 0.35355339]])
+    tape = I.Tape(np.array([(I.VAR, 0, -1), (I.LOG, 0, -1)], dtype=I.NODE_DTYPE), np.zeros(0),
+                  np.array([1], dtype=np.int32), 1)
+    h = mvf.Tape(tape)
+    f = mvf.eval_points(h, torch.tensor(xs[:, None], device="cuda"))
+    torch.cuda.synchronize()
+    enc = f.cpu().numpy()[:, 0, :]
+    h.close()
+    D = decimal.Decimal
+    for x, (lo, hi) in zip(xs, enc):
+        t = D(float(x)).ln()
+        assert D(float(lo)) <= t <= D(float(hi)), (x, lo, hi)
+        assert D(float(hi)) - D(float(lo)) <= abs(t) * D(2) ** -45, (x, lo, hi)
+    one = enc[xs == 1.0][0]
+    assert one[0] == 0.0 and one[1] == 0.0
