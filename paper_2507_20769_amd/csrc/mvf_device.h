@@ -204,15 +204,23 @@ __device__ __forceinline__ Iv imul(Iv u, Iv v) {
     return {lo, nh};
 }
 
+// [a, b]^2: the upper end is the square of max(|a|, |b|); the lower end the
+// square of min(|a|, |b|), or 0 when a <= 0 <= b
+__device__ __forceinline__ double fmax_abs(double a, double b) {
+    double r;
+    asm volatile("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double fmin_abs(double a, double b) {
+    double r;
+    asm volatile("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 __device__ __forceinline__ Iv isqr(Iv u) {
-    double plo = fmul(u.lo, u.lo), pnh = fmul(u.nh, u.nh);
-    double qlo = fmul_n(u.lo, u.lo), qnh = fmul_n(u.nh, u.nh);
-    const bool pos = u.lo >= 0.0, negv = u.nh >= 0.0;      // lo >= 0, or hi <= 0
-    double mn = fmin_(qlo, qnh);
-    Iv z;
-    z.lo = pos ? plo : (negv ? pnh : 0.0);
-    z.nh = pos ? qnh : (negv ? qlo : mn);
-    return z;
+    const double mx = fmax_abs(u.lo, u.nh), mn = fmin_abs(u.lo, u.nh);
+    const double nh = fmul_n(mx, mx), lo = fmul(mn, mn);
+    const bool straddle = u.lo <= 0.0 && u.nh <= 0.0;       // lo <= 0 <= hi
+    return {straddle ? 0.0 : lo, nh};
 }
 
 // U / V with 0 not in V: the extreme quotients are picked by the signs
