@@ -613,55 +613,76 @@ __device__ __forceinline__ double block_min(double v, double *sv, int tid) {
 }
 
 // Reduce per-block partials [nblocks][m][2] into reduced[m][2] (lo, hi), argmin,
-// and the two B&B bounds (extra, nullable).
-__global__ __launch_bounds__(256) void finish_kernel(const double *partial, const double *plo0, const int64_t *pk,
-                                                     const double *pext, int nblocks, int m, double *reduced,
-                                                     int64_t *argmin, double *extra) {
-    __shared__ double sv[256];
-    __shared__ int64_t sk[256];
-    const int tid = threadIdx.x;
-    if (extra) {
-        for (int c = 0; c < 2; ++c) {
-            double v = __builtin_inf();
-            for (int b = tid; b < nblocks; b += 256) v = fmin(v, pext[2 * b + c]);
-            v = block_min(v, sv, tid);
-            if (tid == 0) extra[c] = v;
+// and the two B&B bounds (extra, nullable): every thread takes the minima of
+// all quantities over its share of the blocks (one block each up to 1024
+// blocks, so all loads are in flight at once), each wave reduces them with
+// cross-lane shuffles, and the last step combines the waves.
+constexpr int FIN_BLK = 1024;
+__global__ __launch_bounds__(FIN_BLK) void finish_kernel(const double *partial, const double *plo0, const int64_t *pk,
+                                                         const double *pext, int nblocks, int m, double *reduced,
+                                                         int64_t *argmin, double *extra) {
+    using namespace dev;
+    constexpr int Q = 2 * MVF_MAX_ROOTS;
+    constexpr int W = FIN_BLK / 64;
+    __shared__ double sv[W][Q + 2];
+    __shared__ double sav[W];
+    __shared__ int64_t sak[W];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double v[Q], e0 = __builtin_inf(), e1 = __builtin_inf(), av = __builtin_inf();
+    int64_t ak = INT64_MAX;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = __builtin_inf();
+    for (int b = tid; b < nblocks; b += FIN_BLK) {
+        const double *pb = partial + (size_t)b * m * 2;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (q < 2 * m) v[q] = fmin(v[q], pb[q]);
+        if (extra) {
+            e0 = fmin(e0, pext[2 * (size_t)b]);
+            e1 = fmin(e1, pext[2 * (size_t)b + 1]);
         }
-    }
-    for (int r = 0; r < m; ++r) {
-        for (int c = 0; c < 2; ++c) {
-            double v = __builtin_inf();
-            for (int b = tid; b < nblocks; b += 256) v = fmin(v, partial[((size_t)b * m + r) * 2 + c]);
-            sv[tid] = v;
-            __syncthreads();
-            for (int st = 128; st > 0; st >>= 1) {
-                if (tid < st) sv[tid] = fmin(sv[tid], sv[tid + st]);
-                __syncthreads();
-            }
-            if (tid == 0) reduced[r * 2 + c] = c == 0 ? sv[0] : -sv[0];
-            __syncthreads();
-        }
-    }
-    if (argmin) {
-        double v = __builtin_inf();
-        int64_t k = INT64_MAX;
-        for (int b = tid; b < nblocks; b += 256) {
+        if (argmin) {
             const double v2 = plo0[b];
             const int64_t k2 = pk[b];
-            if (v2 < v || (v2 == v && k2 < k)) { v = v2; k = k2; }
-        }
-        sv[tid] = v;
-        sk[tid] = k;
-        __syncthreads();
-        for (int st = 128; st > 0; st >>= 1) {
-            if (tid < st) {
-                const double v2 = sv[tid + st];
-                const int64_t k2 = sk[tid + st];
-                if (v2 < sv[tid] || (v2 == sv[tid] && k2 < sk[tid])) { sv[tid] = v2; sk[tid] = k2; }
+            if (v2 < av || (v2 == av && k2 < ak)) {
+                av = v2;
+                ak = k2;
             }
-            __syncthreads();
         }
-        if (tid == 0) *argmin = sk[0];
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (q < 2 * m) v[q] = wave_min(v[q]);
+    if (extra) {
+        e0 = wave_min(e0);
+        e1 = wave_min(e1);
+    }
+    if (argmin) wave_argmin(av, ak);
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+            if (q < 2 * m) sv[wave][q] = v[q];
+        sv[wave][Q] = e0;
+        sv[wave][Q + 1] = e1;
+        sav[wave] = av;
+        sak[wave] = ak;
+    }
+    __syncthreads();
+    if (tid < 2 * m || (extra && (tid == Q || tid == Q + 1))) {
+        double r = sv[0][tid];
+        for (int w = 1; w < W; ++w) r = fmin(r, sv[w][tid]);
+        if (tid < 2 * m) reduced[tid] = (tid & 1) ? -r : r;
+        else extra[tid - Q] = r;
+    }
+    if (argmin && tid == 0) {
+        double a = sav[0];
+        int64_t k = sak[0];
+        for (int w = 1; w < W; ++w)
+            if (sav[w] < a || (sav[w] == a && sak[w] < k)) {
+                a = sav[w];
+                k = sak[w];
+            }
+        *argmin = k;
     }
 }
 
@@ -1262,7 +1283,7 @@ hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev
 }
 
 hipError_t launch_finish(const BoxArgs &B, int grid, int m, hipStream_t stream) {
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, stream, B.partial, B.partial_lo0, B.partial_k,
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(FIN_BLK), 0, stream, B.partial, B.partial_lo0, B.partial_k,
                        B.partial_ext, grid, m, B.reduced, B.argmin, B.extra);
     return hipGetLastError();
 }

@@ -149,3 +149,34 @@ def test_forward_with_lds_spill_slots(name):
     o = O.bound(tape, box, splits, mode=O.MODE_BOTH, ks=ks, nthreads=8)
     sc = scale_of(O.bound(tape, box, splits, mode=O.MODE_NIE, ks=ks, per_sub=False, nthreads=8)["reduced"])
     assert_parity(g["per_sub"][:, :, ks], o["per_sub"], not has_transcendental(tape), sc, f"{name} fwd spill")
+
+
+@pytest.mark.parametrize("engine", ["interp", "spec"])
+def test_repeated_launches_reuse_the_workspace(engine):
+    # back-to-back launches on one workspace with changing boxes each give the oracle's
+    # result (the partials of one launch never leak into the next)
+    import torch
+    from paper_2507_20769_amd import mvf
+    t = I.random_small_tape(7, n=3, ops=40, n_con=1, con_ops=12)
+    nodes = t.nodes.copy()                             # rational: results bit for bit
+    nodes["op"][nodes["op"] == I.EXP] = I.SQR
+    nodes["op"][nodes["op"] == I.LOG] = I.SQRT
+    t = I.Tape(nodes, t.consts, t.roots, t.n_vars)
+    h = mvf.Tape(t)
+    if engine == "spec":
+        h.specialize()
+    rng = np.random.default_rng(8)
+    boxes = []
+    for _ in range(5):
+        lo = rng.uniform(-2, 1, 3)
+        boxes.append(np.stack([lo, lo + rng.uniform(0.1, 2.0, 3)], axis=1))
+    dbox = torch.tensor(boxes[0], device="cuda")
+    call = mvf.BoundCall(h, dbox, [37, 9, 5], mode="both", grad="fwd", engine=engine)    # 1,665 subdomains
+    for i, b in enumerate(boxes):
+        dbox.copy_(torch.tensor(b, device="cuda"))
+        call.launch()
+        torch.cuda.synchronize()
+        o = O.bound(t, b, [37, 9, 5], mode=O.MODE_BOTH, nthreads=8)
+        assert np.array_equal(call.reduced.cpu().numpy(), o["reduced"]), i
+        assert int(call.argmin.item()) == o["argmin"], i
+    h.close()
