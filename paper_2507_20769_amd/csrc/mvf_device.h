@@ -155,15 +155,18 @@ __device__ __forceinline__ double pred_finite(double x) { return fadd_s(x, -kTin
 // predecessor of q otherwise.  q > t exactly when the residual x*sign(y) -
 // q*|y| is negative, and an fma rounded down keeps the sign of the exact
 // residual.  A finite quotient that overflows to +inf in round-to-nearest
-// rounds down to the largest finite double.  The two chains are interleaved
-// so each compare-and-select has independent work beside it.
+// has a residual of -inf and steps down to the largest finite double (the
+// predecessor is capped there); an infinite dividend gives a NaN residual and
+// keeps its infinite quotient.  POS: the divisors are known positive (no sign
+// fold).  The two chains are interleaved so each compare-and-select has
+// independent work beside it.
+template <bool POS = false>
 __device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double y1, double &r0, double &r1) {
     double q0, q1;
     div_rn2(x0, y0, x1, y1, q0, q1);
-    if (q0 == __builtin_inf() && __builtin_isfinite(x0)) q0 = kMax;
-    if (q1 == __builtin_inf() && __builtin_isfinite(x1)) q1 = kMax;
-    const double e0 = ffma_n_abs(q0, y0, flip_by(x0, y0)), e1 = ffma_n_abs(q1, y1, flip_by(x1, y1));
-    const double d0 = pred_finite(q0), d1 = pred_finite(q1);
+    const double xs0 = POS ? x0 : flip_by(x0, y0), xs1 = POS ? x1 : flip_by(x1, y1);
+    const double e0 = ffma_n_abs(q0, y0, xs0), e1 = ffma_n_abs(q1, y1, xs1);
+    const double d0 = fmin_(pred_finite(q0), kMax), d1 = fmin_(pred_finite(q1), kMax);
     r0 = e0 < 0.0 ? d0 : q0;
     r1 = e1 < 0.0 ? d1 : q1;
 }
@@ -241,7 +244,7 @@ __device__ __forceinline__ Iv idiv(Iv u, Iv v) {
 __device__ __forceinline__ Iv idiv_pos(Iv u, Iv v) {
     const double a = u.lo, b = -u.nh, c = v.lo, d = -v.nh;
     Iv z;
-    div_rd2(a, a >= 0.0 ? d : c, -b, b >= 0.0 ? c : d, z.lo, z.nh);
+    div_rd2<true>(a, a >= 0.0 ? d : c, -b, b >= 0.0 ? c : d, z.lo, z.nh);
     return z;
 }
 
@@ -249,6 +252,12 @@ __device__ __forceinline__ Iv idiv_pos(Iv u, Iv v) {
 __device__ __forceinline__ Iv irecip(Iv v) {
     Iv z;
     div_rd2(1.0, -v.nh, -1.0, v.lo, z.lo, z.nh);
+    return z;
+}
+// the same for V > 0
+__device__ __forceinline__ Iv irecip_pos(Iv v) {
+    Iv z;
+    div_rd2<true>(1.0, -v.nh, -1.0, v.lo, z.lo, z.nh);
     return z;
 }
 
@@ -265,7 +274,7 @@ __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh
 __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
     const Iv t = itwice(z);
     double lo, nh;
-    div_rd2(1.0, -t.nh, -1.0, t.lo, lo, nh);          // branch-free: lanes differ in the sign test
+    div_rd2<true>(1.0, -t.nh, -1.0, t.lo, lo, nh);    // branch-free: lanes differ in the sign test
     return {lo, t.lo <= 0.0 ? -__builtin_inf() : nh};
 }
 
@@ -474,7 +483,7 @@ __device__ __forceinline__ void imul_pos2(Iv u, Iv r, Iv w, Iv q, Iv &a, Iv &b) 
 // U / k for k > 0
 __device__ __forceinline__ Iv idivk(Iv u, double k) {
     Iv z;
-    div_rd2(u.lo, k, u.nh, k, z.lo, z.nh);
+    div_rd2<true>(u.lo, k, u.nh, k, z.lo, z.nh);
     return z;
 }
 

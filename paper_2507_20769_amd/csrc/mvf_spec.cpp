@@ -443,7 +443,7 @@ class PassWriter {
             if (C > 0 || tape) {
                 const std::string R = "r" + std::to_string(pc);
                 decl.push_back("Iv " + R + ";");
-                s += " " + R + " = irecip(" + tv + ");";
+                s += " " + R + " = " + (nv ? "irecip_pos(" : "irecip(") + tv + ");";
             }
             if (C > 0) {
                 const std::string R = "r" + std::to_string(pc);
@@ -478,7 +478,7 @@ class PassWriter {
                 dexpr = z;
             } else if (I.op == I_LOG) {
                 s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; " + z + " = ilog(" + tu + ");";
-                dexpr = "irecip(" + tu + ")";
+                dexpr = "irecip_pos(" + tu + ")";         // u > 0 wherever the bounds are kept
             } else if (I.op == I_TANH) {
                 s += z + " = itanh(" + tu + ");";
                 dexpr = "itanh_deriv(" + z + ")";
