@@ -121,14 +121,24 @@ __device__ __forceinline__ double succ(double x) {
 // compiler's IEEE division and square root sequences, which are correctly
 // rounded in that mode, run between two mode switches.  The switches take the
 // operands and the estimates as asm operands, so the estimates are computed
-// inside the window and nothing else is.
-__device__ __forceinline__ void div_rn2(double x0, double y0, double x1, double y1, double &q0, double &q1) {
+// inside the window and nothing else is.  The operands are passed by
+// reference: the caller goes on with the switch's (unchanged) outputs, so no
+// copy of the originals is kept alive across the window.
+__device__ __forceinline__ void div_rn2(double &x0, double &y0, double &x1, double &y1, double &q0, double &q1) {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(y0), "+v"(x1), "+v"(y1));
     q0 = x0 / y0;
     q1 = x1 / y1;
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(q0), "+v"(q1));
 }
-__device__ __forceinline__ void sqrt_rn2(double a0, double a1, double &s0, double &s1) {
+// 1/y0 and -1/y1 (the numerators are constants, so only the divisors pass
+// through the switch)
+__device__ __forceinline__ void rcp_rn2(double &y0, double &y1, double &q0, double &q1) {
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(y0), "+v"(y1));
+    q0 = 1.0 / y0;
+    q1 = -1.0 / y1;
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(q0), "+v"(q1));
+}
+__device__ __forceinline__ void sqrt_rn2(double &a0, double &a1, double &s0, double &s1) {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(a0), "+v"(a1));
     s0 = __builtin_sqrt(a0);
     s1 = __builtin_sqrt(a1);
@@ -146,8 +156,26 @@ __device__ __forceinline__ double ffma_n_abs(double a, double b, double c) {   /
     asm volatile("v_fma_f64 %0, -%1, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
+// RD(+-1 - a*|b|) with the constant as an inline operand
+__device__ __forceinline__ double ffma_n_abs_p1(double a, double b) {
+    double r;
+    asm volatile("v_fma_f64 %0, -%1, |%2|, 1.0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double ffma_n_abs_m1(double a, double b) {
+    double r;
+    asm volatile("v_fma_f64 %0, -%1, |%2|, -1.0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 // next double below a finite x (fadd_s rounds down; +inf stays +inf)
 __device__ __forceinline__ double pred_finite(double x) { return fadd_s(x, -kTiny); }
+// the same, capped at the largest finite double (the constant from scalar registers)
+__device__ __forceinline__ double pred_capped(double x) {
+    const double p = pred_finite(x);
+    double r;
+    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(p), "s"(kMax));
+    return r;
+}
 
 // Correctly rounded-down quotients x0 / y0 and x1 / y1 (y != 0).  The
 // estimate q is the correctly rounded-to-nearest quotient, so no double lies
@@ -166,7 +194,24 @@ __device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double 
     div_rn2(x0, y0, x1, y1, q0, q1);
     const double xs0 = POS ? x0 : flip_by(x0, y0), xs1 = POS ? x1 : flip_by(x1, y1);
     const double e0 = ffma_n_abs(q0, y0, xs0), e1 = ffma_n_abs(q1, y1, xs1);
-    const double d0 = fmin_(pred_finite(q0), kMax), d1 = fmin_(pred_finite(q1), kMax);
+    const double d0 = pred_capped(q0), d1 = pred_capped(q1);
+    r0 = e0 < 0.0 ? d0 : q0;
+    r1 = e1 < 0.0 ? d1 : q1;
+}
+// RD(1/y0) and RD(-1/y1): div_rd2 with the constant numerators
+template <bool POS = false>
+__device__ __forceinline__ void rcp_rd2(double y0, double y1, double &r0, double &r1) {
+    double q0, q1;
+    rcp_rn2(y0, y1, q0, q1);
+    double e0, e1;
+    if constexpr (POS) {
+        e0 = ffma_n_abs_p1(q0, y0);
+        e1 = ffma_n_abs_m1(q1, y1);
+    } else {
+        e0 = ffma_n_abs(q0, y0, flip_by(1.0, y0));
+        e1 = ffma_n_abs(q1, y1, flip_by(-1.0, y1));
+    }
+    const double d0 = pred_capped(q0), d1 = pred_capped(q1);
     r0 = e0 < 0.0 ? d0 : q0;
     r1 = e1 < 0.0 ? d1 : q1;
 }
@@ -251,13 +296,13 @@ __device__ __forceinline__ Iv idiv_pos(Iv u, Iv v) {
 // 1 / V with 0 not in V: [RD(1/d), RU(1/c)]
 __device__ __forceinline__ Iv irecip(Iv v) {
     Iv z;
-    div_rd2(1.0, -v.nh, -1.0, v.lo, z.lo, z.nh);
+    rcp_rd2(-v.nh, v.lo, z.lo, z.nh);
     return z;
 }
 // the same for V > 0
 __device__ __forceinline__ Iv irecip_pos(Iv v) {
     Iv z;
-    div_rd2<true>(1.0, -v.nh, -1.0, v.lo, z.lo, z.nh);
+    rcp_rd2<true>(-v.nh, v.lo, z.lo, z.nh);
     return z;
 }
 
@@ -274,7 +319,7 @@ __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh
 __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
     const Iv t = itwice(z);
     double lo, nh;
-    div_rd2<true>(1.0, -t.nh, -1.0, t.lo, lo, nh);    // branch-free: lanes differ in the sign test
+    rcp_rd2<true>(-t.nh, t.lo, lo, nh);               // branch-free: lanes differ in the sign test
     return {lo, t.lo <= 0.0 ? -__builtin_inf() : nh};
 }
 
