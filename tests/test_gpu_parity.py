@@ -180,3 +180,34 @@ def test_repeated_launches_reuse_the_workspace(engine):
         assert np.array_equal(call.reduced.cpu().numpy(), o["reduced"]), i
         assert int(call.argmin.item()) == o["argmin"], i
     h.close()
+
+
+@pytest.mark.parametrize("engine", ["interp", "spec"])
+def test_largest_partition_table(engine):
+    # the breakpoint table at its capacity (2,048 + 2,048 = MVF_MAX_TABLE entries, 4,194,304
+    # subdomains): 400 sampled subdomains recomputed by the oracle one by one, the hull equal to
+    # the per-subdomain extremes, and one more split refused with MVF_ELIMIT
+    import torch
+    from paper_2507_20769_amd import mvf
+    t = I.random_small_tape(12, n=2, ops=30, n_con=1, con_ops=10)
+    nodes = t.nodes.copy()
+    nodes["op"][nodes["op"] == I.EXP] = I.SQR
+    nodes["op"][nodes["op"] == I.LOG] = I.SQRT
+    t = I.Tape(nodes, t.consts, t.roots, t.n_vars)
+    h = mvf.Tape(t)
+    if engine == "spec":
+        h.specialize()
+    box = np.array([[-1.5, 2.0], [-0.5, 1.0]])
+    splits = [2048, 2048]
+    print(f"[case] table capacity engine={engine}", flush=True)
+    g = gpu_bound(t, box, splits, mode="both", handle=h, engine=engine)
+    S = 2048 * 2048
+    ks = np.unique(np.concatenate([np.random.default_rng(13).choice(S, 400, replace=False), [0, 2047, 2048, S - 1]]))
+    o = O.bound(t, box, splits, mode=O.MODE_BOTH, ks=ks, nthreads=8)
+    assert_parity(g["per_sub"][:, :, ks], o["per_sub"], True, None, "sampled")
+    assert np.array_equal(g["reduced"][:, 0], g["per_sub"][:, 0, :].min(axis=1))
+    assert np.array_equal(g["reduced"][:, 1], g["per_sub"][:, 1, :].max(axis=1))
+    with pytest.raises(mvf.MVFError) as e:
+        mvf.bound(h, torch.tensor(box, device="cuda"), [2049, 2048], engine=engine)
+    assert e.value.code == -3
+    h.close()
