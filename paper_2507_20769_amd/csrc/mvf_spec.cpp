@@ -269,6 +269,17 @@ class PassWriter {
                 contribute(I.bk, I.b, st.pb, ib, I.op == I_SUB, zb);
                 break;
             case I_MUL:
+                if (I.ak != K_CONST && I.bk != K_CONST && st.nv == st.nu) {
+                    // both products at once (the same operations, interleaved)
+                    const std::string P = "pa" + pc, Q = "pb" + pc;
+                    decl.push_back("Iv " + P + ";");
+                    decl.push_back("Iv " + Q + ";");
+                    s += std::string(st.nv ? "imul_pos2(" : "imul2(") + zb + ", " + st.V + ", " + zb + ", " + st.U +
+                         ", " + P + ", " + Q + "); ";
+                    contribute(I.ak, I.a, st.pa, ia, false, P);
+                    contribute(I.bk, I.b, st.pb, ib, false, Q);
+                    break;
+                }
                 if (I.ak != K_CONST) contribute(I.ak, I.a, st.pa, ia, false, mul_by(zb, st.V, st.nv, false));
                 if (I.bk != K_CONST) contribute(I.bk, I.b, st.pb, ib, false, mul_by(zb, st.U, st.nu, false));
                 break;
