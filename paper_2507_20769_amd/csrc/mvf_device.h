@@ -11,7 +11,8 @@
 // and negation is a free source modifier.  Every rounding-sensitive
 // instruction is written as volatile inline asm, so the compiler neither
 // folds it under round-to-nearest assumptions nor moves it across a mode
-// change.  Division and square root start from the compiler's correctly
+// change.  Minimum and maximum are exact in every mode: their asm is plain,
+// so the compiler may schedule them freely.  Division and square root start from the compiler's correctly
 // rounded estimate, computed in a short round-to-nearest window, and are
 // corrected with exact-sign residual tests (fma rounded down keeps the sign of
 // the exact residual), which yields the correctly rounded-down result.
@@ -94,12 +95,12 @@ __device__ __forceinline__ double ffma_nn(double a, double b, double c) {  // RD
 }
 __device__ __forceinline__ double fmin_(double a, double b) {
     double r;
-    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 __device__ __forceinline__ double fmax_(double a, double b) {
     double r;
-    asm volatile("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 
@@ -173,7 +174,7 @@ __device__ __forceinline__ double pred_finite(double x) { return fadd_s(x, -kTin
 __device__ __forceinline__ double pred_capped(double x) {
     const double p = pred_finite(x);
     double r;
-    asm volatile("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(p), "s"(kMax));
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(p), "s"(kMax));
     return r;
 }
 
@@ -256,12 +257,12 @@ __device__ __forceinline__ Iv imul(Iv u, Iv v) {
 // square of min(|a|, |b|), or 0 when a <= 0 <= b
 __device__ __forceinline__ double fmax_abs(double a, double b) {
     double r;
-    asm volatile("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 __device__ __forceinline__ double fmin_abs(double a, double b) {
     double r;
-    asm volatile("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
+    asm("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
 __device__ __forceinline__ Iv isqr(Iv u) {
