@@ -207,3 +207,26 @@ def test_reverse_specialised_exp_log_and_mid():
     assert_parity(g["per_sub"], gi["per_sub"], exact, sc, "mid adjoint vs interpreter")
     assert not g["flags"].any()
     h.close()
+
+
+def test_division_by_constants_at_the_extremes():
+    # x / k with constant k: endpoints rounded outward bit for bit as the oracle's, through
+    # overflow, the subnormal range and exact quotients (a quotient estimate corrected with a
+    # residual that falls below the normal range would be several ulps off there)
+    import torch
+    from paper_2507_20769_amd import mvf
+    big = np.finfo(np.float64).max
+    boxes = [[-big, big], [-big, -1e300], [1e-310, 3e-308], [-5.0, 7.0], [-3e-320, 1e-320], [0.0, 0.0],
+             [-1e308, 1e308], [1.0, 3.0], [-6.0, -2.0]]
+    for k in (0.5, 3.0, 0.1, 7.0, 1e-300, 1e300, 0.3, 2.0):
+        tape = I.Tape(np.array([(I.VAR, 0, -1), (I.CONST, 0, -1), (I.DIV, 0, 1)], dtype=I.NODE_DTYPE),
+                      np.array([k]), np.array([2], dtype=np.int32), 1)
+        h = mvf.Tape(tape)
+        h.specialize()
+        for b in boxes:
+            box = np.array([b])
+            o = O.bound(tape, box, [1], mode=O.MODE_NIE, nthreads=1)
+            for engine in ("spec", "interp"):
+                g = gpu_bound(tape, box, [1], mode="nie", handle=h, engine=engine)
+                assert np.array_equal(g["per_sub"], o["per_sub"]), (k, b, engine, g["per_sub"], o["per_sub"])
+        h.close()
