@@ -47,6 +47,7 @@ FP64_PUBLISHED_PEAK = 78.6e12
 # the factors from a 256 MiB copy in the same runs), valid only for the kernel build and tape they were
 # taken on: (engine, grad, tape hash) -> bytes
 TRAFFIC = {}
+METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 
 def parse():
