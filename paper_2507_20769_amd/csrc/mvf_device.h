@@ -489,6 +489,23 @@ __device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
     return {fmin_(fmul(u.lo, r.lo), fmul_n(u.lo, r.nh)), fmin_(fmul(u.nh, r.lo), fmul_n(u.nh, r.nh))};
 }
 
+// U * [k, k] (a degenerate factor, c.lo = -c.nh = k): the four endpoint
+// products of imul are two distinct ones, so this equals imul(u, c)
+__device__ __forceinline__ Iv imul_deg(Iv u, Iv c) {
+    const double k = c.lo;
+    const double p0 = fmul(u.lo, k), q0 = fmul_n(u.lo, k);
+    const double p1 = fmul_n(u.nh, k), q1 = fmul(u.nh, k);
+    return {fmin_(p0, p1), fmin_(q0, q1)};
+}
+// G * D for D = [dl, dh] with dl <= 0 <= dh (X - c with c in X): the lowest
+// of the four endpoint products is gh dl or gl dh, the highest gl dl or gh dh,
+// so this equals imul(g, d)
+__device__ __forceinline__ Iv imul_dx(Iv g, Iv d) {
+    const double a = fmul_n(g.nh, d.lo), b = fmul_n(g.lo, d.nh);
+    const double c = fmul_n(g.lo, d.lo), e = fmul_n(g.nh, d.nh);
+    return {fmin_(a, b), fmin_(c, e)};
+}
+
 // Two independent products with their instructions interleaved: each
 // operation of one product is followed by the same operation of the other,
 // so no instruction waits on the one just before it.  The results are those

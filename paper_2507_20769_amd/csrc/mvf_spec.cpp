@@ -440,7 +440,10 @@ class PassWriter {
             break;
         }
         case I_MUL:
-            zexpr = nv ? mul_by(U, V, true) : nu ? mul_by(V, U, true) : "imul(" + U + ", " + V + ")";
+            if (point && (I.ak == K_VAR || I.bk == K_VAR))     // a variable at the centre is degenerate
+                zexpr = I.bk == K_VAR ? "imul_deg(" + U + ", " + V + ")" : "imul_deg(" + V + ", " + U + ")";
+            else
+                zexpr = nv ? mul_by(U, V, true) : nu ? mul_by(V, U, true) : "imul(" + U + ", " + V + ")";
             if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : mul_by(A[t], V, nv);
             if (bd) for (int t = 0; t < C; ++t) Z[t] = add_tan(Z[t], is_zero(B[t]) ? B[t] : mul_by(B[t], U, nu));
             hit_add(ha, V);
@@ -731,7 +734,7 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
             s += "            Iv G[N_VARS];\n            const Iv nie = adjoint_" + R + "(L, go, bad, G);\n";
             s += "            Iv acc = FC;\n";
             for (int i = 0; i < n; ++i)
-                s += "            acc = iadd(acc, imul(G[" + std::to_string(i) + "], spec_dx(L, " + std::to_string(i) +
+                s += "            acc = iadd(acc, imul_dx(G[" + std::to_string(i) + "], spec_dx(L, " + std::to_string(i) +
                      ")));\n";
             s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";
             s += "        }\n        if (B.lo != B.lo || B.nh != B.nh) bad = 1;\n";
@@ -759,7 +762,7 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
             if (c0 == 0) s += "                nie = v;\n";
             for (int t = 0; t < c; ++t)      // a zero component adds nothing
                 if (!zero[r][c0 + t])
-                    s += "                acc = iadd(acc, imul(G[" + std::to_string(t) + "], spec_dx(L, " +
+                    s += "                acc = iadd(acc, imul_dx(G[" + std::to_string(t) + "], spec_dx(L, " +
                          std::to_string(c0 + t) + ")));\n";
             s += "            }\n";
         }
