@@ -106,6 +106,7 @@ __device__ __forceinline__ double fmax_(double a, double b) {
 
 constexpr double kTiny = 4.9406564584124654e-324;     // 2^-1074
 constexpr double kMax = 1.7976931348623157e308;
+constexpr double kMaxPred = 0x1.ffffffffffffep+1023;    // the double below kMax
 
 // next double below x (x != NaN); +inf steps to the largest finite double
 __device__ __forceinline__ double pred(double x) {
@@ -330,8 +331,9 @@ __device__ __forceinline__ Iv iexp(Iv u) {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(xl), "+v"(xh));
     double el = exp(xl), eh = exp(xh);
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(el), "+v"(eh));
-    double lo = pred(pred(el));
-    return {lo > 0.0 ? lo : 0.0, pred(pred(-eh))};
+    // two predecessor steps (-eh is never +inf, so its steps need no stand-in)
+    const double lo = pred(pred(el));
+    return {lo > 0.0 ? lo : 0.0, pred_finite(pred_finite(-eh))};
 }
 
 // a*b + c with the constant c read from scalar registers, in the current
@@ -426,12 +428,16 @@ __device__ __forceinline__ void lib2(double &x0, double &x1) {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(x0), "+v"(x1));
 }
 __device__ __forceinline__ double pred4(double x) { return pred(pred(pred(pred(x)))); }
+// four predecessor steps of a value that is finite or NaN (library values of tanh, sin, cos)
+__device__ __forceinline__ double pred4_finite(double x) {
+    return pred_finite(pred_finite(pred_finite(pred_finite(x))));
+}
 
 // tanh is increasing with values in (-1, 1)
 __device__ __forceinline__ Iv itanh(Iv u) {
     double a = u.lo, b = -u.nh;
     lib2<LIB_TANH>(a, b);
-    return {fmax_(pred4(a), -1.0), fmax_(pred4(-b), -1.0)};
+    return {fmax_(pred4_finite(a), -1.0), fmax_(pred4_finite(-b), -1.0)};
 }
 // pi lies between these neighbouring doubles
 constexpr double kPiLo = 3.141592653589793, kPiHi = 3.1415926535897936;
@@ -453,7 +459,7 @@ template <int F>
 __device__ __forceinline__ Iv itrig(Iv u) {
     double a = u.lo, b = -u.nh;
     lib2<F>(a, b);
-    double lo = fmin_(pred4(a), pred4(b)), nh = fmin_(pred4(-a), pred4(-b));
+    double lo = fmin_(pred4_finite(a), pred4_finite(b)), nh = fmin_(pred4_finite(-a), pred4_finite(-b));
     const Iv cmax = F == LIB_SIN ? Iv{kPiLo / 2, -kPiHi / 2} : Iv{0.0, -0.0};
     const Iv cmin = F == LIB_SIN ? Iv{-kPiHi / 2, kPiLo / 2} : Iv{kPiLo, -kPiHi};
     const bool hi1 = may_contain(u, cmax), lo1 = may_contain(u, cmin);
@@ -489,6 +495,8 @@ __device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
     return {fmin_(fmul(u.lo, r.lo), fmul_n(u.lo, r.nh)), fmin_(fmul(u.nh, r.lo), fmul_n(u.nh, r.nh))};
 }
 
+// [c, c]^2: both ends are the one product c*c rounded each way (equals isqr)
+__device__ __forceinline__ Iv isqr_deg(Iv u) { return {fmul(u.lo, u.lo), fmul_n(u.lo, u.lo)}; }
 // U * [k, k] (a degenerate factor, c.lo = -c.nh = k): the four endpoint
 // products of imul are two distinct ones, so this equals imul(u, c)
 __device__ __forceinline__ Iv imul_deg(Iv u, Iv c) {

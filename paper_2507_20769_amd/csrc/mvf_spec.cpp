@@ -482,7 +482,7 @@ class PassWriter {
             s += tu + " = " + U + "; ";
             std::string dexpr;
             if (I.op == I_SQR) {
-                s += z + " = isqr(" + tu + ");";
+                s += z + " = " + (point && I.ak == K_VAR ? "isqr_deg(" : "isqr(") + tu + ");";
                 dexpr = "itwice(" + tu + ")";
             } else if (I.op == I_SQRT) {
                 s += "bad |= " + tu + ".lo < 0.0 ? 1u : 0u; " + z + " = isqrt(" + tu + ");";
