@@ -53,11 +53,6 @@ __device__ __forceinline__ double fadd(double a, double b) {
     asm volatile("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
     return r;
 }
-__device__ __forceinline__ double fadd_nn(double a, double b) {       // RD(-a - b)
-    double r;
-    asm volatile("v_add_f64 %0, -%1, -%2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
 __device__ __forceinline__ double fadd_s(double a, double s) {        // s in an SGPR pair
     double r;
     asm volatile("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(s));
@@ -106,17 +101,11 @@ __device__ __forceinline__ double fmax_(double a, double b) {
 
 constexpr double kTiny = 4.9406564584124654e-324;     // 2^-1074
 constexpr double kMax = 1.7976931348623157e308;
-constexpr double kMaxPred = 0x1.ffffffffffffep+1023;    // the double below kMax
 
 // next double below x (x != NaN); +inf steps to the largest finite double
 __device__ __forceinline__ double pred(double x) {
     double r = fadd_s(x, -kTiny);
     return x == __builtin_inf() ? kMax : r;
-}
-// next double above x; -inf steps to the most negative finite double
-__device__ __forceinline__ double succ(double x) {
-    double r = -fadd_ns(x, -kTiny);       // -RD(-x - tiny)
-    return x == -__builtin_inf() ? -kMax : r;
 }
 
 // Round-to-nearest estimates of two quotients (or square roots): the
