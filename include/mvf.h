@@ -186,9 +186,16 @@ int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stre
  * combine of Sec. 2.2 and the Step 3 reduction as in the interpreter),
  * single-box and batched, compiles it at
  * run time with hiprtc for the current device and keeps the loaded module in
- * the tape.  Each operation is the one the interpreter performs, in the same
- * order, so the bounds are bitwise identical; no instruction is decoded or
- * dispatched at run time.  Tangent components that are structurally zero (a
+ * the tape.  Each operation gives the interpreter's result for it, in the
+ * same order, so the bounds are bitwise identical (up to the sign of zero
+ * endpoints); no instruction is decoded or dispatched at run time.  Where the
+ * generator knows more than the interpreter it takes a cheaper form of the
+ * same result: one-sided products and quotients where a factor or divisor is
+ * known nonnegative (squares, roots, exp, derivative factors of sqrt, exp,
+ * log and tanh, sums and products of such values, positive constants) on
+ * every subdomain whose bounds are kept, two products per end where a factor
+ * is degenerate (a variable at the centre) or straddles zero (X - c in the
+ * mean value form).  Tangent components that are structurally zero (a
  * node that does not depend on the component's variable) are neither stored
  * nor computed: with finite enclosures this changes at most the sign of zero
  * endpoints; where a dense product of such a zero with an enclosure unbounded

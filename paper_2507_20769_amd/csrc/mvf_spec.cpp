@@ -8,10 +8,12 @@
 // centre, tangent passes over the subdomain a chunk of gradient components at
 // a time, MVF = [f(c)] + sum_i G_i (X_i - c_i) intersected with the NIE.  The
 // generator walks the same instructions (with their constant-operand forms and
-// slot-0 forwarding) and emits, per instruction, the calls the interpreter
-// makes for that opcode and operand kinds; slots become variables.  The
-// decode, the dispatch and the slot-file moves disappear, and so does the
-// arithmetic on structurally zero tangent components.
+// slot-0 forwarding) and emits, per instruction, calls that give the results
+// of the interpreter's calls for that opcode and operand kinds; slots become
+// variables.  The decode, the dispatch and the slot-file moves disappear, and
+// so does the arithmetic on structurally zero tangent components; facts known
+// when generating (signs, degenerate and straddling factors) select cheaper
+// forms of the same products and quotients.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
