@@ -40,11 +40,18 @@ struct Iv {
 #define MVF_STR(x) MVF_STR2(x)
 
 // ---- FP64 rounding mode -------------------------------------------------
+// A MODE write takes effect for the next VALU instruction of the wave, and an
+// instruction issued before it keeps the mode it was issued under (the
+// compiler's own single-precision division relies on both when it toggles the
+// denormal bits of the same register), so a switch needs no wait states
+// around it.  Two MODE writes need two wait states between them; every switch
+// pair here encloses or is followed by at least two VALU instructions (the
+// build checks the compiled kernels for this).
 __device__ __forceinline__ void mode_round_down() {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" ::: "memory");
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" ::: "memory");
 }
 __device__ __forceinline__ void mode_round_nearest() {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" ::: "memory");
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" ::: "memory");
 }
 
 // ---- single FP64 instructions under the current (round-down) mode ----------
@@ -56,11 +63,6 @@ __device__ __forceinline__ double fadd(double a, double b) {
 __device__ __forceinline__ double fadd_s(double a, double s) {        // s in an SGPR pair
     double r;
     asm volatile("v_add_f64 %0, %1, %2" : "=v"(r) : "v"(a), "s"(s));
-    return r;
-}
-__device__ __forceinline__ double fadd_ns(double a, double s) {       // RD(-a + s)
-    double r;
-    asm volatile("v_add_f64 %0, -%1, %2" : "=v"(r) : "v"(a), "s"(s));
     return r;
 }
 __device__ __forceinline__ double fsub(double a, double b) {          // RD(a - b)
@@ -76,16 +78,6 @@ __device__ __forceinline__ double fmul(double a, double b) {
 __device__ __forceinline__ double fmul_n(double a, double b) {        // RD(a * -b)
     double r;
     asm volatile("v_mul_f64 %0, %1, -%2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double ffma_n(double a, double b, double c) {   // RD(-a*b + c)
-    double r;
-    asm volatile("v_fma_f64 %0, -%1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-__device__ __forceinline__ double ffma_nn(double a, double b, double c) {  // RD(a*b - c)
-    double r;
-    asm volatile("v_fma_f64 %0, %1, %2, -%3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
     return r;
 }
 __device__ __forceinline__ double fmin_(double a, double b) {
@@ -108,65 +100,14 @@ __device__ __forceinline__ double pred(double x) {
     return x == __builtin_inf() ? kMax : r;
 }
 
-// Round-to-nearest estimates of two quotients (or square roots): the
-// compiler's IEEE division and square root sequences, which are correctly
-// rounded in that mode, run between two mode switches.  The switches take the
-// operands and the estimates as asm operands, so the estimates are computed
-// inside the window and nothing else is.  The operands are passed by
-// reference: the caller goes on with the switch's (unchanged) outputs, so no
-// copy of the originals is kept alive across the window.
-__device__ __forceinline__ void div_rn2(double &x0, double &y0, double &x1, double &y1, double &q0, double &q1) {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(y0), "+v"(x1), "+v"(y1));
-    q0 = x0 / y0;
-    q1 = x1 / y1;
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(q0), "+v"(q1));
-}
-// 1/y0 and -1/y1 (the numerators are constants, so only the divisors pass
-// through the switch)
-__device__ __forceinline__ void rcp_rn2(double &y0, double &y1, double &q0, double &q1) {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(y0), "+v"(y1));
-    q0 = 1.0 / y0;
-    q1 = -1.0 / y1;
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(q0), "+v"(q1));
-}
-__device__ __forceinline__ void sqrt_rn2(double &a0, double &a1, double &s0, double &s1) {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(a0), "+v"(a1));
-    s0 = __builtin_sqrt(a0);
-    s1 = __builtin_sqrt(a1);
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(s0), "+v"(s1));
-}
-
 // x with its sign flipped where y is negative (x * sign(y), exact): two
 // 32-bit logic operations on the high words instead of two selects
 __device__ __forceinline__ double flip_by(double x, double y) {
     const uint64_t xb = __builtin_bit_cast(uint64_t, x), yb = __builtin_bit_cast(uint64_t, y);
     return __builtin_bit_cast(double, xb ^ (yb & 0x8000000000000000ull));
 }
-__device__ __forceinline__ double ffma_n_abs(double a, double b, double c) {   // RD(-a*|b| + c)
-    double r;
-    asm volatile("v_fma_f64 %0, -%1, |%2|, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-// RD(+-1 - a*|b|) with the constant as an inline operand
-__device__ __forceinline__ double ffma_n_abs_p1(double a, double b) {
-    double r;
-    asm volatile("v_fma_f64 %0, -%1, |%2|, 1.0" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double ffma_n_abs_m1(double a, double b) {
-    double r;
-    asm volatile("v_fma_f64 %0, -%1, |%2|, -1.0" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
 // next double below a finite x (fadd_s rounds down; +inf stays +inf)
 __device__ __forceinline__ double pred_finite(double x) { return fadd_s(x, -kTiny); }
-// the same, capped at the largest finite double (the constant from scalar registers)
-__device__ __forceinline__ double pred_capped(double x) {
-    const double p = pred_finite(x);
-    double r;
-    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(p), "s"(kMax));
-    return r;
-}
 
 // Correctly rounded-down quotients x0 / y0 and x1 / y1 (y != 0).  The
 // estimate q is the correctly rounded-to-nearest quotient, so no double lies
@@ -177,15 +118,46 @@ __device__ __forceinline__ double pred_capped(double x) {
 // has a residual of -inf and steps down to the largest finite double (the
 // predecessor is capped there); an infinite dividend gives a NaN residual and
 // keeps its infinite quotient.  POS: the divisors are known positive (no sign
-// fold).  The two chains are interleaved so each compare-and-select has
-// independent work beside it.
+// fold).
+//
+// The estimates come from the compiler's IEEE division sequence, correctly
+// rounded in round-to-nearest, run between two mode switches.  The switch to
+// nearest takes the operands as asm operands and the switch back takes the
+// estimates, so the estimates are computed inside the window and nothing else
+// is.  The switch back, the two residuals and the two capped predecessors are
+// one asm statement: the compiler pads an instruction that reads a result of
+// the inline asm just before it, and here the first instructions after the
+// switch read its operands.
+#define MVF_CLOSE_AND_TEST2(N0, N1)                                                    \
+    "s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\t"                               \
+    "v_fma_f64 %0, -%4, |%6|, " N0 "\n\t"        /* e0 = RD(n0 - q0 |y0|) */        \
+    "v_fma_f64 %1, -%5, |%7|, " N1 "\n\t"        /* e1 = RD(n1 - q1 |y1|) */        \
+    "v_add_f64 %2, %4, %8\n\t"                   /* d0 = RD(q0 - 2^-1074) */        \
+    "v_add_f64 %3, %5, %8\n\t"                                                       \
+    "v_min_f64 %2, %2, %9\n\t"                   /* capped at the largest double */ \
+    "v_min_f64 %3, %3, %9"
+__device__ __forceinline__ void close_and_test2(double q0, double q1, double y0, double y1, double n0, double n1,
+                                                double &e0, double &e1, double &d0, double &d1) {
+    asm volatile(MVF_CLOSE_AND_TEST2("%10", "%11")
+                 : "=&v"(e0), "=&v"(e1), "=&v"(d0), "=v"(d1)
+                 : "v"(q0), "v"(q1), "v"(y0), "v"(y1), "s"(-kTiny), "s"(kMax), "v"(n0), "v"(n1));
+}
+// the same with the numerators 1 and -1 (inline constants)
+__device__ __forceinline__ void close_and_test2_pm1(double q0, double q1, double y0, double y1,
+                                                    double &e0, double &e1, double &d0, double &d1) {
+    asm volatile(MVF_CLOSE_AND_TEST2("1.0", "-1.0")
+                 : "=&v"(e0), "=&v"(e1), "=&v"(d0), "=v"(d1)
+                 : "v"(q0), "v"(q1), "v"(y0), "v"(y1), "s"(-kTiny), "s"(kMax));
+}
 template <bool POS = false>
 __device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double y1, double &r0, double &r1) {
     double q0, q1;
-    div_rn2(x0, y0, x1, y1, q0, q1);
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(x0), "+v"(y0), "+v"(x1), "+v"(y1));
+    q0 = x0 / y0;
+    q1 = x1 / y1;
     const double xs0 = POS ? x0 : flip_by(x0, y0), xs1 = POS ? x1 : flip_by(x1, y1);
-    const double e0 = ffma_n_abs(q0, y0, xs0), e1 = ffma_n_abs(q1, y1, xs1);
-    const double d0 = pred_capped(q0), d1 = pred_capped(q1);
+    double e0, e1, d0, d1;
+    close_and_test2(q0, q1, y0, y1, xs0, xs1, e0, e1, d0, d1);
     r0 = e0 < 0.0 ? d0 : q0;
     r1 = e1 < 0.0 ? d1 : q1;
 }
@@ -193,32 +165,35 @@ __device__ __forceinline__ void div_rd2(double x0, double y0, double x1, double 
 template <bool POS = false>
 __device__ __forceinline__ void rcp_rd2(double y0, double y1, double &r0, double &r1) {
     double q0, q1;
-    rcp_rn2(y0, y1, q0, q1);
-    double e0, e1;
-    if constexpr (POS) {
-        e0 = ffma_n_abs_p1(q0, y0);
-        e1 = ffma_n_abs_m1(q1, y1);
-    } else {
-        e0 = ffma_n_abs(q0, y0, flip_by(1.0, y0));
-        e1 = ffma_n_abs(q1, y1, flip_by(-1.0, y1));
-    }
-    const double d0 = pred_capped(q0), d1 = pred_capped(q1);
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(y0), "+v"(y1));
+    q0 = 1.0 / y0;
+    q1 = -1.0 / y1;
+    double e0, e1, d0, d1;
+    if constexpr (POS)
+        close_and_test2_pm1(q0, q1, y0, y1, e0, e1, d0, d1);
+    else
+        close_and_test2(q0, q1, y0, y1, flip_by(1.0, y0), flip_by(-1.0, y1), e0, e1, d0, d1);
     r0 = e0 < 0.0 ? d0 : q0;
     r1 = e1 < 0.0 ? d1 : q1;
 }
 
 // [RD(sqrt(a)), -RU(sqrt(b))] for a, b >= 0 from the correctly rounded-to-
 // nearest roots s: the lower end is s, or its predecessor when s*s > a; the
-// upper end s, or its successor when s*s < b (residual signs as in div_rd2).
+// upper end s, or its successor when s*s < b (residual signs as in div_rd2;
+// the switch back and the tests again one asm statement).
 __device__ __forceinline__ void sqrt_rd_ru2(double a, double b, double &lo, double &nh) {
-    double s0, s1;
-    sqrt_rn2(a, b, s0, s1);
-    const double e0 = ffma_n(s0, s0, a);                               // RD(a - s*s)
-    const double g = ffma_nn(s1, s1, b);                               // RD(s*s - b)
-    const double d0 = pred_finite(s0);
-    const double u1 = -pred_finite(-s1);
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(a), "+v"(b));
+    const double s0 = __builtin_sqrt(a), s1 = __builtin_sqrt(b);
+    double e0, g, d0, m1;
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\t"
+                 "v_fma_f64 %0, -%4, %4, %6\n\t"        // e0 = RD(a - s0*s0)
+                 "v_fma_f64 %1, %5, %5, -%7\n\t"        // g = RD(s1*s1 - b)
+                 "v_add_f64 %2, %4, %8\n\t"             // d0 = pred(s0)
+                 "v_add_f64 %3, -%5, %8"                // m1 = pred(-s1)
+                 : "=&v"(e0), "=&v"(g), "=&v"(d0), "=v"(m1)
+                 : "v"(s0), "v"(s1), "v"(a), "v"(b), "s"(-kTiny));
     lo = e0 < 0.0 ? d0 : s0;
-    nh = -(g < 0.0 ? u1 : s1);
+    nh = g < 0.0 ? m1 : -s1;
 }
 
 // ---- interval operations on (lo, nh) -------------------------------------
@@ -226,20 +201,28 @@ __device__ __forceinline__ Iv iadd(Iv u, Iv v) { return {fadd(u.lo, v.lo), fadd(
 __device__ __forceinline__ Iv isub(Iv u, Iv v) { return {fadd(u.lo, v.nh), fadd(u.nh, v.lo)}; }
 
 // hull of the four endpoint products; hi = -nh, so lo*hi = RD(lo * -nh) etc.
-// (volatile asm keeps source order: each minimum follows its two products, so
-// few temporaries are live at once)
+// One asm statement for the whole hull: the compiler pads an instruction that
+// reads a result of the inline asm just before it (it cannot see what the asm
+// does), so the minima sit inside the statement with their products.  Each
+// minimum follows its two products, so two temporaries suffice.
 __device__ __forceinline__ Iv imul(Iv u, Iv v) {
-    // the two endpoint chains interleaved: each operation's inputs were
-    // produced at least two instructions earlier
-    const double p0 = fmul(u.lo, v.lo), q0 = fmul_n(u.lo, v.lo);
-    const double p1 = fmul_n(u.lo, v.nh), q1 = fmul(u.lo, v.nh);
-    double lo = fmin_(p0, p1), nh = fmin_(q0, q1);
-    const double p2 = fmul_n(u.nh, v.lo), q2 = fmul(u.nh, v.lo);
-    lo = fmin_(lo, p2);
-    nh = fmin_(nh, q2);
-    const double p3 = fmul(u.nh, v.nh), q3 = fmul_n(u.nh, v.nh);
-    lo = fmin_(lo, p3);
-    nh = fmin_(nh, q3);
+    double lo, nh, t, w;
+    asm volatile("v_mul_f64 %0, %4, %6\n\t"          // lo = a c
+                 "v_mul_f64 %1, %4, -%6\n\t"         // nh = -(a c)
+                 "v_mul_f64 %2, %4, -%7\n\t"         // a d
+                 "v_mul_f64 %3, %4, %7\n\t"          // -(a d)
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3\n\t"
+                 "v_mul_f64 %2, %5, -%6\n\t"         // b c
+                 "v_mul_f64 %3, %5, %6\n\t"          // -(b c)
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3\n\t"
+                 "v_mul_f64 %2, %5, %7\n\t"          // b d
+                 "v_mul_f64 %3, %5, -%7\n\t"         // -(b d)
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3"
+                 : "=&v"(lo), "=&v"(nh), "=&v"(t), "=&v"(w)
+                 : "v"(u.lo), "v"(u.nh), "v"(v.lo), "v"(v.nh));
     return {lo, nh};
 }
 
@@ -317,25 +300,12 @@ __device__ __forceinline__ Iv isqrt_deriv(Iv z) {
 // exp: library value in round-to-nearest, widened by two ulps per side
 __device__ __forceinline__ Iv iexp(Iv u) {
     double xl = u.lo, xh = -u.nh;
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(xl), "+v"(xh));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(xl), "+v"(xh));
     double el = exp(xl), eh = exp(xh);
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(el), "+v"(eh));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" : "+v"(el), "+v"(eh));
     // two predecessor steps (-eh is never +inf, so its steps need no stand-in)
     const double lo = pred(pred(el));
     return {lo > 0.0 ? lo : 0.0, pred_finite(pred_finite(-eh))};
-}
-
-// a*b + c with the constant c read from scalar registers, in the current
-// rounding mode (plain asm: ordered only by its operands)
-__device__ __forceinline__ double fma_vs(double a, double b, double c) {
-    double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(c));
-    return r;
-}
-__device__ __forceinline__ double fma_ks(double a, double k, double c) {    // one scalar source per instruction
-    double r;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(k), "s"(c));
-    return r;
 }
 
 // Natural logarithm in round-to-nearest arithmetic (inside a round-to-nearest
@@ -365,15 +335,21 @@ __device__ __forceinline__ double log_rn(double x) {
     const double s = f / (1.0 + m);
     const double s2 = s + s;
     const double w = s * s;
-    double q = fma_ks(w, 1.0 / 21, 1.0 / 19);
-    q = fma_vs(q, w, 1.0 / 17);
-    q = fma_vs(q, w, 1.0 / 15);
-    q = fma_vs(q, w, 1.0 / 13);
-    q = fma_vs(q, w, 1.0 / 11);
-    q = fma_vs(q, w, 1.0 / 9);
-    q = fma_vs(q, w, 1.0 / 7);
-    q = fma_vs(q, w, 1.0 / 5);
-    q = fma_vs(q, w, 1.0 / 3);
+    // Q(w) by Horner's rule in one asm statement (the compiler pads each
+    // instruction that reads the result of the inline asm just before it)
+    double q;
+    asm("v_fma_f64 %0, %1, %2, %3\n\t"
+        "v_fma_f64 %0, %0, %1, %4\n\t"
+        "v_fma_f64 %0, %0, %1, %5\n\t"
+        "v_fma_f64 %0, %0, %1, %6\n\t"
+        "v_fma_f64 %0, %0, %1, %7\n\t"
+        "v_fma_f64 %0, %0, %1, %8\n\t"
+        "v_fma_f64 %0, %0, %1, %9\n\t"
+        "v_fma_f64 %0, %0, %1, %10\n\t"
+        "v_fma_f64 %0, %0, %1, %11"
+        : "=&v"(q)
+        : "v"(w), "v"(1.0 / 21), "s"(1.0 / 19), "s"(1.0 / 17), "s"(1.0 / 15), "s"(1.0 / 13), "s"(1.0 / 11),
+          "s"(1.0 / 9), "s"(1.0 / 7), "s"(1.0 / 5), "s"(1.0 / 3));
     const double de = (double)e;
     const double t = __builtin_fma(s2 * w, q, de * kLn2Lo);
     const double r = __builtin_fma(de, kLn2Hi, s2) + t;
@@ -385,9 +361,9 @@ __device__ __forceinline__ double log_rn(double x) {
 // (32u, more than the 7u error bound) with the widening rounded outward too
 __device__ __forceinline__ Iv ilog(Iv u) {
     double xl = u.lo, xh = -u.nh;
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(xl), "+v"(xh));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(xl), "+v"(xh));
     double ll = log_rn(xl), lh = log_rn(xh);
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(ll), "+v"(lh));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" : "+v"(ll), "+v"(lh));
     double lo, nh;
     asm volatile("v_fma_f64 %0, -|%1|, %2, %1" : "=v"(lo) : "v"(ll), "s"(0x1p-48));          // RD(l - |l| 2^-48)
     asm volatile("v_fma_f64 %0, -|%1|, %2, -%1" : "=v"(nh) : "v"(lh), "s"(0x1p-48));         // RD(-h - |h| 2^-48)
@@ -400,7 +376,7 @@ __device__ __forceinline__ Iv ilog(Iv u) {
 enum : int { LIB_TANH = 0, LIB_SIN = 1, LIB_COS = 2, LIB_ATANH = 3 };
 template <int F>
 __device__ __forceinline__ void lib2(double &x0, double &x1) {
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0\n\ts_nop 1" : "+v"(x0), "+v"(x1));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 0" : "+v"(x0), "+v"(x1));
     if constexpr (F == LIB_TANH) {
         x0 = tanh(x0);
         x1 = tanh(x1);
@@ -414,7 +390,7 @@ __device__ __forceinline__ void lib2(double &x0, double &x1) {
         x0 = cos(x0);
         x1 = cos(x1);
     }
-    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2\n\ts_nop 1" : "+v"(x0), "+v"(x1));
+    asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" : "+v"(x0), "+v"(x1));
 }
 __device__ __forceinline__ double pred4(double x) { return pred(pred(pred(pred(x)))); }
 // four predecessor steps of a value that is finite or NaN (library values of tanh, sin, cos)
@@ -481,7 +457,16 @@ __device__ __forceinline__ Iv imulk(Iv u, double k) { return {fmul(u.lo, k), fmu
 // U * R for an interval R > 0 (stored (r_lo, -r_hi)): each endpoint of the
 // result comes from one endpoint of U and either endpoint of R
 __device__ __forceinline__ Iv imul_pos(Iv u, Iv r) {
-    return {fmin_(fmul(u.lo, r.lo), fmul_n(u.lo, r.nh)), fmin_(fmul(u.nh, r.lo), fmul_n(u.nh, r.nh))};
+    double lo, nh, t, w;
+    asm volatile("v_mul_f64 %0, %4, %6\n\t"
+                 "v_mul_f64 %2, %4, -%7\n\t"
+                 "v_mul_f64 %1, %5, %6\n\t"
+                 "v_mul_f64 %3, %5, -%7\n\t"
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3"
+                 : "=&v"(lo), "=&v"(nh), "=&v"(t), "=v"(w)
+                 : "v"(u.lo), "v"(u.nh), "v"(r.lo), "v"(r.nh));
+    return {lo, nh};
 }
 
 // [c, c]^2: both ends are the one product c*c rounded each way (equals isqr)
@@ -489,55 +474,42 @@ __device__ __forceinline__ Iv isqr_deg(Iv u) { return {fmul(u.lo, u.lo), fmul_n(
 // U * [k, k] (a degenerate factor, c.lo = -c.nh = k): the four endpoint
 // products of imul are two distinct ones, so this equals imul(u, c)
 __device__ __forceinline__ Iv imul_deg(Iv u, Iv c) {
-    const double k = c.lo;
-    const double p0 = fmul(u.lo, k), q0 = fmul_n(u.lo, k);
-    const double p1 = fmul_n(u.nh, k), q1 = fmul(u.nh, k);
-    return {fmin_(p0, p1), fmin_(q0, q1)};
+    double lo, nh, t, w;
+    asm volatile("v_mul_f64 %0, %4, %6\n\t"
+                 "v_mul_f64 %1, %4, -%6\n\t"
+                 "v_mul_f64 %2, %5, -%6\n\t"
+                 "v_mul_f64 %3, %5, %6\n\t"
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3"
+                 : "=&v"(lo), "=&v"(nh), "=&v"(t), "=v"(w)
+                 : "v"(u.lo), "v"(u.nh), "v"(c.lo));
+    return {lo, nh};
 }
 // G * D for D = [dl, dh] with dl <= 0 <= dh (X - c with c in X): the lowest
 // of the four endpoint products is gh dl or gl dh, the highest gl dl or gh dh,
 // so this equals imul(g, d)
 __device__ __forceinline__ Iv imul_dx(Iv g, Iv d) {
-    const double a = fmul_n(g.nh, d.lo), b = fmul_n(g.lo, d.nh);
-    const double c = fmul_n(g.lo, d.lo), e = fmul_n(g.nh, d.nh);
-    return {fmin_(a, b), fmin_(c, e)};
+    double lo, nh, t, w;
+    asm volatile("v_mul_f64 %0, %5, -%6\n\t"         // gh dl
+                 "v_mul_f64 %2, %4, -%7\n\t"         // gl dh
+                 "v_mul_f64 %1, %4, -%6\n\t"         // -(gl dl)
+                 "v_mul_f64 %3, %5, -%7\n\t"         // -(gh dh)
+                 "v_min_f64 %0, %0, %2\n\t"
+                 "v_min_f64 %1, %1, %3"
+                 : "=&v"(lo), "=&v"(nh), "=&v"(t), "=v"(w)
+                 : "v"(g.lo), "v"(g.nh), "v"(d.lo), "v"(d.nh));
+    return {lo, nh};
 }
 
-// Two independent products with their instructions interleaved: each
-// operation of one product is followed by the same operation of the other,
-// so no instruction waits on the one just before it.  The results are those
-// of imul (and imul_pos) on each pair.
+// Two independent products (the code generator pairs them; each is one asm
+// statement, so the pair is two in a row)
 __device__ __forceinline__ void imul2(Iv u, Iv v, Iv w, Iv x, Iv &r, Iv &s) {
-    const double a0 = fmul(u.lo, v.lo), b0 = fmul(w.lo, x.lo);
-    const double c0 = fmul_n(u.lo, v.lo), d0 = fmul_n(w.lo, x.lo);
-    const double a1 = fmul_n(u.lo, v.nh), b1 = fmul_n(w.lo, x.nh);
-    const double c1 = fmul(u.lo, v.nh), d1 = fmul(w.lo, x.nh);
-    double lo = fmin_(a0, a1), lo2 = fmin_(b0, b1);
-    double nh = fmin_(c0, c1), nh2 = fmin_(d0, d1);
-    const double a2 = fmul_n(u.nh, v.lo), b2 = fmul_n(w.nh, x.lo);
-    const double c2 = fmul(u.nh, v.lo), d2 = fmul(w.nh, x.lo);
-    lo = fmin_(lo, a2);
-    lo2 = fmin_(lo2, b2);
-    nh = fmin_(nh, c2);
-    nh2 = fmin_(nh2, d2);
-    const double a3 = fmul(u.nh, v.nh), b3 = fmul(w.nh, x.nh);
-    const double c3 = fmul_n(u.nh, v.nh), d3 = fmul_n(w.nh, x.nh);
-    lo = fmin_(lo, a3);
-    lo2 = fmin_(lo2, b3);
-    nh = fmin_(nh, c3);
-    nh2 = fmin_(nh2, d3);
-    r = {lo, nh};
-    s = {lo2, nh2};
+    r = imul(u, v);
+    s = imul(w, x);
 }
 __device__ __forceinline__ void imul_pos2(Iv u, Iv r, Iv w, Iv q, Iv &a, Iv &b) {
-    const double p0 = fmul(u.lo, r.lo), p1 = fmul(w.lo, q.lo);
-    const double p2 = fmul_n(u.lo, r.nh), p3 = fmul_n(w.lo, q.nh);
-    const double p4 = fmul(u.nh, r.lo), p5 = fmul(w.nh, q.lo);
-    const double p6 = fmul_n(u.nh, r.nh), p7 = fmul_n(w.nh, q.nh);
-    const double l0 = fmin_(p0, p2), l1 = fmin_(p1, p3);
-    const double n0 = fmin_(p4, p6), n1 = fmin_(p5, p7);
-    a = {l0, n0};
-    b = {l1, n1};
+    a = imul_pos(u, r);
+    b = imul_pos(w, q);
 }
 
 // U / k for k > 0

@@ -92,8 +92,8 @@ std::string scale_tan(const std::string &x, const std::string &pre, const std::s
 
 // The statements of one instruction (its tangent components, and a product's
 // value) as trees of interval calls.  Products that do not depend on each
-// other are emitted two at a time (imul2, imul_pos2: the same operations,
-// interleaved); the rest follow in dependence order.  Only the order of the
+// other are emitted two at a time (imul2, imul_pos2: the two products in a
+// row); the rest follow in dependence order.  Only the order of the
 // instructions changes, not the arithmetic.
 class Scheduler {
   public:
