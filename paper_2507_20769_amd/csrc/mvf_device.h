@@ -227,22 +227,19 @@ __device__ __forceinline__ Iv imul(Iv u, Iv v) {
 }
 
 // [a, b]^2: the upper end is the square of max(|a|, |b|); the lower end the
-// square of min(|a|, |b|), or 0 when a <= 0 <= b
-__device__ __forceinline__ double fmax_abs(double a, double b) {
-    double r;
-    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
-__device__ __forceinline__ double fmin_abs(double a, double b) {
-    double r;
-    asm("v_min_f64 %0, |%1|, |%2|" : "=v"(r) : "v"(a), "v"(b));
-    return r;
-}
+// square of max(a, -b, 0), which is min(|a|, |b|) when 0 is not in [a, b]
+// and 0 when it is (a square of a zero is +0 in every rounding mode).  One
+// asm statement; nh = -b, so max(a, -b) is max(lo, nh).
 __device__ __forceinline__ Iv isqr(Iv u) {
-    const double mx = fmax_abs(u.lo, u.nh), mn = fmin_abs(u.lo, u.nh);
-    const double nh = fmul_n(mx, mx), lo = fmul(mn, mn);
-    const bool straddle = u.lo <= 0.0 && u.nh <= 0.0;       // lo <= 0 <= hi
-    return {straddle ? 0.0 : lo, nh};
+    double lo, nh;
+    asm volatile("v_max_f64 %1, |%2|, |%3|\n\t"
+                 "v_max_f64 %0, %2, %3\n\t"
+                 "v_mul_f64 %1, %1, -%1\n\t"
+                 "v_max_f64 %0, %0, 0\n\t"
+                 "v_mul_f64 %0, %0, %0"
+                 : "=v"(lo), "=&v"(nh)
+                 : "v"(u.lo), "v"(u.nh));
+    return {lo, nh};
 }
 
 // U / V with 0 not in V: the extreme quotients are picked by the signs

@@ -230,3 +230,34 @@ def test_division_by_constants_at_the_extremes():
                 g = gpu_bound(tape, box, [1], mode="nie", handle=h, engine=engine)
                 assert np.array_equal(g["per_sub"], o["per_sub"]), (k, b, engine, g["per_sub"], o["per_sub"])
         h.close()
+
+
+@pytest.mark.parametrize("engine", ["interp", "spec"])
+def test_square_at_sign_boundaries(engine):
+    # x^2 (the interval square) and x*x (the general product) on one-subdomain boxes whose ends
+    # are zeros of either sign, tiny, huge or on both sides of 0: bitwise the oracle's, and the
+    # square is [0, max(a^2, b^2)] when a <= 0 <= b, [min^2, max^2] otherwise
+    from fractions import Fraction
+    V = I.VAR
+    nodes = np.array([(V, 0, -1), (I.SQR, 0, -1), (I.MUL, 0, 0)], dtype=I.NODE_DTYPE)
+    tape = I.Tape(nodes, np.zeros(0), np.array([1, 2], dtype=np.int32), 1)
+    ends = [(-2.0, 3.0), (-3.0, 2.0), (2.0, 5.0), (-5.0, -2.0), (-0.0, 0.0), (0.0, 0.0), (-0.0, 4.0),
+            (-4.0, -0.0), (1e-200, 2e-200), (-1e-200, 1e-200), (-3e-160, -1e-160), (1e200, 1e300),
+            (-1e300, 1e250), (0.1, 0.3), (-0.7, 0.2), (5e-324, 1e-323)]
+    h = _handle(tape, grad="auto") if engine == "spec" else None
+    for a, b in ends:
+        box = np.array([[a, b]])
+        print(f"[case] square of [{a!r}, {b!r}] engine={engine}", flush=True)
+        for grad in ("fwd", "rev"):
+            g = gpu_bound(tape, box, [1], mode="nie", grad=grad, handle=h, engine=engine)
+            o = O.bound(tape, box, [1], mode=O.MODE_NIE, grad=O.GRAD_FWD if grad == "fwd" else O.GRAD_REV)
+            assert_parity(g["per_sub"], o["per_sub"], True, what=f"[{a}, {b}] {grad}")
+        lo, hi = g["per_sub"][0, :, 0]
+        fa, fb = Fraction(a), Fraction(b)
+        sq_hi = max(fa * fa, fb * fb)
+        sq_lo = Fraction(0) if a <= 0.0 <= b else min(fa * fa, fb * fb)
+        assert (lo == 0.0 or Fraction(lo) <= sq_lo) and (hi == np.inf or sq_hi <= Fraction(hi)), (a, b, lo, hi)
+        if a <= 0.0 <= b:
+            assert lo == 0.0 and not np.signbit(lo), (a, b, lo)
+    if h is not None:
+        h.close()
