@@ -284,6 +284,18 @@ __device__ __forceinline__ Iv isqrt(Iv u) {
 }
 
 // 2U (exact up to overflow)
+// U + k and k - U for a constant k, each one asm statement with k read from
+// scalar registers (the same two sums as iadd and isub with [k, k])
+__device__ __forceinline__ Iv iaddk(Iv u, double k) {
+    double lo, nh;
+    asm volatile("v_add_f64 %0, %2, %4\n\tv_add_f64 %1, %3, -%4" : "=&v"(lo), "=v"(nh) : "v"(u.lo), "v"(u.nh), "s"(k));
+    return {lo, nh};
+}
+__device__ __forceinline__ Iv iksub(double k, Iv u) {
+    double lo, nh;
+    asm volatile("v_add_f64 %0, %4, %3\n\tv_add_f64 %1, %2, -%4" : "=&v"(lo), "=v"(nh) : "v"(u.lo), "v"(u.nh), "s"(k));
+    return {lo, nh};
+}
 __device__ __forceinline__ Iv itwice(Iv u) { return {fadd(u.lo, u.lo), fadd(u.nh, u.nh)}; }
 
 // enclosure of 1/(2 sqrt(u)) from Z = sqrt(U); unbounded above when z_lo is 0
@@ -450,6 +462,12 @@ __device__ __forceinline__ Iv icos_deriv(Iv u) { return ineg(isin(u)); }
 
 // U * k for k > 0
 __device__ __forceinline__ Iv imulk(Iv u, double k) { return {fmul(u.lo, k), fmul(u.nh, k)}; }
+// the same for a compile-time constant k: one asm statement, k from scalar registers
+__device__ __forceinline__ Iv imulks(Iv u, double k) {
+    double lo, nh;
+    asm volatile("v_mul_f64 %0, %2, %4\n\tv_mul_f64 %1, %3, %4" : "=&v"(lo), "=v"(nh) : "v"(u.lo), "v"(u.nh), "s"(k));
+    return {lo, nh};
+}
 
 // U * R for an interval R > 0 (stored (r_lo, -r_hi)): each endpoint of the
 // result comes from one endpoint of U and either endpoint of R

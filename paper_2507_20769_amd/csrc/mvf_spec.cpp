@@ -157,7 +157,7 @@ class Scheduler {
 
     bool is_op(int k) const { return !pool[k].fn.empty() && pool[k].fn != "ineg"; }
     static bool scheduled(const std::string &f) {
-        return f == "imul" || f == "imul_pos" || f == "iadd" || f == "isub" || f == "imulk" || f == "ineg";
+        return f == "imul" || f == "imul_pos" || f == "iadd" || f == "isub" || f == "imulks" || f == "ineg";
     }
     static void skip(const std::string &e, size_t &i) {
         while (i < e.size() && e[i] == ' ') ++i;
@@ -311,7 +311,7 @@ class PassWriter {
             case I_MULK:
             case I_MULKN:
                 contribute(I.ak, I.a, st.pa, ia, false,
-                           "imulk(" + (I.op == I_MULKN ? "ineg(" + zb + ")" : zb) + ", " + lit(I.k) + ")");
+                           "imulks(" + (I.op == I_MULKN ? "ineg(" + zb + ")" : zb) + ", " + lit(I.k) + ")");
                 break;
             default:   // I_DIVK, I_DIVKN
                 contribute(I.ak, I.a, st.pa, ia, false,
@@ -523,8 +523,8 @@ class PassWriter {
             const std::string tu = "u" + std::to_string(pc);
             decl.push_back("Iv " + tu + ";");
             s += tu + " = " + U + "; ";
-            if (I.op == I_ADDK) s += z + " = Iv{fadd(" + tu + ".lo, " + k + "), fsub(" + tu + ".nh, " + k + ")};";
-            else if (ks) s += z + " = Iv{fadd(" + k + ", " + tu + ".nh), fsub(" + tu + ".lo, " + k + ")};";
+            if (I.op == I_ADDK) s += z + " = iaddk(" + tu + ", " + k + ");";
+            else if (ks) s += z + " = iksub(" + k + ", " + tu + ");";
             else s += z + " = " + tu + ";";
             if (ad) for (int t = 0; t < C; ++t) Z[t] = ks ? scale_tan(A[t], "ineg(", ")") : A[t];
             if (ha >= 0) Z[ha] = ks ? "ineg(kOne)" : "kOne";
@@ -534,9 +534,9 @@ class PassWriter {
         case I_MULKN: {
             const bool ng = I.op == I_MULKN;
             auto sg = [&](const std::string &x) { return ng ? "ineg(" + x + ")" : x; };
-            s += z + " = imulk(" + sg(U) + ", " + k + ");";
-            if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : "imulk(" + sg(A[t]) + ", " + k + ")";
-            if (ha >= 0) Z[ha] = "imulk(" + sg("kOne") + ", " + k + ")";
+            s += z + " = imulks(" + sg(U) + ", " + k + ");";
+            if (ad) for (int t = 0; t < C; ++t) Z[t] = is_zero(A[t]) ? A[t] : "imulks(" + sg(A[t]) + ", " + k + ")";
+            if (ha >= 0) Z[ha] = "imulks(" + sg("kOne") + ", " + k + ")";
             break;
         }
         default: {   // I_DIVK, I_DIVKN: operand b indexes the enclosure of 1/k
