@@ -18,7 +18,7 @@
 //     the (re-used) slot file and the variable gradients in LDS;
 //   * MVF = [f(c)] + sum_i G_i * (X_i - c_i), i ascending, intersected with
 //     the NIE.
-// The subdomain bounds are min-reduced per wave with cross-lane shuffles, per
+// The subdomain bounds are min-reduced per wave with DPP lane moves, per
 // workgroup through LDS and across workgroups by a second kernel (Sec. 3.1
 // Step 3, the interval hull).  The batched form runs many B&B nodes of
 // uneven size in one persistent launch: workgroups pull (node, chunk) work
@@ -616,7 +616,7 @@ __device__ __forceinline__ double block_min(double v, double *sv, int tid) {
 // and the two B&B bounds (extra, nullable): every thread takes the minima of
 // all quantities over its share of the blocks (one block each up to 1024
 // blocks, so all loads are in flight at once), each wave reduces them with
-// cross-lane shuffles, and the last step combines the waves.
+// DPP lane moves, and the last step combines the waves.
 constexpr int FIN_BLK = 1024;
 __global__ __launch_bounds__(FIN_BLK) void finish_kernel(const double *partial, const double *plo0, const int64_t *pk,
                                                          const double *pext, int nblocks, int m, double *reduced,

@@ -38,21 +38,50 @@ __device__ __forceinline__ KPtr<K> kargs() {
 constexpr Iv kZero = {0.0, 0.0};
 constexpr Iv kOne = {1.0, -1.0};
 
+// Wave reductions with DPP lane moves (VALU, no LDS round trip): swaps within
+// quads, mirrors within half-rows and rows (each lane then holds its row's
+// result), then row 0 into row 1 and row 2 into row 3, then row 1 into rows 2
+// and 3; lane 63 ends with the whole wave's, which is read back uniform.  A
+// lane a move does not write keeps its own value, which the minimum ignores.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t x) {
+    const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+    const int rlo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+    const int rhi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+    return (uint64_t)(uint32_t)rhi << 32 | (uint32_t)rlo;
+}
+__device__ __forceinline__ uint64_t lane63_u64(uint64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+    return (uint64_t)hi << 32 | lo;
+}
+// the six moves: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror, row_bcast:15 into rows 1 and 3, row_bcast:31 into rows 2 and 3
+#define MVF_WAVE_STEPS(STEP) \
+    STEP(0xB1, 0xf) STEP(0x4E, 0xf) STEP(0x141, 0xf) STEP(0x140, 0xf) STEP(0x142, 0xa) STEP(0x143, 0xc)
+
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+#define MVF_MIN_STEP(C, R) \
+    v = fmin_(v, __builtin_bit_cast(double, dpp_u64<C, R>(__builtin_bit_cast(uint64_t, v))));
+    MVF_WAVE_STEPS(MVF_MIN_STEP)
+#undef MVF_MIN_STEP
+    return __builtin_bit_cast(double, lane63_u64(__builtin_bit_cast(uint64_t, v)));
 }
 
+// (value, index) minimum, ties to the smaller index
 __device__ __forceinline__ void wave_argmin(double &v, int64_t &k) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        double v2 = __shfl_xor(v, o, 64);
-        int64_t k2 = __shfl_xor(k, o, 64);
-        const bool take = v2 < v || (v2 == v && k2 < k);
-        v = take ? v2 : v;
-        k = take ? k2 : k;
+#define MVF_ARGMIN_STEP(C, R)                                                                        \
+    {                                                                                                \
+        const double v2 = __builtin_bit_cast(double, dpp_u64<C, R>(__builtin_bit_cast(uint64_t, v))); \
+        const int64_t k2 = (int64_t)dpp_u64<C, R>((uint64_t)k);                                       \
+        const bool take = v2 < v || (v2 == v && k2 < k);                                             \
+        v = take ? v2 : v;                                                                           \
+        k = take ? k2 : k;                                                                           \
     }
+    MVF_WAVE_STEPS(MVF_ARGMIN_STEP)
+#undef MVF_ARGMIN_STEP
+    v = __builtin_bit_cast(double, lane63_u64(__builtin_bit_cast(uint64_t, v)));
+    k = (int64_t)lane63_u64((uint64_t)k);
 }
 
 // Where a lane's results go: the optional per-subdomain output and the wave's
@@ -97,12 +126,14 @@ __device__ __forceinline__ void track_root(FeasTrack &F, int r, Iv B, Iv FC, boo
 }
 
 __device__ __forceinline__ int64_t wave_min_i64(int64_t v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        const int64_t u = __shfl_xor(v, o, 64);
-        v = u < v ? u : v;
+#define MVF_MINI_STEP(C, R)                                \
+    {                                                      \
+        const int64_t u = (int64_t)dpp_u64<C, R>((uint64_t)v); \
+        v = u < v ? u : v;                                 \
     }
-    return v;
+    MVF_WAVE_STEPS(MVF_MINI_STEP)
+#undef MVF_MINI_STEP
+    return (int64_t)lane63_u64((uint64_t)v);
 }
 
 // Fold root r's bound on this lane's subdomain into the wave record.  A lane
