@@ -46,8 +46,8 @@ FP64_PUBLISHED_PEAK = 78.6e12
 # HBM bytes per launch of the headline kernel from rocprofv3 counters (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00,
 # the factors from a 256 MiB copy in the same runs), valid only for the kernel build and tape they were
 # taken on: (engine, grad, tape hash) -> bytes
-TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea"): (9316.4 * 2.0 + 44414.0) * 1024,
-           ("spec", "rev", "aa75c5b416e4faea"): (145360.9 * 2.0 + 279702.7) * 1024}
+TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea"): (7824.2 * 2.0 + 41133.4) * 1024,
+           ("spec", "rev", "aa75c5b416e4faea"): (141888.8 * 2.0 + 278716.2) * 1024}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 
 
