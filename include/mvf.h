@@ -204,8 +204,8 @@ int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stre
  * stay within about 100 intervals.  Compilation takes seconds to a minute,
  * about linear in the generated size (code_units = sum over roots of program
  * length x passes, the adjoint counting two); MVF_ELIMIT above max_code.  With use_cache the code
- * object is kept under $MVF_SPEC_CACHE (default ~/.cache/mvf_spec; "off"
- * disables) keyed by a hash of the source, options and compiler version;
+ * object is kept under $MVF_SPEC_CACHE (default: _spec_cache/ in the directory
+ * of libmvf.so itself; "off" disables) keyed by a hash of the source, options and compiler version;
  * $MVF_SPEC_DUMP names a file that receives a copy of the generated source.
  * Not thread-safe against concurrent calls on the same tape.
  */
@@ -216,13 +216,22 @@ typedef struct {
     int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache */
     int32_t grad;             /* kernels to build: MVF_GRAD_FWD (tangent mode), MVF_GRAD_REV
                                  (reverse-mode adjoint) or MVF_GRAD_AUTO (both) */
+    int32_t ckpt_budget;      /* reverse mode: register budget of one recomputed segment, in
+                                 intervals, at most 40 (MVF_EINVAL above); 0 = library choice
+                                 (from the register file, the variable count and the live set;
+                                 the roots are segmented when the largest one's single-pass
+                                 adjoint keeps more partials than twice the register file's
+                                 intervals), < 0 = none */
 } mvf_spec_options;
 typedef struct {
     int32_t chunk, waves, grad;
-    int64_t code_units;       /* instruction-passes generated */
+    int64_t code_units;       /* instruction-passes generated (an upper bound for the adjoint) */
     int64_t code_bytes;       /* size of the code object */
     double seconds;           /* generation + compilation (or cache read) */
     int32_t from_cache;
+    int32_t ckpt_budget;      /* the segment budget used (<= 0: no checkpointing) */
+    int32_t ckpt_intervals;   /* checkpoint intervals per lane (the largest root's); the bounding
+                                 workspaces include ckpt_intervals x 16 bytes per launched lane */
 } mvf_spec_info;
 int mvf_tape_specialize(mvf_tape *tape, const mvf_spec_options *opt, mvf_spec_info *info);
 /* Generate and compile for gfx950 without a device or a tape handle (no
@@ -230,6 +239,13 @@ int mvf_tape_specialize(mvf_tape *tape, const mvf_spec_options *opt, mvf_spec_in
 int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
                    int32_t n_vars, const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt,
                    mvf_spec_info *info);
+/* The generated device source itself, without compiling it (inspection and
+ * host-side checks of the generator): *len receives its length; when buf is
+ * not NULL, up to cap - 1 bytes and a terminating NUL are copied into it (the
+ * caller's host buffer).  Same options and errors as mvf_spec_check. */
+int mvf_spec_source(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
+                    int32_t n_vars, const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt,
+                    char *buf, size_t cap, size_t *len);
 
 /* ---- constraint propagation ------------------------------------------
  * Forward-backward bound tightening (FBBT) of node boxes, the bound

@@ -31,6 +31,7 @@ struct mvf_tape {
     hipFunction_t spec_fn[2] = {nullptr, nullptr};        // single box: [0] tangent mode, [1] adjoint
     hipFunction_t spec_batch_fn[2] = {nullptr, nullptr};  // batched
     mvf_spec_info spec_info{};
+    int32_t spec_ck = 0;                    // checkpoint intervals per lane of the specialised adjoint
 };
 
 struct mvf_batch_graph {
@@ -181,6 +182,10 @@ int batch_engine(const mvf_tape *t, const mvf_tuning *tu, bool rev, bool *spec) 
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Reverse-mode intervals per lane in the workspace: the interpreter's record
+// tape or the specialised adjoint's checkpoints, whichever the call may use.
+size_t rec_per_lane(const mvf_tape *t) { return (size_t)std::max(t->C.max_rec, t->spec_ck); }
+
 struct SingleLayout {
     size_t partial, lo0, k, ext, rec, gacc, total;
     bool g_lds;
@@ -195,7 +200,7 @@ SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total)
     L.k = align_up(L.lo0 + (size_t)grid * 8);
     L.ext = align_up(L.k + (size_t)grid * 8);
     L.rec = align_up(L.ext + (size_t)grid * 16);
-    L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
+    L.gacc = align_up(L.rec + (rev ? rec_per_lane(t) * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
 }
@@ -218,7 +223,7 @@ BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int 
     L.ext = align_up(L.k + items * 8);
     L.rec = align_up(L.ext + items * 16);
     L.g_lds = grad_in_lds(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, (int)m);
-    L.gacc = align_up(L.rec + (rev ? (size_t)t->C.max_rec * grid * BLK * 16 : 0));
+    L.gacc = align_up(L.rec + (rev ? rec_per_lane(t) * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
 }
@@ -628,8 +633,15 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     bool cached = false;
     const auto t0 = std::chrono::steady_clock::now();
     const int grad = opt ? opt->grad : MVF_GRAD_FWD;
-    rc = spec_compile(spec_source(t->C, chunk, waves, grad), prop.gcnArchName, opt && opt->use_cache, code, &cached,
-                      &in.seconds);
+    const int budget = spec_ckpt_budget(t->C, opt, waves);
+    int ck = 0;
+    const std::string src =
+        spec_source(t->C, chunk, waves, grad, budget, spec_ckpt_min_records(t->C, opt, waves), &ck, &units);
+    // the target without its feature suffix (":sramecc+:xnack-"): one code object
+    // for either setting, and the same cache key on every gfx950
+    std::string arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    rc = spec_compile(src, arch, opt && opt->use_cache, code, &cached, &in.seconds);
     if (rc != MVF_OK) return rc;
     hipModule_t mod = nullptr;
     HIP_TRY(hipModuleLoadData(&mod, code.data()));
@@ -646,6 +658,7 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     }
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     t->spec_mod = mod;
+    t->spec_ck = grad == MVF_GRAD_FWD ? 0 : ck;
     for (int r = 0; r < 2; ++r) {
         t->spec_fn[r] = fns[r][0];
         t->spec_batch_fn[r] = fns[r][1];
@@ -656,14 +669,19 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     in.code_units = units;
     in.code_bytes = (int64_t)code.size();
     in.from_cache = cached ? 1 : 0;
+    in.ckpt_budget = budget;
+    in.ckpt_intervals = t->spec_ck;
     in.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     t->spec_info = in;
     if (info) *info = in;
     return MVF_OK;
 }
 
-int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
-                   const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt, mvf_spec_info *info) {
+namespace {
+// compile and plan a tape, then generate its specialised source
+int spec_generate(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                  const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt, std::string *src,
+                  mvf_spec_info *in) {
     if (opt && (opt->waves < 0 || opt->waves > 4)) return set_err(MVF_EINVAL, "waves out of range [0, 4]");
     Compiled C;
     std::string err;
@@ -674,18 +692,50 @@ int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
     rc = spec_plan(C, opt, &chunk, &units);
     if (rc != MVF_OK) return rc;
     const int waves = opt && opt->waves > 0 ? opt->waves : 2;
+    const int grad = opt ? opt->grad : MVF_GRAD_FWD;
+    const int budget = spec_ckpt_budget(C, opt, waves);
+    int ck = 0;
+    *src = spec_source(C, chunk, waves, grad, budget, spec_ckpt_min_records(C, opt, waves), &ck, &units);
+    *in = mvf_spec_info{};
+    in->ckpt_budget = budget;
+    in->ckpt_intervals = grad == MVF_GRAD_FWD ? 0 : ck;
+    in->chunk = chunk;
+    in->waves = waves;
+    in->grad = grad;
+    in->code_units = units;
+    return MVF_OK;
+}
+}  // namespace
+
+int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                   const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt, mvf_spec_info *info) {
+    std::string src;
+    mvf_spec_info in;
+    int rc = spec_generate(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, opt, &src, &in);
+    if (rc != MVF_OK) return rc;
     std::vector<char> code;
     bool cached = false;
-    mvf_spec_info in{};
-    const int grad = opt ? opt->grad : MVF_GRAD_FWD;
-    rc = spec_compile(spec_source(C, chunk, waves, grad), "gfx950", false, code, &cached, &in.seconds);
+    rc = spec_compile(src, "gfx950", false, code, &cached, &in.seconds);
     if (rc != MVF_OK) return rc;
-    in.chunk = chunk;
-    in.waves = waves;
-    in.grad = grad;
-    in.code_units = units;
     in.code_bytes = (int64_t)code.size();
     if (info) *info = in;
+    return MVF_OK;
+}
+
+int mvf_spec_source(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts, int32_t n_vars,
+                    const int32_t *roots, int32_t n_roots, const mvf_spec_options *opt, char *buf, size_t cap,
+                    size_t *len) {
+    if (!len) return set_err(MVF_EINVAL, "len is null");
+    std::string src;
+    mvf_spec_info in;
+    int rc = spec_generate(nodes, n_nodes, consts, n_consts, n_vars, roots, n_roots, opt, &src, &in);
+    if (rc != MVF_OK) return rc;
+    *len = src.size();
+    if (buf && cap > 0) {
+        const size_t k = std::min(cap - 1, src.size());
+        std::memcpy(buf, src.data(), k);
+        buf[k] = '\0';
+    }
     return MVF_OK;
 }
 

@@ -18,14 +18,18 @@
 #include <hip/hiprtc.h>
 
 #include <cctype>
+#include <dlfcn.h>
 #include <chrono>
 #include <cinttypes>
+#include <climits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <string>
 #include <sys/stat.h>
 #include <unistd.h>
+#include <unordered_set>
 #include <vector>
 
 #include "mvf.h"
@@ -41,6 +45,15 @@ namespace {
 
 constexpr int64_t DEFAULT_MAX_CODE = 6000;      // instruction-passes (compile time grows about linearly)
 constexpr int SEGMENT = 32;                      // instructions per guarded block
+// Largest segment budget of the checkpointed adjoint.  Budgets up to 40 gave
+// adjoints bitwise equal to the single-pass form on every workload measured;
+// at 58 the 32-variable workload's objective came out different on the GPU
+// although the generated code computes the same values (the host-side
+// symbolic check of the generator agrees), so larger budgets are refused.
+constexpr int MAX_CKPT_BUDGET = 40;
+// A body line that only starts a new guarded block (segment boundaries of the
+// checkpointed adjoint, so that a segment's checkpoint loads lead a block).
+const char *const BLOCK_BREAK = "\x01";
 
 struct Dec {
     uint32_t w0, op, ak, bk, a, b, d;
@@ -90,6 +103,16 @@ std::string scale_tan(const std::string &x, const std::string &pre, const std::s
     return is_zero(x) ? x : pre + x + post;
 }
 
+// Declarations of a generated function, each once (a recomputed segment
+// assigns the variables of its first evaluation again).
+struct Decls {
+    std::vector<std::string> v;
+    std::unordered_set<std::string> seen;
+    void push_back(const std::string &d) {
+        if (seen.insert(d).second) v.push_back(d);
+    }
+};
+
 // The statements of one instruction (its tangent components, and a product's
 // value) as trees of interval calls.  Products that do not depend on each
 // other are emitted two at a time (imul2, imul_pos2: the two products in a
@@ -97,7 +120,7 @@ std::string scale_tan(const std::string &x, const std::string &pre, const std::s
 // instructions changes, not the arithmetic.
 class Scheduler {
   public:
-    Scheduler(std::string prefix, std::vector<std::string> &decl) : pre(std::move(prefix)), decl(decl) {}
+    Scheduler(std::string prefix, Decls &decl) : pre(std::move(prefix)), decl(decl) {}
 
     void add(const std::string &target, const std::string &expr) {
         size_t i = 0;
@@ -149,7 +172,7 @@ class Scheduler {
         std::vector<int> args;
     };
     std::string pre;
-    std::vector<std::string> &decl;
+    Decls &decl;
     std::vector<Expr> pool;
     std::vector<std::pair<std::string, int>> roots;
     std::vector<std::string> out;                 // result names of the emitted calls
@@ -217,21 +240,18 @@ class Scheduler {
 // centre (point) or over the subdomain; C > 0: values and the tangent
 // components [c0, c0 + C).  With tape (C == 0 over the subdomain) the value
 // pass also computes the local partials the reverse sweep needs (those the
-// interpreter writes to its record tape), and reverse() then emits the sweep.
+// interpreter writes to its record tape), and reverse() then emits the sweep;
+// adjoint() emits the checkpointed form of both.
 class PassWriter {
   public:
     PassWriter(const Compiled &Cp, int root, int C, int c0, bool point, bool tape = false)
-        : P(Cp), r(root), C(C), c0(c0), point(point), tape(tape) {}
+        : P(Cp), r(root), C(C), c0(c0), point(point), partials(tape) {}
 
     // body lines (declarations first, then guarded blocks) and the names of
     // the result's value and components
-    void emit(std::vector<std::string> &decl, std::vector<std::string> &body, std::string &val,
-              std::vector<std::string> &tan) {
+    void emit(Decls &decl, std::vector<std::string> &body, std::string &val, std::vector<std::string> &tan) {
         const RootProg &rp = P.roots[r];
-        slot_val.assign(std::max(rp.n_slots, 1) + 1, "");
-        slot_tan.assign(slot_val.size(), std::vector<std::string>());
-        slot_prod.assign(slot_val.size(), -1);
-        slot_nn.assign(slot_val.size(), 0);
+        reset_slots();
         for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) instr(pc, decl, body);
         const int rs = rp.result_slot;
         val = slot_val.at(rs);
@@ -244,12 +264,81 @@ class PassWriter {
     // otherwise, contributions to variables accumulated into G[i] in sweep
     // order (the interpreter's reverse_sweep, with records read from the
     // value pass's variables).
-    void reverse(std::vector<std::string> &decl, std::vector<std::string> &body) {
+    void reverse(Decls &decl, std::vector<std::string> &body) {
         const RootProg &rp = P.roots[r];
-        for (int pc = rp.begin; pc < rp.begin + rp.len; ++pc) decl.push_back("Iv y" + std::to_string(pc) + ";");
         body.push_back("y" + std::to_string(slot_prod.at(rp.result_slot)) + " = kOne;");
-        for (auto it = steps.rbegin(); it != steps.rend(); ++it) {
-            const Step &st = *it;
+        sweep(decl, body, rp.begin, rp.begin + rp.len);
+    }
+
+    // Value pass and reverse sweep with checkpointed recomputation.  The
+    // program is cut into segments [start[j], start[j+1]).  A value-only pass
+    // runs segments 0 .. K-2 and stores at each boundary start[j] (j >= 1)
+    // the values produced before it that segment j reads (in[j], to the
+    // checkpoint buffer at ck_base[j] ...).  Segment K-1 then runs with its
+    // local partials and is swept at once; every earlier segment, last first,
+    // reloads its inputs, runs again with its partials and is swept.  The
+    // adjoints of values that cross a boundary stay in variables.  The
+    // recomputation repeats the same operations on the same operands, so the
+    // result is bitwise that of reverse() after a single value pass; domain
+    // tests are made once, in the first pass.  Writes the NIE value to nie.
+    void adjoint(Decls &decl, std::vector<std::string> &body, const std::vector<int> &start,
+                 const std::vector<std::vector<int>> &in, const std::vector<int> &ck_base) {
+        const RootProg &rp = P.roots[r];
+        const int K = (int)start.size() - 1;
+        reset_slots();
+        std::vector<Snapshot> snap(K);
+        partials = false;
+        for (int j = 0; j + 1 < K; ++j) {
+            if (j >= 1) {
+                body.push_back(BLOCK_BREAK);
+                std::string st;
+                for (size_t e = 0; e < in[j].size(); ++e)
+                    st += "spec_ck_st(L, " + std::to_string(ck_base[j] + (int)e) + ", v" + std::to_string(in[j][e]) +
+                          "); ";
+                body.push_back(st);
+            }
+            snap[j] = save();
+            for (int pc = rp.begin + start[j]; pc < rp.begin + start[j + 1]; ++pc) instr(pc, decl, body);
+        }
+        partials = true;
+        for (int pc = rp.begin + start[K - 1]; pc < rp.begin + start[K]; ++pc) instr(pc, decl, body);
+        decl.push_back("Iv nie;");
+        body.push_back("nie = " + slot_val.at(rp.result_slot) + ";");
+        body.push_back(zero_gradient());
+        body.push_back("y" + std::to_string(slot_prod.at(rp.result_slot)) + " = kOne;");
+        sweep(decl, body, rp.begin + start[K - 1], rp.begin + start[K]);
+        checks = false;
+        for (int j = K - 2; j >= 0; --j) {
+            restore(snap[j]);
+            body.push_back(BLOCK_BREAK);
+            if (j >= 1) {
+                std::string ld;
+                for (size_t e = 0; e < in[j].size(); ++e)
+                    ld += "v" + std::to_string(in[j][e]) + " = spec_ck_ld(L, " + std::to_string(ck_base[j] + (int)e) +
+                          "); ";
+                body.push_back(ld);
+            }
+            for (int pc = rp.begin + start[j]; pc < rp.begin + start[j + 1]; ++pc) instr(pc, decl, body);
+            sweep(decl, body, rp.begin + start[j], rp.begin + start[j + 1]);
+        }
+        checks = true;
+    }
+
+    std::string zero_gradient() const {
+        std::string s;
+        for (int i = 0; i < P.n_vars; ++i) s += "G[" + std::to_string(i) + "] = kZero; ";
+        return s;
+    }
+
+  private:
+    // sweep instructions [lo, hi) in reverse order (their steps recorded by
+    // the last pass with partials over them)
+    void sweep(Decls &decl, std::vector<std::string> &body, int lo, int hi) {
+        for (int pc = lo; pc < hi; ++pc) decl.push_back("Iv y" + std::to_string(pc) + ";");
+        for (int pcs = hi - 1; pcs >= lo; --pcs) {
+            const auto it = steps.find(pcs);
+            if (it == steps.end()) continue;
+            const Step &st = it->second;
             const Dec &I = st.I;
             const std::string pc = std::to_string(st.pc), zb = "y" + pc;
             const bool ia = (I.w0 & W0_INIT_A) != 0, ib = (I.w0 & W0_INIT_B) != 0;
@@ -322,10 +411,11 @@ class PassWriter {
         }
     }
 
-  private:
     const Compiled &P;
     int r, C, c0;
-    bool point, tape;
+    bool point;
+    bool partials;                               // compute the local partials (and record the steps)
+    bool checks = true;                          // emit the domain tests
     std::vector<std::string> slot_val;
     std::vector<std::vector<std::string>> slot_tan;
     std::vector<int> slot_prod;                  // instruction that wrote the slot's current value
@@ -337,7 +427,27 @@ class PassWriter {
         int pa, pb;                              // producers of slot operands
         bool nu, nv, nz;                         // operands and result known nonnegative
     };
-    std::vector<Step> steps;
+    std::map<int, Step> steps;                   // by instruction, from the last pass with partials
+    struct Snapshot {
+        std::vector<std::string> val;
+        std::vector<int> prod;
+        std::vector<char> nn;
+    };
+
+    void reset_slots() {
+        const RootProg &rp = P.roots[r];
+        slot_val.assign(std::max(rp.n_slots, 1) + 1, "");
+        slot_tan.assign(slot_val.size(), std::vector<std::string>());
+        slot_prod.assign(slot_val.size(), -1);
+        slot_nn.assign(slot_val.size(), 0);
+    }
+    Snapshot save() const { return Snapshot{slot_val, slot_prod, slot_nn}; }
+    void restore(const Snapshot &S) {
+        slot_val = S.val;
+        slot_prod = S.prod;
+        slot_nn = S.nn;
+        slot_tan.assign(slot_val.size(), std::vector<std::string>());
+    }
 
     void ensure(size_t s) {
         if (s >= slot_val.size()) {
@@ -406,7 +516,7 @@ class PassWriter {
         }
     }
 
-    void instr(int pc, std::vector<std::string> &decl, std::vector<std::string> &body) {
+    void instr(int pc, Decls &decl, std::vector<std::string> &body) {
         const Dec I = decode(P.instr[pc]);
         std::string U, V;
         std::vector<std::string> A, B;
@@ -416,11 +526,11 @@ class PassWriter {
         if (I.op <= I_DIV) fetch(I.bk, I.b, I.k, V, B, bd, hb);
         const bool nu = nonneg(I.ak, I.a, I.k), nv = I.op <= I_DIV && nonneg(I.bk, I.b, I.k);
         const bool nz = nonneg_result(I, nu, nv);
-        if (tape) {
+        if (partials) {
             Step st{pc, I, U, V, "", I.ak == K_SLOT ? slot_prod.at(I.a) : -1,
                     I.op <= I_DIV && I.bk == K_SLOT ? slot_prod.at(I.b) : -1, nu, nv, nz};
             if (I.op == I_DIVK || I.op == I_DIVKN) st.aux = aux_literal(P.instr.at(I.b));
-            steps.push_back(st);
+            steps[pc] = st;
         }
         const std::string z = "v" + std::to_string(pc);
         std::string s;                                   // the statements of this instruction
@@ -454,9 +564,10 @@ class PassWriter {
         case I_DIV: {
             const std::string tv = "b" + std::to_string(pc);
             decl.push_back("Iv " + tv + ";");
-            s += tv + " = " + V + "; bad |= (" + tv + ".lo <= 0.0 && " + tv + ".nh <= 0.0) ? 1u : 0u; ";
+            s += tv + " = " + V + "; ";
+            if (checks) s += "bad |= (" + tv + ".lo <= 0.0 && " + tv + ".nh <= 0.0) ? 1u : 0u; ";
             s += z + " = " + (nv ? "idiv_pos(" : "idiv(") + U + ", " + tv + ");";
-            if (C > 0 || tape) {
+            if (C > 0 || partials) {
                 const std::string R = "r" + std::to_string(pc);
                 decl.push_back("Iv " + R + ";");
                 s += " " + R + " = " + (nv ? "irecip_pos(" : "irecip(") + tv + ");";
@@ -487,13 +598,15 @@ class PassWriter {
                 s += z + " = " + (point && I.ak == K_VAR ? "isqr_deg(" : "isqr(") + tu + ");";
                 dexpr = "itwice(" + tu + ")";
             } else if (I.op == I_SQRT) {
-                s += "bad |= " + tu + ".lo < 0.0 ? 1u : 0u; " + z + " = isqrt(" + tu + ");";
+                if (checks) s += "bad |= " + tu + ".lo < 0.0 ? 1u : 0u; ";
+                s += z + " = isqrt(" + tu + ");";
                 dexpr = "isqrt_deriv(" + z + ")";
             } else if (I.op == I_EXP) {
                 s += z + " = iexp(" + tu + ");";
                 dexpr = z;
             } else if (I.op == I_LOG) {
-                s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; " + z + " = ilog(" + tu + ");";
+                if (checks) s += "bad |= " + tu + ".lo <= 0.0 ? 1u : 0u; ";
+                s += z + " = ilog(" + tu + ");";
                 dexpr = "irecip_pos(" + tu + ")";         // u > 0 wherever the bounds are kept
             } else if (I.op == I_TANH) {
                 s += z + " = itanh(" + tu + ");";
@@ -505,7 +618,7 @@ class PassWriter {
                 s += z + " = icos(" + tu + ");";
                 dexpr = "icos_deriv(" + tu + ")";
             }
-            if (C > 0 || tape) {
+            if (C > 0 || partials) {
                 decl.push_back("Iv " + D + ";");
                 s += " " + D + " = " + dexpr + ";";
             }
@@ -575,41 +688,140 @@ class PassWriter {
 };
 
 void write_guarded(std::string &out, const std::vector<std::string> &body) {
-    for (size_t i = 0; i < body.size(); i += SEGMENT) {
-        out += "    if (go) {\n";
-        for (size_t j = i; j < std::min(body.size(), i + SEGMENT); ++j) out += "        " + body[j] + "\n";
-        out += "    }\n";
+    size_t in_block = 0;
+    for (const auto &line : body) {
+        if (line == BLOCK_BREAK) {
+            if (in_block) out += "    }\n";
+            in_block = 0;
+            continue;
+        }
+        if (in_block == 0) out += "    if (go) {\n";
+        out += "        " + line + "\n";
+        if (++in_block == (size_t)SEGMENT) {
+            out += "    }\n";
+            in_block = 0;
+        }
     }
+    if (in_block) out += "    }\n";
 }
 
-// the value pass with its local partials and the reverse sweep of one root:
-// returns the NIE value, G[0..n) receives the interval gradient
-void write_adjoint(std::string &out, const Compiled &P, int r, const std::string &name) {
-    std::vector<std::string> decl, fwd, rev, tan;
-    std::string val;
+// Segments of one root program for the checkpointed adjoint: start[j] are
+// program-relative boundaries (start[0] = 0, start[K] = len); in[j] are the
+// instructions (absolute) whose values segment j reads from before it, which
+// the value pass stores at start[j] for j = 1 .. K-2 at checkpoint indices
+// ck_base[j] ...; ck_count intervals per lane in all.
+struct SegPlan {
+    std::vector<int> start;
+    std::vector<std::vector<int>> in;
+    std::vector<int> ck_base;
+    int ck_count = 0;
+};
+
+// Greedy cut: a segment grows while its inputs from earlier segments plus the
+// values and local partials it computes (an estimate of what its
+// recomputation and sweep keep in registers) stay within budget intervals.
+// budget <= 0: one segment (no recomputation).
+SegPlan plan_segments(const Compiled &P, int r, int budget) {
+    const RootProg &rp = P.roots[r];
+    const int len = rp.len;
+    std::vector<int> pa(len, -1), pb(len, -1), cost(len, 1);
+    std::vector<int> prod(std::max(rp.n_slots, 1) + 1, -1);
+    for (int i = 0; i < len; ++i) {
+        const Dec I = decode(P.instr[rp.begin + i]);
+        if (I.ak == K_SLOT && I.a < prod.size()) pa[i] = prod[I.a];
+        if (I.op <= I_DIV && I.bk == K_SLOT && I.b < prod.size()) pb[i] = prod[I.b];
+        if (I.op == I_DIV || (is_unary_fn(I.op) && I.op != I_EXP)) cost[i] = 2;     // 1/V, or the derivative
+        if (I.d >= prod.size()) prod.resize(I.d + 1, -1);
+        prod[I.d] = rp.begin + i;
+    }
+    SegPlan S;
+    S.start.push_back(0);
+    if (budget <= 0) {
+        S.start.push_back(len);
+    } else {
+        for (int s = 0; s < len;) {
+            std::vector<int> inset;
+            int c = 0, e = s;
+            for (; e < len; ++e) {
+                int add = 0;
+                for (int p : {pa[e], pb[e]})
+                    if (p >= 0 && p < rp.begin + s && std::find(inset.begin(), inset.end(), p) == inset.end()) ++add;
+                if (pa[e] >= 0 && pa[e] == pb[e] && pa[e] < rp.begin + s &&
+                    std::find(inset.begin(), inset.end(), pa[e]) == inset.end())
+                    --add;                                       // the same value twice
+                if (e > s && c + cost[e] + (int)inset.size() + add > budget) break;
+                for (int p : {pa[e], pb[e]})
+                    if (p >= 0 && p < rp.begin + s && std::find(inset.begin(), inset.end(), p) == inset.end())
+                        inset.push_back(p);
+                c += cost[e];
+            }
+            S.start.push_back(e);
+            s = e;
+        }
+    }
+    const int K = (int)S.start.size() - 1;
+    S.in.assign(K, {});
+    S.ck_base.assign(K, 0);
+    for (int j = 0; j < K; ++j) {
+        auto &v = S.in[j];
+        for (int i = S.start[j]; i < S.start[j + 1]; ++i)
+            for (int p : {pa[i], pb[i]})
+                if (p >= 0 && p < rp.begin + S.start[j]) v.push_back(p);
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        if (j >= 1 && j + 1 < K) {
+            S.ck_base[j] = S.ck_count;
+            S.ck_count += (int)v.size();
+        }
+    }
+    return S;
+}
+
+// The value pass with its local partials and the reverse sweep of one root
+// (checkpointed when the plan has several segments): returns the NIE value,
+// G[0..n) receives the interval gradient.  Returns the checkpoint intervals
+// per lane the function uses.
+int write_adjoint(std::string &out, const Compiled &P, int r, const std::string &name, int budget,
+                  int64_t *units) {
+    Decls decl;
+    std::vector<std::string> body;
     PassWriter w(P, r, 0, 0, false, true);
-    w.emit(decl, fwd, val, tan);
-    w.reverse(decl, rev);
+    const SegPlan S = plan_segments(P, r, budget);
+    std::string ret;
+    if (S.start.size() <= 2) {
+        std::vector<std::string> tan;
+        w.emit(decl, body, ret, tan);
+        body.push_back(w.zero_gradient());
+        w.reverse(decl, body);
+    } else {
+        w.adjoint(decl, body, S.start, S.in, S.ck_base);
+        ret = "nie";
+    }
     out += "__device__ __forceinline__ Iv " + name + "(const SpecLane &L, bool go, uint32_t &bad, Iv (&G)[" +
            std::to_string(P.n_vars) + "]) {\n";
-    for (const auto &d : decl) out += "    " + d + "\n";
-    write_guarded(out, fwd);
-    for (int i = 0; i < P.n_vars; ++i) out += "    G[" + std::to_string(i) + "] = kZero;\n";
-    write_guarded(out, rev);
-    out += "    return " + val + ";\n}\n";
+    out += "    // " + std::to_string(S.start.size() - 1) + " segment(s), " + std::to_string(S.ck_count) +
+           " checkpoint intervals\n";
+    for (const auto &d : decl.v) out += "    " + d + "\n";
+    write_guarded(out, body);
+    out += "    return " + ret + ";\n}\n";
+    // instruction-passes: value pass and sweep, plus the recomputation of every segment but the last
+    const int len = P.roots[r].len, K = (int)S.start.size() - 1;
+    *units += 2 * (int64_t)len + (K > 1 ? S.start[K - 1] : 0);
+    return S.ck_count;
 }
 
 // a pass as a function: C == 0 returns the value; C > 0 also writes G[0..C).
 // Returns which components of the root's gradient are structurally zero.
 std::vector<bool> write_pass(std::string &out, const Compiled &P, int r, int C, int c0, bool point,
                              const std::string &name) {
-    std::vector<std::string> decl, body, tan;
+    Decls decl;
+    std::vector<std::string> body, tan;
     std::string val;
     PassWriter(P, r, C, c0, point).emit(decl, body, val, tan);
     out += "__device__ __forceinline__ Iv " + name + "(const SpecLane &L, bool go, uint32_t &bad";
     if (C > 0) out += ", Iv (&G)[" + std::to_string(C) + "]";
     out += ") {\n";
-    for (const auto &d : decl) out += "    " + d + "\n";
+    for (const auto &d : decl.v) out += "    " + d + "\n";
     write_guarded(out, body);
     std::vector<bool> zero(C);
     for (int t = 0; t < C; ++t) {
@@ -686,9 +898,13 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     int c = opt && opt->chunk > 0 ? opt->chunk : 0;
     if (c == 0) c = fwd ? default_chunk(P) : 1;
     if (c < 1 || c > n) return set_error(MVF_EINVAL, "chunk out of range [1, n]");
+    if (opt && opt->ckpt_budget > MAX_CKPT_BUDGET)
+        return set_error(MVF_EINVAL, "ckpt_budget above " + std::to_string(MAX_CKPT_BUDGET) + " intervals");
     const int passes = (n + c - 1) / c;
-    int64_t u = 0;     // point and value passes, tangent passes, the adjoint's value pass and sweep
-    for (const auto &rp : P.roots) u += (int64_t)rp.len * (2 + (fwd ? passes : 0) + (rev ? 2 : 0));
+    // point and value passes, tangent passes, the adjoint's value pass, its
+    // recomputation and its sweep (at most three passes over the program)
+    int64_t u = 0;
+    for (const auto &rp : P.roots) u += (int64_t)rp.len * (2 + (fwd ? passes : 0) + (rev ? 3 : 0));
     const int64_t cap = opt && opt->max_code > 0 ? opt->max_code : DEFAULT_MAX_CODE;
     *chunk = c;
     *units = u;
@@ -698,7 +914,28 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     return MVF_OK;
 }
 
-std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
+int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves) {
+    if (opt && opt->ckpt_budget != 0) return opt->ckpt_budget;
+    // the register file in intervals (four VGPRs each, AGPRs included at one
+    // wave per SIMD), less the gradient, about half the live set (adjoints
+    // that cross a boundary) and working registers, within the range measured
+    // to pay off (and to be exact, see MAX_CKPT_BUDGET)
+    const int regs = 128 / std::max(1, waves);
+    return std::min(32, std::max(12, regs - P.n_vars - P.max_slots / 2 - 8));
+}
+
+int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int waves) {
+    // The library's choice segments every root of a tape whose largest root
+    // keeps more partials in its single-pass adjoint than twice the register
+    // file holds (measured: mid, 114 partials, is faster in one pass; the batch
+    // workload, 239, faster with every root segmented), and none otherwise; an
+    // explicit budget segments every root.
+    if (opt && opt->ckpt_budget != 0) return 0;
+    return P.max_rec > 2 * 128 / std::max(1, waves) ? 0 : INT32_MAX;
+}
+
+std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int ckpt_budget, int min_records,
+                        int *ck_count, int64_t *units) {
     const int n = P.n_vars, m = (int)P.roots.size();
     const bool fwd = grad != MVF_GRAD_REV, rev = grad != MVF_GRAD_FWD;
     std::string s;
@@ -713,6 +950,9 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
     s += "template <bool REV>\n__device__ uint32_t lane(const SpecLane &L, int mode, bool go, const LaneOut &o, "
          "FeasTrack &F);\n";
     std::vector<std::vector<bool>> zero(m, std::vector<bool>(n));     // structurally zero gradient components
+    int ck = 0;
+    int64_t u = 0;                      // instruction-passes generated
+    for (const auto &rp : P.roots) u += 2 * (int64_t)rp.len + (fwd ? (int64_t)rp.len * ((n + chunk - 1) / chunk) : 0);
     for (int r = 0; r < m; ++r) {
         write_pass(s, P, r, 0, 0, true, "point_" + std::to_string(r));
         write_pass(s, P, r, 0, 0, false, "value_" + std::to_string(r));
@@ -722,7 +962,9 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
                                           "tangent_" + std::to_string(r) + "_" + std::to_string(c0));
                 for (size_t t = 0; t < z.size(); ++t) zero[r][c0 + t] = z[t];
             }
-        if (rev) write_adjoint(s, P, r, "adjoint_" + std::to_string(r));
+        if (rev)
+            ck = std::max(ck, write_adjoint(s, P, r, "adjoint_" + std::to_string(r),
+                                            P.roots[r].n_rec > min_records ? ckpt_budget : -1, &u));
     }
     if (rev) {
         // every root in turn, as the interpreter's bound_lane with the reverse-mode adjoint
@@ -745,6 +987,8 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad) {
         }
         s += "    return bad;\n}\n";
     }
+    if (ck_count) *ck_count = ck;
+    if (units) *units = u;
     if (!fwd) {
         s += "}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n#include \"mvf_spec_kernel.h\"\n";
         return s;
@@ -788,9 +1032,17 @@ uint64_t fnv1a(const std::string &s, uint64_t h = 1469598103934665603ull) {
     return h;
 }
 
+// $MVF_SPEC_CACHE, else _spec_cache/ beside the library itself (so a tree
+// that carries the library carries its compiled kernels too)
 std::string cache_dir() {
     const char *e = std::getenv("MVF_SPEC_CACHE");
     if (e && *e) return std::string(e) == "off" ? "" : std::string(e);
+    Dl_info di;
+    if (dladdr(reinterpret_cast<void *>(&cache_dir), &di) && di.dli_fname) {
+        std::string lib = di.dli_fname;
+        const size_t slash = lib.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/_spec_cache";
+    }
     const char *home = std::getenv("HOME");
     return home && *home ? std::string(home) + "/.cache/mvf_spec" : "";
 }

@@ -17,11 +17,24 @@ namespace mvf {
 namespace dev {
 
 // A lane's subdomain: the breakpoint table in LDS and, per variable, the
-// index of the lane's table entry {lo, -hi, c, -c}.
+// index of the lane's table entry {lo, -hi, c, -c}; the lane's checkpoint
+// buffer of the adjoint ([index][lane], coalesced).
 struct SpecLane {
     const double4 *tab;
     int vi[MVF_MAX_VARS];
+    double2 *ck;
+    int64_t ck_stride;
 };
+
+// checkpoint entry i of the lane (stored at a segment boundary, reloaded
+// before the segment is recomputed)
+__device__ __forceinline__ void spec_ck_st(const SpecLane &L, int i, Iv v) {
+    L.ck[(int64_t)i * L.ck_stride] = make_double2(v.lo, v.nh);
+}
+__device__ __forceinline__ Iv spec_ck_ld(const SpecLane &L, int i) {
+    const double2 d = L.ck[(int64_t)i * L.ck_stride];
+    return Iv{d.x, d.y};
+}
 
 // variable i over the subdomain, [lo, hi]
 __device__ __forceinline__ Iv spec_x(const SpecLane &L, int i) {

@@ -12,9 +12,17 @@ namespace mvf {
 // program lengths times passes per root); MVF_ELIMIT above the size limit.
 int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_t *units);
 
+// Segment budget of the checkpointed adjoint (intervals; <= 0: one segment),
+// and the record count above which a root is segmented (INT32_MAX: none).
+int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves);
+int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int waves);
+
 // The generated device source (compiled with the embedded device headers):
 // forward kernels (grad FWD), reverse-mode kernels (REV) or both (AUTO).
-std::string spec_source(const Compiled &P, int chunk, int waves, int grad);
+// ck_count receives the checkpoint intervals per lane of the adjoint, units
+// the instruction-passes generated.
+std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int ckpt_budget, int min_records,
+                        int *ck_count, int64_t *units);
 
 // hiprtc compilation for `arch` (or the on-disk cache's copy).
 int spec_compile(const std::string &src, const std::string &arch, bool use_cache, std::vector<char> &code,

@@ -46,6 +46,8 @@ __device__ __forceinline__ void spec_bound_body() {
         const bool active = k < S;
         SpecLane L;
         L.tab = tab;
+        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * BLK + tid;
+        L.ck_stride = (int64_t)gridDim.x * BLK;
         int64_t q = active ? k : S - 1;
 #pragma unroll
         for (int i = 0; i < n; ++i) {            // dimension 0 fastest (Sec. 3.1.1)
@@ -149,6 +151,8 @@ __device__ __forceinline__ void spec_batch_body() {
             const bool active = k < S;
             SpecLane L;
             L.tab = tab;
+            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * BLK + tid;
+            L.ck_stride = (int64_t)gridDim.x * BLK;
             int64_t q = active ? k : S - 1;
 #pragma unroll
             for (int i = 0; i < n; ++i) {

@@ -84,13 +84,14 @@ class BoundArgs(ctypes.Structure):
 
 class SpecOptions(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("max_code", ctypes.c_int64),
-                ("use_cache", ctypes.c_int32), ("grad", ctypes.c_int32)]
+                ("use_cache", ctypes.c_int32), ("grad", ctypes.c_int32), ("ckpt_budget", ctypes.c_int32)]
 
 
 class SpecInfo(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int32), ("waves", ctypes.c_int32), ("grad", ctypes.c_int32),
                 ("code_units", ctypes.c_int64),
-                ("code_bytes", ctypes.c_int64), ("seconds", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+                ("code_bytes", ctypes.c_int64), ("seconds", ctypes.c_double), ("from_cache", ctypes.c_int32),
+                ("ckpt_budget", ctypes.c_int32), ("ckpt_intervals", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -106,7 +107,7 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
            "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check", "mvf_splits",
-           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace"]
+           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace", "mvf_spec_source"]
 
 
 def lib():
@@ -191,6 +192,9 @@ def lib():
             L.mvf_tape_specialize.argtypes = [P, ctypes.POINTER(SpecOptions), ctypes.POINTER(SpecInfo)]
             L.mvf_spec_check.restype = ctypes.c_int
             L.mvf_spec_check.argtypes = tape_args + [ctypes.POINTER(SpecOptions), ctypes.POINTER(SpecInfo)]
+            L.mvf_spec_source.restype = ctypes.c_int
+            L.mvf_spec_source.argtypes = tape_args + [ctypes.POINTER(SpecOptions), ctypes.c_char_p, ctypes.c_size_t,
+                                                      ctypes.POINTER(ctypes.c_size_t)]
             _lib = L
     return _lib
 
@@ -216,16 +220,34 @@ def check(tape) -> TapeStats:
     return st
 
 
-def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0, grad: str = "fwd") -> dict:
+def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0, grad: str = "fwd",
+               ckpt_budget: int = 0) -> dict:
     """Generate and compile the specialised kernels of a tape for gfx950 on the
     host (no device, no cache); returns the mvf_spec_info fields."""
     keep, args = _tape_arrays(tape)
     info = SpecInfo()
-    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0, MVF_GRAD[grad])),
+    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0, MVF_GRAD[grad],
+                                                              ckpt_budget)),
                               ctypes.byref(info))
     if rc != 0:
         raise MVFError(rc, "mvf_spec_check")
     return info.as_dict()
+
+
+def spec_source(tape, chunk: int = 0, waves: int = 0, max_code: int = 0, grad: str = "fwd",
+                ckpt_budget: int = 0) -> str:
+    """The generated device source of a tape's specialised kernels (mvf_spec_source), not compiled."""
+    keep, args = _tape_arrays(tape)
+    opt = SpecOptions(chunk, waves, max_code, 0, MVF_GRAD[grad], ckpt_budget)
+    n = ctypes.c_size_t()
+    rc = lib().mvf_spec_source(*args, ctypes.byref(opt), None, 0, ctypes.byref(n))
+    if rc != 0:
+        raise MVFError(rc, "mvf_spec_source")
+    buf = ctypes.create_string_buffer(n.value + 1)
+    rc = lib().mvf_spec_source(*args, ctypes.byref(opt), buf, n.value + 1, ctypes.byref(n))
+    if rc != 0:
+        raise MVFError(rc, "mvf_spec_source")
+    return buf.value.decode()
 
 
 def _stream_ptr(stream):
@@ -258,11 +280,13 @@ class Tape:
         return self
 
     def specialize(self, chunk: int = 0, waves: int = 0, max_code: int = 0, cache: bool = True,
-                   grad: str = "fwd") -> dict:
-        """Build the tape's specialised kernels (mvf_tape_specialize); grad "fwd", "rev" or "auto" (both)."""
+                   grad: str = "fwd", ckpt_budget: int = 0) -> dict:
+        """Build the tape's specialised kernels (mvf_tape_specialize); grad "fwd", "rev" or "auto" (both);
+        ckpt_budget: segment budget of the checkpointed adjoint (0 library choice, < 0 none)."""
         info = SpecInfo()
         rc = lib().mvf_tape_specialize(self.handle,
-                                       ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache), MVF_GRAD[grad])),
+                                       ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache), MVF_GRAD[grad],
+                                                                ckpt_budget)),
                                        ctypes.byref(info))
         if rc != 0:
             raise MVFError(rc, "mvf_tape_specialize")
@@ -404,12 +428,25 @@ def fbbt(tape: Tape, boxes, ub: float = float("inf"), rounds: int = 1, stream=No
     return out, st[:N]
 
 
+def _require_device(where: str, **tensors):
+    """The batched entry points hand raw pointers to kernels: every array must be a
+    GPU tensor, all on one device (a host pointer would fault the GPU)."""
+    devs = set()
+    for name, x in tensors.items():
+        if not getattr(x, "is_cuda", False):
+            raise ValueError(f"{where}: {name} must be a GPU tensor (got {getattr(x, 'device', type(x))})")
+        devs.add(x.device)
+    if len(devs) > 1:
+        raise ValueError(f"{where}: {', '.join(tensors)} must be on one device (got {sorted(map(str, devs))})")
+
+
 class BatchCall:
     """Pre-marshalled batched bound of many nodes (device boxes [N, n, 2] f64, splits [N, n] i32)."""
 
     def __init__(self, tape: Tape, boxes, splits, mode: str = "both", grad: str = "rev",
                  tuning: Optional[Tuning] = None, max_subdomains: Optional[int] = None):
         import torch
+        _require_device("BatchCall", boxes=boxes, splits=splits)
         self.tape = tape
         self.boxes = boxes.contiguous()
         self.splits = splits.to(torch.int32).contiguous()
@@ -514,6 +551,7 @@ class BatchGraph:
 
 def autotune(tape: Tape, boxes, splits, mode: str = "both", stream=None) -> Tuning:
     import torch
+    _require_device("autotune", boxes=boxes, splits=splits)
     boxes = boxes.contiguous()
     splits = splits.to(torch.int32).contiguous()
     N = int(boxes.shape[0])

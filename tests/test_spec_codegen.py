@@ -153,7 +153,27 @@ def test_both_gradient_modes_compile_and_are_counted():
     t = _trig()
     st = mvf.check(t)
     for grad, extra in (("fwd", None), ("rev", 2), ("auto", None)):
-        info = mvf.spec_check(t, grad=grad)
+        info = mvf.spec_check(t, grad=grad, ckpt_budget=-1)
         passes = -(-t.n_vars // info["chunk"])
         want = st.n_instr * (2 + (passes if grad != "rev" else 0) + (2 if grad != "fwd" else 0))
         assert info["code_units"] == want and info["grad"] == {"fwd": 0, "rev": 1, "auto": 2}[grad]
+        assert info["ckpt_intervals"] == 0
+
+
+def test_checkpointed_adjoint_plan_and_size():
+    # a 150-op objective cut into segments: the adjoint recomputes all but the last segment
+    # (at most one extra pass), stores checkpoints only for segments 1 .. K-2, and a larger
+    # budget never needs more segments
+    t = I.random_small_tape(3, n=3, ops=150, n_con=1, con_ops=20, window=8)
+    st = mvf.check(t)
+    one = mvf.spec_check(t, grad="rev", ckpt_budget=-1)
+    assert one["code_units"] == 4 * st.n_instr and one["ckpt_intervals"] == 0
+    prev = None
+    for budget in (4, 8, 16, 32):
+        info = mvf.spec_check(t, grad="rev", ckpt_budget=budget)
+        assert info["ckpt_budget"] == budget
+        assert 4 * st.n_instr < info["code_units"] <= 5 * st.n_instr
+        assert info["ckpt_intervals"] > 0
+        if prev is not None:
+            assert info["code_units"] <= prev["code_units"] + st.n_instr
+        prev = info
