@@ -176,6 +176,28 @@ int mvf_bound_workspace(const mvf_tape *tape, const int32_t *splits, int32_t mod
  */
 int mvf_bound(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mvf_bound
+ * without a workspace.  The same kernels and the same bits as mvf_bound;
+ * args->workspace and args->workspace_bytes are ignored and the call's
+ * scratch (per-workgroup partial results; the adjoint's checkpoints or
+ * records) lives in a file-scope device array of MVF_NOALLOC_SCRATCH_BYTES
+ * that each GPU the library runs on holds until the process ends.  The
+ * caller still owns args->box, reduced, argmin, per_sub, flags and extra.
+ * Calls that need more scratch than the array holds return MVF_ELIMIT with
+ * the size they need (in practice: tangent mode and the NIE at any size, the
+ * adjoint only when its checkpoints or records are small).  Nothing is
+ * allocated, and no allocating library routine is called; the tape must
+ * belong to the current device (else MVF_EINVAL).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one device (two streams, or a call
+ * before the previous one's kernels have finished on another stream) race
+ * and must not be issued.  Nothing in the array needs clearing between
+ * calls: every kernel writes what it later reads.
+ */
+#define MVF_NOALLOC_SCRATCH_BYTES (8u << 20)
+int mvf_bound_noalloc(const mvf_tape *tape, const mvf_bound_args *args, hipStream_t stream);
+
 /* ---- specialised kernels ---------------------------------------------
  * The interpreter kernels evaluate the DAG node by node (the single-kernel
  * evaluation of Sec. 3.2), decoding every instruction at run time.

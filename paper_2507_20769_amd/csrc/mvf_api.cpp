@@ -191,7 +191,7 @@ struct SingleLayout {
     bool g_lds;
 };
 
-SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total) {
+SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total, size_t rec_lane) {
     const size_t m = t->C.roots.size();
     SingleLayout L;
     L.g_lds = grad_in_lds(t->C.n_bound, tab_total, t->C.n_vars, (int)m);
@@ -200,7 +200,7 @@ SingleLayout single_layout(const mvf_tape *t, int grid, bool rev, int tab_total)
     L.k = align_up(L.lo0 + (size_t)grid * 8);
     L.ext = align_up(L.k + (size_t)grid * 8);
     L.rec = align_up(L.ext + (size_t)grid * 16);
-    L.gacc = align_up(L.rec + (rev ? rec_per_lane(t) * grid * BLK * 16 : 0));
+    L.gacc = align_up(L.rec + (rev ? rec_lane * grid * BLK * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
 }
@@ -513,13 +513,18 @@ int mvf_bound_workspace(const mvf_tape *t, const int32_t *splits, int32_t mode, 
     int chunk;
     rc = resolve_grad(t, mode, grad, nullptr, &rev, &chunk);
     if (rc != MVF_OK) return rc;
-    *bytes = single_layout(t, single_grid(t, S, rev), rev, tt).total;
+    *bytes = single_layout(t, single_grid(t, S, rev), rev, tt, rec_per_lane(t)).total;
     return MVF_OK;
 }
 
-int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
+namespace {
+// mvf_bound with the workspace given as (ws, ws_bytes); engine_rec: size the
+// reverse-mode region for the kernel that runs (else for either, as
+// mvf_bound_workspace does)
+int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_bytes, bool engine_rec,
+               hipStream_t stream) {
     if (!t || !a) return set_err(MVF_EINVAL, "null argument");
-    if (!a->box || !a->reduced || !a->workspace) return set_err(MVF_EINVAL, "box, reduced and workspace are required");
+    if (!a->box || !a->reduced || !ws) return set_err(MVF_EINVAL, "box, reduced and workspace are required");
     if (a->mode < MVF_MODE_NIE || a->mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
     if (a->grad < MVF_GRAD_FWD || a->grad > MVF_GRAD_AUTO) return set_err(MVF_EINVAL, "bad grad");
     if (a->engine < MVF_ENGINE_AUTO || a->engine > MVF_ENGINE_SPEC) return set_err(MVF_EINVAL, "bad engine");
@@ -535,8 +540,12 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
         return set_err(MVF_EINVAL, "no specialised kernel for this gradient mode: see mvf_tape_specialize");
     const bool spec = t->spec_fn[rev] && a->engine != MVF_ENGINE_INTERP;
     const int grid = single_grid(t, S, rev);
-    const SingleLayout L = single_layout(t, grid, rev, tt);
-    if (a->workspace_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
+    const size_t rec_lane = engine_rec ? (size_t)(spec ? t->spec_ck : t->C.max_rec) : rec_per_lane(t);
+    const SingleLayout L = single_layout(t, grid, rev, tt, rec_lane);
+    if (ws_bytes < L.total)
+        return set_err(engine_rec ? MVF_ELIMIT : MVF_EINVAL,
+                       "workspace too small: the call needs " + std::to_string(L.total) + " bytes, " +
+                           std::to_string(ws_bytes) + " given");
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
     const size_t lds = spec ? spec_lds_bytes(tt, m)
                             : lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
@@ -556,7 +565,7 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     B.flags = a->flags;
     B.reduced = a->reduced;
     B.argmin = a->argmin;
-    uint8_t *w = static_cast<uint8_t *>(a->workspace);
+    uint8_t *w = static_cast<uint8_t *>(ws);
     B.partial = reinterpret_cast<double *>(w + L.partial);
     B.partial_lo0 = reinterpret_cast<double *>(w + L.lo0);
     B.partial_k = reinterpret_cast<int64_t *>(w + L.k);
@@ -577,6 +586,22 @@ int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
     hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
     if (e != hipSuccess) return hip_err(e, "launch_bound");
     return MVF_OK;
+}
+}  // namespace
+
+int mvf_bound(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
+    if (!a) return set_err(MVF_EINVAL, "null argument");
+    return bound_impl(t, a, a->workspace, a->workspace_bytes, false, stream);
+}
+
+int mvf_bound_noalloc(const mvf_tape *t, const mvf_bound_args *a, hipStream_t stream) {
+    if (!t || !a) return set_err(MVF_EINVAL, "null argument");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != t->device) return set_err(MVF_EINVAL, "the current device is not the tape's device");
+    void *scratch = nullptr;
+    HIP_TRY(noalloc_scratch(dev, &scratch));
+    return bound_impl(t, a, scratch, MVF_NOALLOC_SCRATCH_BYTES, true, stream);
 }
 
 int mvf_fbbt_workspace(const mvf_tape *t, int64_t n_boxes, size_t *bytes) {

@@ -23,6 +23,10 @@ hipError_t launch_batch(const TapeArgs &T, const BatchArgs &A, int chunk, bool r
 hipError_t launch_batch_plan(const BatchArgs &A, hipStream_t stream);
 hipError_t launch_batch_finish(const BatchArgs &A, int m, int max_nodes, hipStream_t stream);
 
+// This device's copy of the no-allocation entry point's scratch array
+// (MVF_NOALLOC_SCRATCH_BYTES), looked up once per device.
+hipError_t noalloc_scratch(int device, void **ptr);
+
 constexpr size_t LDS_BUDGET = 160 * 1024;
 
 // LDS bytes of a workgroup (programs, table, gradient accumulators when in

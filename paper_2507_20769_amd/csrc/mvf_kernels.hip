@@ -1337,4 +1337,34 @@ hipError_t launch_points(const PointsArgs &A, int op, int chunk, int grid, size_
     }
 }
 
+// ---------------------------------------------------------------------------
+// the no-allocation entry point's scratch: one file-scope device array per
+// device (each GPU the library runs on holds its own copy until the process
+// ends), shared by every call on that device
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[MVF_NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(int device, void **ptr) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void *addr[MAX_DEVICES] = {};
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        // the host-side name of the array is not a device address: look up this
+        // device's copy once, with the device current
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (cur != device) hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        addr[device] = a;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
+
 }  // namespace mvf

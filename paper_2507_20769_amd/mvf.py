@@ -107,7 +107,7 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
            "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check", "mvf_splits",
-           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace", "mvf_spec_source"]
+           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace", "mvf_spec_source", "mvf_bound_noalloc"]
 
 
 def lib():
@@ -144,6 +144,8 @@ def lib():
             L.mvf_bound_workspace.argtypes = [P, P, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
             L.mvf_bound.restype = ctypes.c_int
             L.mvf_bound.argtypes = [P, ctypes.POINTER(BoundArgs), P]
+            L.mvf_bound_noalloc.restype = ctypes.c_int
+            L.mvf_bound_noalloc.argtypes = [P, ctypes.POINTER(BoundArgs), P]
             i64 = ctypes.c_int64
             L.mvf_adaptive_splits.restype = i64
             L.mvf_adaptive_splits.argtypes = [i32, P, i64, P]
@@ -317,10 +319,13 @@ class BoundCall:
     so repeated launches only enqueue kernels)."""
 
     def __init__(self, tape: Tape, box, splits: Sequence[int], mode: str = "both", grad: str = "fwd",
-                 per_sub: bool = False, flags: bool = False, tuning: "Tuning | None" = None, engine: str = "auto"):
+                 per_sub: bool = False, flags: bool = False, tuning: "Tuning | None" = None, engine: str = "auto",
+                 noalloc: bool = False):
+        """noalloc: launch through mvf_bound_noalloc (no workspace; the library's device scratch)."""
         import torch
         self.tape = tape
         self.tuning = tuning
+        self.noalloc = noalloc
         dev = box.device
         assert box.dtype == torch.float64 and box.is_cuda and tuple(box.shape) == (tape.n_vars, 2)
         self.box = box.contiguous()
@@ -333,24 +338,29 @@ class BoundCall:
         self.extra = torch.empty(2, dtype=torch.float64, device=dev)
         self.per_sub = torch.empty((m, 2, self.S), dtype=torch.float64, device=dev) if per_sub else None
         self.flags = torch.empty(self.S, dtype=torch.int32, device=dev) if flags else None
-        ws = ctypes.c_size_t()
-        rc = lib().mvf_bound_workspace(tape.handle, self.splits.ctypes.data_as(ctypes.c_void_p), MVF_MODE[mode],
-                                       MVF_GRAD[grad], ctypes.byref(ws))
-        if rc != 0:
-            raise MVFError(rc, "mvf_bound_workspace")
-        self.workspace = torch.empty(max(int(ws.value), 8), dtype=torch.uint8, device=dev)
+        if noalloc:
+            self.workspace = None
+        else:
+            ws = ctypes.c_size_t()
+            rc = lib().mvf_bound_workspace(tape.handle, self.splits.ctypes.data_as(ctypes.c_void_p),
+                                           MVF_MODE[mode], MVF_GRAD[grad], ctypes.byref(ws))
+            if rc != 0:
+                raise MVFError(rc, "mvf_bound_workspace")
+            self.workspace = torch.empty(max(int(ws.value), 8), dtype=torch.uint8, device=dev)
         self.args = BoundArgs(self.box.data_ptr(), self.splits.ctypes.data, MVF_MODE[mode], MVF_GRAD[grad],
                               self.reduced.data_ptr(), self.argmin.data_ptr(),
                               self.per_sub.data_ptr() if per_sub else None,
                               self.flags.data_ptr() if flags else None,
-                              self.workspace.data_ptr(), self.workspace.numel(),
+                              self.workspace.data_ptr() if self.workspace is not None else None,
+                              self.workspace.numel() if self.workspace is not None else 0,
                               ctypes.addressof(tuning) if tuning is not None else None, self.extra.data_ptr(),
                               MVF_ENGINE[engine])
 
     def launch(self, stream=None):
-        rc = lib().mvf_bound(self.tape.handle, ctypes.byref(self.args), _stream_ptr(stream))
+        fn = lib().mvf_bound_noalloc if self.noalloc else lib().mvf_bound
+        rc = fn(self.tape.handle, ctypes.byref(self.args), _stream_ptr(stream))
         if rc != 0:
-            raise MVFError(rc, "mvf_bound")
+            raise MVFError(rc, "mvf_bound_noalloc" if self.noalloc else "mvf_bound")
         return self
 
 
