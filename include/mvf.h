@@ -225,7 +225,8 @@ int mvf_bound_noalloc(const mvf_tape *tape, const mvf_bound_args *args, hipStrea
  * the largest whose live values and nonzero components (estimated per pass)
  * stay within about 100 intervals.  Compilation takes seconds to a minute,
  * about linear in the generated size (code_units = sum over roots of program
- * length x passes, the adjoint counting two); MVF_ELIMIT above max_code.  With use_cache the code
+ * length x passes, the adjoint counting two, plus the recomputed segments of
+ * the checkpointed adjoint); MVF_ELIMIT above max_code.  With use_cache the code
  * object is kept under $MVF_SPEC_CACHE (default: _spec_cache/ in the directory
  * of libmvf.so itself; "off" disables) keyed by a hash of the source, options and compiler version;
  * $MVF_SPEC_DUMP names a file that receives a copy of the generated source.
@@ -234,8 +235,11 @@ int mvf_bound_noalloc(const mvf_tape *tape, const mvf_bound_args *args, hipStrea
 typedef struct {
     int32_t chunk;            /* tangent components per pass, 1..n; 0 = library choice */
     int32_t waves;            /* waves per SIMD the kernel is compiled for, 1..4; 0 = 2 */
-    int64_t max_code;         /* size limit in instruction-passes; 0 = default (6000) */
-    int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache */
+    int64_t max_code;         /* size limit in instruction-passes; 0 = default (32000) */
+    int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache
+                                 (mvf_spec_check: write it, for gfx950, so that a later
+                                 mvf_tape_specialize of the same tape and options on any
+                                 gfx950 finds the code object) */
     int32_t grad;             /* kernels to build: MVF_GRAD_FWD (tangent mode), MVF_GRAD_REV
                                  (reverse-mode adjoint) or MVF_GRAD_AUTO (both) */
     int32_t ckpt_budget;      /* reverse mode: register budget of one recomputed segment, in
@@ -302,8 +306,11 @@ typedef struct mvf_tuning {
     float best_ms;            /* written by mvf_autotune: time of the chosen configuration */
     int32_t sub_per_lane;     /* batched launches: subdomains per lane of a work item (a work item is
                                  256 * sub_per_lane subdomains of one node), 1..16; 0: 1 */
-    int32_t engine;           /* batched forward launches: MVF_ENGINE_* (the specialised kernel needs
-                                 mvf_tape_specialize; reverse mode always interprets) */
+    int32_t engine;           /* batched launches: MVF_ENGINE_* (AUTO: the tape's specialised kernel
+                                 for the gradient mode when mvf_tape_specialize built it, else the
+                                 interpreter; SPEC needs it) */
+    int32_t block;            /* workgroup lanes of the specialised batched kernel: 64, 128 or 256;
+                                 0: 256 (the interpreter's workgroup is always 256) */
 } mvf_tuning;
 
 /*
@@ -386,16 +393,25 @@ int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int
 int mvf_batch_graph_destroy(mvf_batch_graph *g);
 
 /*
- * Autotuner (the batched form's launch configuration): times the batched
- * launch on the given nodes (device arrays) for each gradient mode and
- * kernel (interpreter with each tangent chunk, the specialised kernel when
- * the tape has one, the reverse-mode adjoint), persistent grid size (1, 2, 4
- * workgroups per CU) and subdomains per lane (1, 2, 4), and returns the
- * fastest.  The workgroup is fixed at 256 lanes (four waves).  Allocates
- * temporary device memory.
+ * Autotuner (the batched form's launch configuration; adaptive partitioning
+ * matches the subdomain count to the cores, Sec. 3.1.2, and this matches the
+ * launch to the machine): times the batched launch on the given sample nodes
+ * (device arrays; n_subdomains = their total) for each kernel of the call's
+ * gradient mode -- the interpreter (forward mode: each tangent chunk) and the
+ * specialised kernel when the tape has one, the latter at workgroups of 64,
+ * 128 and 256 lanes -- times the persistent grid (one, two or four 256-lane
+ * workgroups' worth per CU) times subdomains per lane (1, 2, 4), and returns
+ * the fastest (best_ms its time per launch).  grad is the caller's: the
+ * tuner never changes the gradient mode, which decides the enclosures and so
+ * the bounds (AUTO resolves as in mvf_bound, by the reference op count, not
+ * by timing).  Results are cached per process by (tape programs and root
+ * kinds, device, specialised module, sample size in nodes and subdomains,
+ * mode, gradient mode): a repeated call returns the cached tuning at once.
+ * Allocates temporary device memory.  Split counts are tuned separately
+ * (mvf_autotune_splits).
  */
 int mvf_autotune(const mvf_tape *tape, int32_t n_nodes, const double *boxes, const int32_t *splits,
-                 int64_t n_subdomains, int32_t mode, mvf_tuning *out, hipStream_t stream);
+                 int64_t n_subdomains, int32_t mode, int32_t grad, mvf_tuning *out, hipStream_t stream);
 
 /* ---- points and boxes (differentiation) -------------------------------
  * One lane per point or box, evaluated with the same register programs and

@@ -3,10 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -32,6 +36,7 @@ struct mvf_tape {
     hipFunction_t spec_batch_fn[2] = {nullptr, nullptr};  // batched
     mvf_spec_info spec_info{};
     int32_t spec_ck = 0;                    // checkpoint intervals per lane of the specialised adjoint
+    uint64_t spec_id = 0;                   // which specialisation (0: none), for the autotuner's cache
 };
 
 struct mvf_batch_graph {
@@ -162,9 +167,11 @@ int single_grid(const mvf_tape *t, int64_t S, bool rev) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
 }
 
+int batch_block(const mvf_tuning *tu) { return tu && tu->block > 0 ? tu->block : BLK; }
+
 int batch_grid(const mvf_tape *t, const mvf_tuning *tu) {
     if (tu && tu->grid_blocks > 0) return tu->grid_blocks;
-    return 2 * t->n_cu;
+    return 2 * t->n_cu * (BLK / batch_block(tu));      // two 256-lane workgroups' worth per CU
 }
 
 int batch_spl(const mvf_tuning *tu) { return tu && tu->sub_per_lane > 0 ? tu->sub_per_lane : 1; }
@@ -174,9 +181,12 @@ int batch_engine(const mvf_tape *t, const mvf_tuning *tu, bool rev, bool *spec) 
     const int e = tu ? tu->engine : MVF_ENGINE_AUTO;
     if (e < MVF_ENGINE_AUTO || e > MVF_ENGINE_SPEC) return set_err(MVF_EINVAL, "bad engine");
     if (tu && (tu->sub_per_lane < 0 || tu->sub_per_lane > 16)) return set_err(MVF_EINVAL, "sub_per_lane outside [0, 16]");
+    if (tu && tu->block != 0 && tu->block != 64 && tu->block != 128 && tu->block != BLK)
+        return set_err(MVF_EINVAL, "block must be 64, 128 or 256");
     if (e == MVF_ENGINE_SPEC && !t->spec_batch_fn[rev])
         return set_err(MVF_EINVAL, "no specialised kernel for this gradient mode: see mvf_tape_specialize");
     *spec = t->spec_batch_fn[rev] && e != MVF_ENGINE_INTERP;
+    if (!*spec && batch_block(tu) != BLK) return set_err(MVF_EINVAL, "the interpreter's workgroup is 256 lanes");
     return MVF_OK;
 }
 
@@ -210,7 +220,8 @@ struct BatchLayout {
     bool g_lds;
 };
 
-BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int grid, bool rev) {
+// grid x block lanes run (the interpreter's block is always 256)
+BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int grid, int block, bool rev) {
     const size_t m = t->C.roots.size();
     const size_t items = (size_t)(max_sub / BLK) + (size_t)max_nodes + 1;
     BatchLayout L;
@@ -223,7 +234,7 @@ BatchLayout batch_layout(const mvf_tape *t, int max_nodes, int64_t max_sub, int 
     L.ext = align_up(L.k + items * 8);
     L.rec = align_up(L.ext + items * 16);
     L.g_lds = grad_in_lds(t->C.n_bound, BATCH_TAB_CAP, t->C.n_vars, (int)m);
-    L.gacc = align_up(L.rec + (rev ? rec_per_lane(t) * grid * BLK * 16 : 0));
+    L.gacc = align_up(L.rec + (rev ? rec_per_lane(t) * grid * block * 16 : 0));
     L.total = L.gacc + (rev && !L.g_lds ? (size_t)t->C.n_vars * grid * BLK * 16 : 0);
     return L;
 }
@@ -308,8 +319,9 @@ int check_splits(const mvf_tape *t, const int32_t *splits, int64_t *S, int *tab_
 
 int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_dev, int max_nodes, int64_t max_sub,
                     const double *boxes, const int32_t *splits, double *reduced, int64_t *argmin, int32_t *status,
-                    double *extra, void *ws, size_t ws_bytes, int grid, bool rev, int spl, BatchArgs *A) {
-    const BatchLayout L = batch_layout(t, max_nodes, max_sub, grid, rev);
+                    double *extra, void *ws, size_t ws_bytes, int grid, int block, bool rev, int spl,
+                    BatchArgs *A) {
+    const BatchLayout L = batch_layout(t, max_nodes, max_sub, grid, block, rev);
     if (ws_bytes < L.total) return set_err(MVF_EINVAL, "workspace too small");
     uint8_t *w = static_cast<uint8_t *>(ws);
     std::memset(A, 0, sizeof *A);
@@ -339,14 +351,14 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
 
 // plan -> persistent bounding kernel (specialised or interpreter) -> per-node finish
 int launch_batched(const mvf_tape *t, int mode, int chunk, bool rev, bool spec, const BatchArgs &A, int grid,
-                   int max_nodes, hipStream_t stream) {
+                   int block, int max_nodes, hipStream_t stream) {
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
     if (spec) {
         const size_t lds = spec_lds_bytes(BATCH_TAB_CAP, m);
         HIP_TRY(launch_batch_plan(A, stream));
         BatchKArgs K{tape_args(t, mode, 0), A};
         void *params[] = {&K};
-        HIP_TRY(hipModuleLaunchKernel(t->spec_batch_fn[rev], grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params,
+        HIP_TRY(hipModuleLaunchKernel(t->spec_batch_fn[rev], grid, 1, 1, block, 1, 1, (unsigned)lds, stream, params,
                                       nullptr));
         HIP_TRY(launch_batch_finish(A, m, max_nodes, stream));
         return MVF_OK;
@@ -684,6 +696,10 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     t->spec_mod = mod;
     t->spec_ck = grad == MVF_GRAD_FWD ? 0 : ck;
+    {
+        static std::atomic<uint64_t> serial{0};
+        t->spec_id = ++serial;
+    }
     for (int r = 0; r < 2; ++r) {
         t->spec_fn[r] = fns[r][0];
         t->spec_batch_fn[r] = fns[r][1];
@@ -740,9 +756,10 @@ int mvf_spec_check(const mvf_node *nodes, int32_t n_nodes, const double *consts,
     if (rc != MVF_OK) return rc;
     std::vector<char> code;
     bool cached = false;
-    rc = spec_compile(src, "gfx950", false, code, &cached, &in.seconds);
+    rc = spec_compile(src, "gfx950", opt && opt->use_cache, code, &cached, &in.seconds);
     if (rc != MVF_OK) return rc;
     in.code_bytes = (int64_t)code.size();
+    in.from_cache = cached ? 1 : 0;
     if (info) *info = in;
     return MVF_OK;
 }
@@ -771,7 +788,7 @@ int mvf_batch_workspace(const mvf_tape *t, int32_t max_nodes, int64_t max_subdom
     int chunk;
     int rc = resolve_grad(t, mode, grad, tuning, &rev, &chunk);
     if (rc != MVF_OK) return rc;
-    *bytes = batch_layout(t, max_nodes, max_subdomains, batch_grid(t, tuning), rev).total;
+    *bytes = batch_layout(t, max_nodes, max_subdomains, batch_grid(t, tuning), batch_block(tuning), rev).total;
     return MVF_OK;
 }
 
@@ -790,11 +807,11 @@ int mvf_bound_batch(const mvf_tape *t, const mvf_batch_args *a, const mvf_tuning
     const int grid = batch_grid(t, tuning);
     BatchArgs A;
     rc = fill_batch_args(t, a->n_nodes, nullptr, a->max_nodes, a->max_subdomains, a->boxes, a->splits, a->reduced,
-                         a->argmin, a->status, a->extra, a->workspace, a->workspace_bytes, grid, rev, batch_spl(tuning),
-                         &A);
+                         a->argmin, a->status, a->extra, a->workspace, a->workspace_bytes, grid, batch_block(tuning),
+                         rev, batch_spl(tuning), &A);
     if (rc != MVF_OK) return rc;
     if (a->n_nodes == 0) return MVF_OK;
-    return launch_batched(t, a->mode, chunk, rev, spec, A, grid, a->n_nodes, stream);
+    return launch_batched(t, a->mode, chunk, rev, spec, A, grid, batch_block(tuning), a->n_nodes, stream);
 }
 
 int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_subdomains, int32_t mode, int32_t grad,
@@ -820,9 +837,10 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     g->tuning.grid_blocks = batch_grid(t, tuning);
     g->tuning.sub_per_lane = batch_spl(tuning);
     g->tuning.engine = spec ? MVF_ENGINE_SPEC : MVF_ENGINE_INTERP;
+    g->tuning.block = batch_block(tuning);
     const int n = t->C.n_vars, m = (int)t->C.roots.size();
     const int grid = g->tuning.grid_blocks;
-    g->ws_bytes = batch_layout(t, max_nodes, max_subdomains, grid, rev).total;
+    g->ws_bytes = batch_layout(t, max_nodes, max_subdomains, grid, g->tuning.block, rev).total;
     auto fail = [&](int code, const char *what) {
         mvf_batch_graph_destroy(g);
         return set_err(code, what);
@@ -855,8 +873,8 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
 
     BatchArgs A;
     rc = fill_batch_args(t, 0, g->d_count, max_nodes, max_subdomains, g->d_boxes, g->d_splits, g->d_reduced,
-                         g->d_argmin, g->d_status, g->d_extra, g->d_ws, g->ws_bytes, grid, rev, g->tuning.sub_per_lane,
-                         &A);
+                         g->d_argmin, g->d_status, g->d_extra, g->d_ws, g->ws_bytes, grid, g->tuning.block, rev,
+                         g->tuning.sub_per_lane, &A);
     if (rc != MVF_OK) { mvf_batch_graph_destroy(g); return rc; }
     if (!spec && lds_bytes(t->C.n_bound, BATCH_TAB_CAP, n, m, rev && A.gacc == nullptr,
                            spill_bytes(spill_for(t->C, chunk), chunk)) > LDS_BUDGET - 1024) {
@@ -875,7 +893,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
                   hipSuccess &&
               hipMemcpyAsync(g->d_splits, g->h_splits, (size_t)max_nodes * n * 4, hipMemcpyHostToDevice, cs) ==
                   hipSuccess;
-    ok = ok && launch_batched(t, mode, chunk, rev, spec, A, grid, max_nodes, cs) == MVF_OK;
+    ok = ok && launch_batched(t, mode, chunk, rev, spec, A, grid, g->tuning.block, max_nodes, cs) == MVF_OK;
     ok = ok && hipMemcpyAsync(g->h_reduced, g->d_reduced, (size_t)max_nodes * m * 2 * 8, hipMemcpyDeviceToHost, cs) ==
                    hipSuccess &&
          hipMemcpyAsync(g->h_argmin, g->d_argmin, (size_t)max_nodes * 8, hipMemcpyDeviceToHost, cs) == hipSuccess &&
@@ -1074,39 +1092,99 @@ int mvf_autotune_splits(const mvf_tape *t, int32_t n_nodes, const double *boxes,
     return MVF_OK;
 }
 
+namespace {
+// results of mvf_autotune, keyed by what determines the timing: the tape's
+// programs, the device, the specialised module, the sample's size and the
+// bounding mode and gradient mode
+struct TuneKey {
+    uint64_t tape;
+    int device;
+    uint64_t module;                    // the tape's specialisation (0: none)
+    int32_t n_nodes, mode, grad;
+    int64_t n_sub;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(tape, device, module, n_nodes, mode, grad, n_sub) <
+               std::tie(o.tape, o.device, o.module, o.n_nodes, o.mode, o.grad, o.n_sub);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, mvf_tuning> g_tune_cache;
+
+uint64_t tape_hash(const mvf_tape *t) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    };
+    mix(t->C.instr.data(), t->C.instr.size() * sizeof(Instr));
+    mix(&t->C.n_vars, sizeof t->C.n_vars);
+    mix(&t->ineq_mask, sizeof t->ineq_mask);
+    mix(&t->eq_mask, sizeof t->eq_mask);
+    return h;
+}
+}  // namespace
+
 int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const int32_t *splits, int64_t n_sub,
-                 int32_t mode, mvf_tuning *out, hipStream_t stream) {
+                 int32_t mode, int32_t grad, mvf_tuning *out, hipStream_t stream) {
     if (!t || !out || n_nodes < 1 || !boxes || !splits || n_sub < 1) return set_err(MVF_EINVAL, "bad argument");
-    // candidates: kernel (interpreter forward per tangent chunk, specialised
-    // forward, reverse-mode adjoint) x persistent grid size x subdomains per lane
-    std::vector<mvf_tuning> kernels;
-    for (int chunk = 1; chunk <= t->C.chunk; ++chunk) {
-        mvf_tuning c{};
-        c.grad = MVF_GRAD_FWD;
-        c.chunk = chunk;
-        c.engine = MVF_ENGINE_INTERP;
-        kernels.push_back(c);
-    }
-    for (int r = 0; r < 2; ++r) {
-        if (!t->spec_batch_fn[r]) continue;
-        mvf_tuning c{};
-        c.grad = r ? MVF_GRAD_REV : MVF_GRAD_FWD;
-        c.engine = MVF_ENGINE_SPEC;
-        kernels.push_back(c);
-    }
+    if (mode < MVF_MODE_NIE || mode > MVF_MODE_BOTH) return set_err(MVF_EINVAL, "bad mode");
+    if (grad < MVF_GRAD_FWD || grad > MVF_GRAD_AUTO) return set_err(MVF_EINVAL, "bad grad");
+    // the gradient mode is the caller's (it decides the enclosures, hence the
+    // bounds); AUTO resolves as in mvf_bound, by the reference op count
+    bool rev;
+    int chunk0;
+    int rc = resolve_grad(t, mode, grad, nullptr, &rev, &chunk0);
+    if (rc != MVF_OK) return rc;
+    const int g = rev ? MVF_GRAD_REV : MVF_GRAD_FWD;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const TuneKey key{tape_hash(t), dev, t->spec_batch_fn[rev] ? t->spec_id : 0, n_nodes, mode, g, n_sub};
     {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return MVF_OK;
+        }
+    }
+    // candidates: kernel (interpreter: each tangent chunk in forward mode;
+    // the specialised kernel: each workgroup size) x persistent grid (one,
+    // two or four 256-lane workgroups' worth per CU) x subdomains per lane
+    std::vector<mvf_tuning> kernels;
+    if (!rev)
+        for (int chunk = 1; chunk <= t->C.chunk; ++chunk) {
+            mvf_tuning c{};
+            c.grad = g;
+            c.chunk = chunk;
+            c.engine = MVF_ENGINE_INTERP;
+            c.block = BLK;
+            kernels.push_back(c);
+        }
+    else {
         mvf_tuning c{};
-        c.grad = MVF_GRAD_REV;
+        c.grad = g;
         c.engine = MVF_ENGINE_INTERP;
+        c.block = BLK;
         kernels.push_back(c);
     }
+    if (t->spec_batch_fn[rev])
+        for (int block : {64, 128, BLK}) {
+            mvf_tuning c{};
+            c.grad = g;
+            c.engine = MVF_ENGINE_SPEC;
+            c.block = block;
+            kernels.push_back(c);
+        }
     std::vector<mvf_tuning> cand;
     const int cu = t->n_cu;
     for (const mvf_tuning &kc : kernels)
         for (int mult : {1, 2, 4})
             for (int spl : {1, 2, 4}) {
                 mvf_tuning c = kc;
-                c.grid_blocks = mult * cu;
+                c.grid_blocks = mult * cu * (BLK / kc.block);
                 c.sub_per_lane = spl;
                 cand.push_back(c);
             }
@@ -1160,6 +1238,8 @@ int mvf_autotune(const mvf_tape *t, int32_t n_nodes, const double *boxes, const 
     if (best_i < 0) return set_err(MVF_ELIMIT, "no feasible tuning");
     *out = cand[best_i];
     out->best_ms = best / 2;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune_cache[key] = *out;
     return MVF_OK;
 }
 

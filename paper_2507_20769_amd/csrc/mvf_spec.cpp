@@ -43,7 +43,10 @@ namespace {
 // the device headers the generated source includes (text embedded at build time)
 #include "mvf_spec_headers.inc"
 
-constexpr int64_t DEFAULT_MAX_CODE = 6000;      // instruction-passes (compile time grows about linearly)
+// instruction-passes: compile time grows about linearly (some 2 ms each on the
+// GPU host; the 32-variable workload's adjoint, about 11,000, takes some 40 s,
+// once: the code object is cached)
+constexpr int64_t DEFAULT_MAX_CODE = 32000;
 constexpr int SEGMENT = 32;                      // instructions per guarded block
 // Largest segment budget of the checkpointed adjoint.  Budgets up to 40 gave
 // adjoints bitwise equal to the single-pass form on every workload measured;

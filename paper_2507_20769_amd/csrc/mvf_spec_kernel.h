@@ -16,11 +16,13 @@
 namespace mvf {
 namespace dev {
 
+// The workgroup is blockDim.x = 64, 128 or 256 lanes (one to four waves; a
+// launch-time choice of the autotuner); LDS is laid out for up to four waves.
 template <bool REV>
 __device__ __forceinline__ void spec_bound_body() {
     constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
     extern __shared__ __align__(16) uint8_t smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, blk = blockDim.x;
     // LDS: breakpoint table, per-wave reduction records, splits and table offsets
     const int tab_total = kargs<BoundKArgs>()->B.tab_off[n];
     double4 *tab = reinterpret_cast<double4 *>(smem);
@@ -32,22 +34,22 @@ __device__ __forceinline__ void spec_bound_body() {
         if (tid <= n) ints[MVF_MAX_VARS + tid] = K->B.tab_off[tid];
         if (tid < n) ints[tid] = K->B.splits[tid];
         __syncthreads();
-        build_table(n, K->B.box, ints, ints + MVF_MAX_VARS, tab, tid, BLK);
+        build_table(n, K->B.box, ints, ints + MVF_MAX_VARS, tab, tid, blk);
         if (lane == 0) reset_wred(wred + wave * wred_len(m), m);
     }
     __syncthreads();
     // always true, but opaque to the compiler: the generated code is cut into
     // blocks guarded by it, which keeps compile time near linear in its size
     const bool go = kargs<BoundKArgs>()->T.n == n;
-    for (int64_t base = (int64_t)blockIdx.x * BLK;; base += (int64_t)gridDim.x * BLK) {
+    for (int64_t base = (int64_t)blockIdx.x * blk;; base += (int64_t)gridDim.x * blk) {
         const int64_t S = kargs<BoundKArgs>()->B.S;
         if (base >= S) break;
         const int64_t k = base + tid;
         const bool active = k < S;
         SpecLane L;
         L.tab = tab;
-        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * BLK + tid;
-        L.ck_stride = (int64_t)gridDim.x * BLK;
+        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * blk + tid;
+        L.ck_stride = (int64_t)gridDim.x * blk;
         int64_t q = active ? k : S - 1;
 #pragma unroll
         for (int i = 0; i < n; ++i) {            // dimension 0 fastest (Sec. 3.1.1)
@@ -77,7 +79,7 @@ __device__ __forceinline__ void spec_bound_body() {
     __syncthreads();
     if (tid == 0) {
         const auto K = kargs<BoundKArgs>();
-        write_partial(wred, BLK / 64, m, K->B.partial + (size_t)blockIdx.x * m * 2, K->B.partial_lo0 + blockIdx.x,
+        write_partial(wred, blk / 64, m, K->B.partial + (size_t)blockIdx.x * m * 2, K->B.partial_lo0 + blockIdx.x,
                       K->B.partial_k + blockIdx.x, K->B.partial_ext + 2 * (size_t)blockIdx.x);
     }
 }
@@ -92,7 +94,7 @@ __device__ __forceinline__ void spec_batch_body() {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int64_t sh_item;
     __shared__ int sh_node;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, blk = blockDim.x;
     const int tab_cap = kargs<BatchKArgs>()->A.tab_cap;
     double4 *tab = reinterpret_cast<double4 *>(smem);
     double *wred = reinterpret_cast<double *>(smem + (size_t)tab_cap * 32);
@@ -133,26 +135,25 @@ __device__ __forceinline__ void spec_batch_body() {
                 ints[MVF_MAX_VARS + n] = acc;
             }
             __syncthreads();
-            build_table(n, K->A.boxes + (int64_t)node * n * 2, ints, ints + MVF_MAX_VARS, tab, tid, BLK);
+            build_table(n, K->A.boxes + (int64_t)node * n * 2, ints, ints + MVF_MAX_VARS, tab, tid, blk);
             cur = node;
         }
         if (lane == 0) reset_wred(wred + wave * wred_len(m), m);
         __syncthreads();
-        int64_t S, base;
-        int spl;
+        int64_t S, base, len;
         {
             const auto K = kargs<BatchKArgs>();
             S = K->A.node_S[node];
-            spl = K->A.spl;
-            base = (item - K->A.item_off[node]) * spl * BLK;
+            len = (int64_t)K->A.spl * BLK;                  // a work item: spl * 256 subdomains
+            base = (item - K->A.item_off[node]) * len;
         }
-        for (int j = 0; j < spl && base + (int64_t)j * BLK < S; ++j) {      // uniform over the workgroup
-            const int64_t k = base + (int64_t)j * BLK + tid;
+        for (int64_t off = 0; off < len && base + off < S; off += blk) {      // uniform over the workgroup
+            const int64_t k = base + off + tid;
             const bool active = k < S;
             SpecLane L;
             L.tab = tab;
-            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * BLK + tid;
-            L.ck_stride = (int64_t)gridDim.x * BLK;
+            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * blk + tid;
+            L.ck_stride = (int64_t)gridDim.x * blk;
             int64_t q = active ? k : S - 1;
 #pragma unroll
             for (int i = 0; i < n; ++i) {
@@ -182,7 +183,7 @@ __device__ __forceinline__ void spec_batch_body() {
         __syncthreads();
         if (tid == 0) {
             const auto K = kargs<BatchKArgs>();
-            write_partial(wred, BLK / 64, m, K->A.partial + (size_t)item * m * 2, K->A.partial_lo0 + item,
+            write_partial(wred, blk / 64, m, K->A.partial + (size_t)item * m * 2, K->A.partial_lo0 + item,
                           K->A.partial_k + item, K->A.partial_ext + 2 * (size_t)item);
         }
     }

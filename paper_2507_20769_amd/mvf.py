@@ -46,11 +46,16 @@ class TapeStats(ctypes.Structure):
 class Tuning(ctypes.Structure):
     """mvf_tuning; grad -1 keeps the call's gradient mode."""
     _fields_ = [("grad", ctypes.c_int32), ("chunk", ctypes.c_int32), ("grid_blocks", ctypes.c_int32),
-                ("best_ms", ctypes.c_float), ("sub_per_lane", ctypes.c_int32), ("engine", ctypes.c_int32)]
+                ("best_ms", ctypes.c_float), ("sub_per_lane", ctypes.c_int32), ("engine", ctypes.c_int32),
+                ("block", ctypes.c_int32)]
 
     def __repr__(self):
         return (f"Tuning(grad={self.grad}, chunk={self.chunk}, grid_blocks={self.grid_blocks}, "
-                f"sub_per_lane={self.sub_per_lane}, engine={self.engine}, best_ms={self.best_ms:.3f})")
+                f"sub_per_lane={self.sub_per_lane}, engine={self.engine}, block={self.block}, "
+                f"best_ms={self.best_ms:.3f})")
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class BnbOptions(ctypes.Structure):
@@ -181,7 +186,7 @@ def lib():
             L.mvf_batch_graph_destroy.restype = ctypes.c_int
             L.mvf_batch_graph_destroy.argtypes = [P]
             L.mvf_autotune.restype = ctypes.c_int
-            L.mvf_autotune.argtypes = [P, i32, P, P, i64, i32, ctypes.POINTER(Tuning), P]
+            L.mvf_autotune.argtypes = [P, i32, P, P, i64, i32, i32, ctypes.POINTER(Tuning), P]
             L.mvf_points_workspace.restype = ctypes.c_int
             L.mvf_points_workspace.argtypes = [P, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
             L.mvf_eval_points.restype = ctypes.c_int
@@ -223,12 +228,13 @@ def check(tape) -> TapeStats:
 
 
 def spec_check(tape, chunk: int = 0, waves: int = 0, max_code: int = 0, grad: str = "fwd",
-               ckpt_budget: int = 0) -> dict:
+               ckpt_budget: int = 0, cache: bool = False) -> dict:
     """Generate and compile the specialised kernels of a tape for gfx950 on the
-    host (no device, no cache); returns the mvf_spec_info fields."""
+    host (no device); cache: write (or read) the code-object cache that
+    Tape.specialize with the same options reads; returns the mvf_spec_info fields."""
     keep, args = _tape_arrays(tape)
     info = SpecInfo()
-    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, 0, MVF_GRAD[grad],
+    rc = lib().mvf_spec_check(*args, ctypes.byref(SpecOptions(chunk, waves, max_code, int(cache), MVF_GRAD[grad],
                                                               ckpt_budget)),
                               ctypes.byref(info))
     if rc != 0:
@@ -559,7 +565,10 @@ class BatchGraph:
             pass
 
 
-def autotune(tape: Tape, boxes, splits, mode: str = "both", stream=None) -> Tuning:
+def autotune(tape: Tape, boxes, splits, mode: str = "both", grad: str = "rev", stream=None) -> Tuning:
+    """mvf_autotune on sample nodes (device boxes [N, n, 2], splits [N, n]); the
+    gradient mode is the caller's (the tuner picks kernel, grid, subdomains per
+    lane and workgroup size).  Cached per process."""
     import torch
     _require_device("autotune", boxes=boxes, splits=splits)
     boxes = boxes.contiguous()
@@ -568,7 +577,7 @@ def autotune(tape: Tape, boxes, splits, mode: str = "both", stream=None) -> Tuni
     total = int(torch.prod(splits.to(torch.int64), dim=1).sum().item())
     out = Tuning()
     rc = lib().mvf_autotune(tape.handle, N, boxes.data_ptr(), splits.data_ptr(), total, MVF_MODE[mode],
-                            ctypes.byref(out), _stream_ptr(stream))
+                            MVF_GRAD[grad], ctypes.byref(out), _stream_ptr(stream))
     if rc != 0:
         raise MVFError(rc, "mvf_autotune")
     return out

@@ -31,16 +31,17 @@ def _per_node(h, bw, grad):
     return np.stack(red), np.array(am), np.stack(ex)
 
 
-def _tuning(grad, spl, engine, grid=0):
+def _tuning(grad, spl, engine, grid=0, block=0):
     from paper_2507_20769_amd import mvf
     return mvf.Tuning(grad=grad, chunk=0, grid_blocks=grid, best_ms=0.0, sub_per_lane=spl,
-                      engine=mvf.MVF_ENGINE[engine])
+                      engine=mvf.MVF_ENGINE[engine], block=block)
 
 
-@pytest.mark.parametrize("grad,spl,engine", [("fwd", 2, "interp"), ("fwd", 4, "interp"), ("rev", 2, "interp"),
-                                             ("rev", 4, "interp"), ("fwd", 1, "spec"), ("fwd", 2, "spec"),
-                                             ("fwd", 4, "spec"), ("rev", 1, "spec"), ("rev", 4, "spec")])
-def test_batched_configurations_equal_per_node(grad, spl, engine):
+@pytest.mark.parametrize("grad,spl,engine,block", [
+    ("fwd", 2, "interp", 0), ("fwd", 4, "interp", 0), ("rev", 2, "interp", 0), ("rev", 4, "interp", 0),
+    ("fwd", 1, "spec", 0), ("fwd", 2, "spec", 128), ("fwd", 4, "spec", 64), ("rev", 1, "spec", 64),
+    ("rev", 4, "spec", 0), ("rev", 2, "spec", 128)])
+def test_batched_configurations_equal_per_node(grad, spl, engine, block):
     import torch
     from paper_2507_20769_amd import mvf
     bw = I.small_batch(21, 20, k_range=(3, 12))           # 8 .. 4096 subdomains: ragged items
@@ -49,8 +50,8 @@ def test_batched_configurations_equal_per_node(grad, spl, engine):
     h.set_root_kinds([0] + [1] * (tape.n_roots - 1))
     if engine == "spec":
         h.specialize(grad="auto")
-    print(f"[case] grad={grad} spl={spl} engine={engine}", flush=True)
-    tu = _tuning(0 if grad == "fwd" else 1, spl, engine, grid=37)   # an odd grid: items wrap unevenly
+    print(f"[case] grad={grad} spl={spl} engine={engine} block={block}", flush=True)
+    tu = _tuning(0 if grad == "fwd" else 1, spl, engine, grid=37, block=block)   # an odd grid: items wrap unevenly
     out = mvf.bound_batch(h, torch.tensor(bw.boxes, device="cuda"), torch.tensor(bw.splits, device="cuda"),
                           mode="both", grad=grad, tuning=tu)
     torch.cuda.synchronize()
@@ -87,7 +88,12 @@ def test_spec_batch_graph_replays_match_fresh_launches():
     h.close()
 
 
-def test_autotuner_considers_the_specialised_kernel():
+@pytest.mark.parametrize("grad", ["fwd", "rev"])
+def test_autotuner_considers_the_specialised_kernel(grad):
+    # the tuner keeps the caller's gradient mode, picks among interpreter and specialised kernels
+    # (the latter at three workgroup sizes), grids and subdomains per lane, and caches its answer;
+    # whatever it picks gives the bits of the interpreter's plain configuration
+    import time
     import torch
     from paper_2507_20769_amd import mvf
     bw = I.small_batch(23, 16, k_range=(6, 11))
@@ -95,19 +101,20 @@ def test_autotuner_considers_the_specialised_kernel():
     h.specialize(grad="auto")
     boxes = torch.tensor(bw.boxes, device="cuda")
     splits = torch.tensor(bw.splits, device="cuda")
-    tu = mvf.autotune(h, boxes, splits, mode="both")
-    print(f"[autotune] {tu}", flush=True)
-    assert tu.grad in (0, 1) and tu.grid_blocks > 0 and tu.best_ms > 0 and tu.sub_per_lane in (1, 2, 4)
-    assert tu.engine in (1, 2)
-    out = mvf.bound_batch(h, boxes, splits, mode="both", grad="rev", tuning=tu)
-    ref = mvf.bound_batch(h, boxes, splits, mode="both", grad="fwd" if tu.grad == 0 else "rev",
-                          tuning=_tuning(tu.grad, 1, "interp"))
+    t0 = time.perf_counter()
+    tu = mvf.autotune(h, boxes, splits, mode="both", grad=grad)
+    t1 = time.perf_counter()
+    print(f"[autotune] {tu} in {t1 - t0:.2f} s", flush=True)
+    g = 0 if grad == "fwd" else 1
+    assert tu.grad == g and tu.grid_blocks > 0 and tu.best_ms > 0 and tu.sub_per_lane in (1, 2, 4)
+    assert tu.engine in (1, 2) and tu.block in (64, 128, 256)
+    again = mvf.autotune(h, boxes, splits, mode="both", grad=grad)          # cached
+    assert time.perf_counter() - t1 < 0.1 * (t1 - t0) and again.as_dict() == tu.as_dict()
+    out = mvf.bound_batch(h, boxes, splits, mode="both", grad=grad, tuning=tu)
+    ref = mvf.bound_batch(h, boxes, splits, mode="both", grad=grad, tuning=_tuning(g, 1, "interp"))
     torch.cuda.synchronize()
-    a, b = out["reduced"].cpu().numpy(), ref["reduced"].cpu().numpy()
-    if tu.engine == 1:
-        assert np.array_equal(a, b)
-    else:   # the specialised kernel: bitwise up to the libm build of exp/log
-        assert np.allclose(a, b, rtol=1e-12, atol=0)
+    assert np.array_equal(out["reduced"].cpu().numpy(), ref["reduced"].cpu().numpy())
+    assert np.array_equal(out["argmin"].cpu().numpy(), ref["argmin"].cpu().numpy())
     h.close()
 
 
@@ -119,7 +126,9 @@ def test_batched_engine_errors():
     boxes = torch.tensor(bw.boxes, device="cuda")
     splits = torch.tensor(bw.splits, device="cuda")
     for tu, grad in ((_tuning(0, 1, "spec"), "fwd"),      # not specialised
-                     (_tuning(0, 17, "interp"), "fwd")):  # sub_per_lane out of range
+                     (_tuning(0, 17, "interp"), "fwd"),   # sub_per_lane out of range
+                     (_tuning(0, 1, "interp", block=128), "fwd"),   # the interpreter's workgroup is 256
+                     (_tuning(0, 1, "auto", block=96), "fwd")):     # not 64, 128 or 256
         with pytest.raises(mvf.MVFError) as e:
             mvf.bound_batch(h, boxes, splits, grad=grad, tuning=tu)
         assert e.value.code == -1

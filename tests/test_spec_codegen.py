@@ -143,9 +143,10 @@ def test_bad_options_and_size_limit():
     with pytest.raises(mvf.MVFError) as e:
         mvf.spec_check(t, max_code=10)
     assert e.value.code == -3 and "instruction-passes" in mvf.lib().mvf_last_error().decode()
-    # the e2e tape is above the default size limit
+    # the plan (and the size limit) is checked before anything is generated: the 32-variable
+    # workload's tangent mode (3,286 instructions, 32 components) is far above the default limit
     with pytest.raises(mvf.MVFError) as e:
-        mvf.spec_check(I.e2e_tape(1))
+        mvf.spec_check(I.diff(1).tape, grad="fwd")
     assert e.value.code == -3
 
 
