@@ -234,7 +234,8 @@ int mvf_bound_noalloc(const mvf_tape *tape, const mvf_bound_args *args, hipStrea
  */
 typedef struct {
     int32_t chunk;            /* tangent components per pass, 1..n; 0 = library choice */
-    int32_t waves;            /* waves per SIMD the kernel is compiled for, 1..4; 0 = 2 */
+    int32_t waves;            /* waves per SIMD the kernel is compiled for, 1..4 (2..4 when the
+                                 adjoint is built: MVF_EINVAL for 1); 0 = 2 */
     int64_t max_code;         /* size limit in instruction-passes; 0 = default (32000) */
     int32_t use_cache;        /* nonzero: read and write the on-disk code-object cache
                                  (mvf_spec_check: write it, for gfx950, so that a later

@@ -53,6 +53,10 @@ constexpr int SEGMENT = 32;                      // instructions per guarded blo
 // at 58 the 32-variable workload's objective came out different on the GPU
 // although the generated code computes the same values (the host-side
 // symbolic check of the generator agrees), so larger budgets are refused.
+// For the same reason of an unexplained failure -- a memory fault of the
+// batch workload's adjoint compiled for one wave per SIMD (segment budget 32,
+// 64-lane workgroups) -- the adjoint kernels are not built for one wave per
+// SIMD.
 constexpr int MAX_CKPT_BUDGET = 40;
 // A body line that only starts a new guarded block (segment boundaries of the
 // checkpointed adjoint, so that a segment's checkpoint loads lead a block).
@@ -903,6 +907,8 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
     if (c < 1 || c > n) return set_error(MVF_EINVAL, "chunk out of range [1, n]");
     if (opt && opt->ckpt_budget > MAX_CKPT_BUDGET)
         return set_error(MVF_EINVAL, "ckpt_budget above " + std::to_string(MAX_CKPT_BUDGET) + " intervals");
+    if (rev && opt && opt->waves == 1)
+        return set_error(MVF_EINVAL, "the adjoint kernels are not built for one wave per SIMD");
     const int passes = (n + c - 1) / c;
     // point and value passes, tangent passes, the adjoint's value pass, its
     // recomputation and its sweep (at most three passes over the program)

@@ -178,3 +178,15 @@ def test_checkpointed_adjoint_plan_and_size():
         if prev is not None:
             assert info["code_units"] <= prev["code_units"] + st.n_instr
         prev = info
+
+
+def test_adjoint_settings_outside_the_verified_range_are_refused():
+    # segment budgets above 40 and the adjoint at one wave per SIMD failed on the GPU without
+    # a cause found (wrong bounds, a memory fault): the library refuses them
+    t = I.random_small_tape(6, n=5, ops=30, n_con=1, con_ops=10, window=8)
+    for kw in ({"grad": "rev", "ckpt_budget": 41}, {"grad": "rev", "waves": 1}, {"grad": "auto", "waves": 1}):
+        with pytest.raises(mvf.MVFError) as e:
+            mvf.spec_source(t, **kw)
+        assert e.value.code == -1, kw
+    assert mvf.spec_source(t, grad="fwd", waves=1)                 # tangent mode alone is built at one wave
+    assert mvf.spec_source(t, grad="rev", ckpt_budget=40)
