@@ -115,7 +115,7 @@ __device__ __forceinline__ void track_root(FeasTrack &F, int r, Iv B, Iv FC, boo
     if (r == 0) {
         F.obj_lo = B.lo;
         F.centre_hi = -FC.nh;
-        F.centre_ok = have_fc && o.eq == 0;
+        F.centre_ok &= have_fc && o.eq == 0;            // (combined, so the roots may come in any order)
         return;
     }
     if ((o.ineq >> r) & 1u) {

@@ -28,6 +28,7 @@
 #include <map>
 #include <string>
 #include <sys/stat.h>
+#include <utime.h>
 #include <unistd.h>
 #include <unordered_set>
 #include <vector>
@@ -1109,6 +1110,7 @@ int spec_compile(const std::string &src, const std::string &arch, bool use_cache
     const std::string dir = use_cache ? cache_dir() : "";
     const std::string path = dir.empty() ? "" : dir + "/mvf_spec_" + hex + ".co";
     if (!path.empty() && read_file(path, code)) {
+        utime(path.c_str(), nullptr);                // last use, for pruning stale entries
         *from_cache = true;
         *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return MVF_OK;
