@@ -381,14 +381,22 @@ int mvf_bound_batch(const mvf_tape *tape, const mvf_batch_args *args, const mvf_
  * reduction -> {D2H of reduced, argmin, status to pinned memory}.  Replays
  * take the node count through device memory, so the graph is never
  * re-instantiated.  create allocates all buffers; launch validates the staged
- * splits on the host and enqueues one graph launch; results are valid after
- * the caller synchronises the stream.
+ * splits on the host and enqueues one graph launch (waiting first for the
+ * previous replay, whose first copy reads the pinned node count); results are
+ * valid after the caller synchronises the stream or calls
+ * mvf_batch_graph_wait.
  */
 typedef struct mvf_batch_graph mvf_batch_graph;
 int mvf_batch_graph_create(const mvf_tape *tape, int32_t max_nodes, int64_t max_subdomains, int32_t mode,
                            int32_t grad, const mvf_tuning *tuning, hipStream_t stream, mvf_batch_graph **out);
 int mvf_batch_graph_staging(mvf_batch_graph *g, double **boxes, int32_t **splits);
 int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stream);
+/* Blocks until the graph's last replay (its staging H2D copies and its result
+ * D2H copies included) has finished.  The staging buffers are read by the
+ * replay's copies, so a caller must not write them for the next batch before
+ * this returns (or before it has synchronised the replay's stream); the
+ * results are valid after it too. */
+int mvf_batch_graph_wait(mvf_batch_graph *g);
 int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int64_t **argmin,
                            const int32_t **status, const double **extra);
 int mvf_batch_graph_destroy(mvf_batch_graph *g);

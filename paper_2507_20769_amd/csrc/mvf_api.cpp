@@ -56,6 +56,8 @@ struct mvf_batch_graph {
     int64_t *h_argmin = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;            // recorded after each replay (staging reuse guard)
+    bool launched = false;
 };
 
 namespace {
@@ -904,6 +906,7 @@ int mvf_batch_graph_create(const mvf_tape *t, int32_t max_nodes, int64_t max_sub
     if (!ok || ee != hipSuccess) return fail(MVF_EHIP, "graph capture failed");
     if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
         return fail(MVF_EHIP, "hipGraphInstantiate");
+    if (hipEventCreateWithFlags(&g->done, hipEventDisableTiming) != hipSuccess) return fail(MVF_EHIP, "hipEventCreate");
     *out = g;
     return MVF_OK;
 }
@@ -931,8 +934,18 @@ int mvf_batch_graph_launch(mvf_batch_graph *g, int32_t n_nodes, hipStream_t stre
         total += S;
     }
     if (total > g->max_subdomains) return set_err(MVF_ELIMIT, "total subdomains above the graph's capacity");
+    // the count sits in pinned memory that the previous replay's first copy reads
+    if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     *g->h_count = n_nodes;
     HIP_TRY(hipGraphLaunch(g->exec, stream));
+    HIP_TRY(hipEventRecord(g->done, stream));
+    g->launched = true;
+    return MVF_OK;
+}
+
+int mvf_batch_graph_wait(mvf_batch_graph *g) {
+    if (!g) return set_err(MVF_EINVAL, "null graph");
+    if (g->launched) HIP_TRY(hipEventSynchronize(g->done));
     return MVF_OK;
 }
 
@@ -948,6 +961,7 @@ int mvf_batch_graph_result(mvf_batch_graph *g, const double **reduced, const int
 
 int mvf_batch_graph_destroy(mvf_batch_graph *g) {
     if (!g) return MVF_OK;
+    if (g->done) hipEventDestroy(g->done);
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
     hipFree(g->d_ws);

@@ -112,7 +112,7 @@ EXPORTS = ["mvf_tape_create", "mvf_tape_check", "mvf_tape_stats_get", "mvf_tape_
            "mvf_batch_graph_destroy", "mvf_autotune", "mvf_strerror", "mvf_last_error",
            "mvf_points_workspace", "mvf_eval_points", "mvf_vjp_points", "mvf_gradient_boxes",
            "mvf_tape_set_root_kinds", "mvf_bnb_solve", "mvf_tape_specialize", "mvf_spec_check", "mvf_splits",
-           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace", "mvf_spec_source", "mvf_bound_noalloc"]
+           "mvf_autotune_splits", "mvf_fbbt", "mvf_fbbt_workspace", "mvf_spec_source", "mvf_bound_noalloc", "mvf_batch_graph_wait"]
 
 
 def lib():
@@ -174,6 +174,8 @@ def lib():
                                                   ctypes.POINTER(ctypes.POINTER(ctypes.c_int32))]
             L.mvf_batch_graph_launch.restype = ctypes.c_int
             L.mvf_batch_graph_launch.argtypes = [P, i32, P]
+            L.mvf_batch_graph_wait.restype = ctypes.c_int
+            L.mvf_batch_graph_wait.argtypes = [P]
             L.mvf_batch_graph_result.restype = ctypes.c_int
             L.mvf_batch_graph_result.argtypes = [P, ctypes.POINTER(ctypes.POINTER(ctypes.c_double)),
                                                  ctypes.POINTER(ctypes.POINTER(ctypes.c_int64)),
@@ -534,8 +536,12 @@ class BatchGraph:
         self.h_status = np.ctypeslib.as_array(stp, shape=(max_nodes,))
 
     def launch(self, boxes: np.ndarray, splits: np.ndarray, stream=None):
-        """Stage node data (host arrays) into pinned memory and replay the graph."""
+        """Stage node data (host arrays) into pinned memory and replay the graph.  Waits
+        first for the previous replay, whose copies read the staging buffers."""
         N = boxes.shape[0]
+        rc = lib().mvf_batch_graph_wait(self.handle)
+        if rc != 0:
+            raise MVFError(rc, "mvf_batch_graph_wait")
         self.h_boxes[:N] = boxes
         self.h_splits[:N] = splits
         rc = lib().mvf_batch_graph_launch(self.handle, N, _stream_ptr(stream))

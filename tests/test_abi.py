@@ -113,6 +113,7 @@ def test_bound_rejects_bad_arguments_without_device():
     assert L.mvf_tape_destroy(None) == 0
     assert L.mvf_bound_batch(None, None, None, None) == -1
     assert L.mvf_batch_graph_launch(None, 0, None) == -1
+    assert L.mvf_batch_graph_wait(None) == -1
 
 
 def test_points_entry_points_reject_bad_arguments_without_device():
