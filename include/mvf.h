@@ -148,6 +148,10 @@ typedef struct {
                                  equality roots, MVF modes only), else +inf (Sec. 3.1, the
                                  feasibility check; the centres are rigorously feasible points) */
     int32_t engine;           /* MVF_ENGINE_*: the interpreter or the tape's specialised kernel */
+    hipEvent_t kernel_events[2];  /* NULL, or two events that the call records on its stream right
+                                     before the bounding kernel and right after it, ahead of the
+                                     one-block reduction kernel: the bounding kernel's own duration
+                                     (hipEventElapsedTime) for profiling; the caller owns them */
 } mvf_bound_args;
 
 /* Kernel choice of mvf_bound: AUTO runs the tape's specialised kernel for the

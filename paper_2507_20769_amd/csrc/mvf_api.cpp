@@ -587,17 +587,19 @@ int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_b
     B.extra = a->extra;
     B.rec = reinterpret_cast<double2 *>(w + L.rec);
     B.gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
+    if (a->kernel_events[0]) HIP_TRY(hipEventRecord(a->kernel_events[0], stream));
     if (spec) {
         BoundKArgs K{T, B};
         void *params[] = {&K};
         hipError_t e =
             hipModuleLaunchKernel(t->spec_fn[rev], grid, 1, 1, BLK, 1, 1, (unsigned)lds, stream, params, nullptr);
         if (e != hipSuccess) return hip_err(e, "hipModuleLaunchKernel (specialised kernel)");
+        if (a->kernel_events[1]) HIP_TRY(hipEventRecord(a->kernel_events[1], stream));
         e = launch_finish(B, grid, m, stream);
         if (e != hipSuccess) return hip_err(e, "finish kernel");
         return MVF_OK;
     }
-    hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream);
+    hipError_t e = launch_bound(T, B, chunk, rev, grid, lds, stream, a->kernel_events[1]);
     if (e != hipSuccess) return hip_err(e, "launch_bound");
     return MVF_OK;
 }

@@ -12,7 +12,8 @@ namespace mvf {
 hipError_t launch_points(const PointsArgs &A, int op, int chunk, int grid, size_t lds, hipStream_t stream);
 
 hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev, int grid, size_t lds,
-                        hipStream_t stream);
+                        hipStream_t stream,
+                        hipEvent_t after = nullptr);
 // Step 3 across the workgroups of a single-box launch (per-block partials -> reduced, argmin, extra)
 hipError_t launch_finish(const BoxArgs &B, int grid, int m, hipStream_t stream);
 // forward-backward bound tightening, one lane per box

@@ -1267,7 +1267,7 @@ hipError_t launch_fbbt(const FbbtArgs &A, hipStream_t stream) {
     } while (0)
 
 hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev, int grid, size_t lds,
-                        hipStream_t stream) {
+                        hipStream_t stream, hipEvent_t after) {
     static_assert(MAX_CHUNK == 4, "one kernel instance per chunk size");
     hipError_t e = hipSuccess;
     MVF_DISPATCH(chunk, rev, {
@@ -1279,6 +1279,7 @@ hipError_t launch_bound(const TapeArgs &T, const BoxArgs &B, int chunk, bool rev
     });
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (after && (e = hipEventRecord(after, stream)) != hipSuccess) return e;
     return launch_finish(B, grid, T.n_roots, stream);
 }
 

@@ -11,6 +11,7 @@ typedef __hip_internal::uint32_t uint32_t;
 typedef __hip_internal::int64_t int64_t;
 typedef __hip_internal::uint64_t uint64_t;
 typedef struct ihipStream_t *hipStream_t;
+typedef struct ihipEvent_t *hipEvent_t;
 #ifndef INT64_MAX
 #define INT64_MAX 0x7fffffffffffffffLL
 #endif

@@ -49,6 +49,7 @@ namespace {
 // once: the code object is cached)
 constexpr int64_t DEFAULT_MAX_CODE = 32000;
 constexpr int SEGMENT = 32;                      // instructions per guarded block
+constexpr int LDS_LEAD = 2;                      // statements a variable's LDS read runs ahead of its use
 // Largest segment budget of the checkpointed adjoint.  Budgets up to 40 gave
 // adjoints bitwise equal to the single-pass form on every workload measured;
 // at 58 the 32-variable workload's objective came out different on the GPU
@@ -253,7 +254,7 @@ class Scheduler {
 class PassWriter {
   public:
     PassWriter(const Compiled &Cp, int root, int C, int c0, bool point, bool tape = false)
-        : P(Cp), r(root), C(C), c0(c0), point(point), partials(tape) {}
+        : P(Cp), r(root), C(C), c0(c0), point(point), partials(tape), lead(!tape) {}
 
     // body lines (declarations first, then guarded blocks) and the names of
     // the result's value and components
@@ -423,6 +424,8 @@ class PassWriter {
     int r, C, c0;
     bool point;
     bool partials;                               // compute the local partials (and record the steps)
+    const bool lead;                             // place variable reads LDS_LEAD statements early
+    int n_hoist = 0;
     bool checks = true;                          // emit the domain tests
     std::vector<std::string> slot_val;
     std::vector<std::vector<std::string>> slot_tan;
@@ -524,6 +527,21 @@ class PassWriter {
         }
     }
 
+    // A variable's LDS read placed LDS_LEAD statements ahead of its use, into a
+    // temporary, so that its latency overlaps the arithmetic in between (the
+    // compiler keeps reads next to their uses under this register pressure).
+    // Tangent-mode and point passes only: in the adjoint's value pass the
+    // longer live ranges cost more spills than the overlap gains.
+    std::string hoist(const std::string &e, Decls &decl, std::vector<std::string> &body) {
+        const std::string name = "x" + std::to_string(r) + (point ? "p" : "t") + std::to_string(c0) + "_" +
+                                 std::to_string(n_hoist++);
+        decl.push_back("Iv " + name + ";");
+        const size_t d = (size_t)LDS_LEAD;
+        const size_t pos = body.size() > d ? body.size() - d : 0;
+        body.insert(body.begin() + (long)pos, name + " = " + e + ";");
+        return name;
+    }
+
     void instr(int pc, Decls &decl, std::vector<std::string> &body) {
         const Dec I = decode(P.instr[pc]);
         std::string U, V;
@@ -532,10 +550,15 @@ class PassWriter {
         int ha = -1, hb = -1;
         fetch(I.ak, I.a, I.k, U, A, ad, ha);
         if (I.op <= I_DIV) fetch(I.bk, I.b, I.k, V, B, bd, hb);
+        const std::string Ue = U, Ve = V;                // operand expressions for the sweep
+        if (lead && LDS_LEAD > 0) {
+            if (I.ak == K_VAR) U = hoist(U, decl, body);
+            if (I.op <= I_DIV && I.bk == K_VAR) V = I.ak == K_VAR && I.a == I.b ? U : hoist(V, decl, body);
+        }
         const bool nu = nonneg(I.ak, I.a, I.k), nv = I.op <= I_DIV && nonneg(I.bk, I.b, I.k);
         const bool nz = nonneg_result(I, nu, nv);
         if (partials) {
-            Step st{pc, I, U, V, "", I.ak == K_SLOT ? slot_prod.at(I.a) : -1,
+            Step st{pc, I, Ue, Ve, "", I.ak == K_SLOT ? slot_prod.at(I.a) : -1,
                     I.op <= I_DIV && I.bk == K_SLOT ? slot_prod.at(I.b) : -1, nu, nv, nz};
             if (I.op == I_DIVK || I.op == I_DIVKN) st.aux = aux_literal(P.instr.at(I.b));
             steps[pc] = st;
@@ -988,8 +1011,9 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
             s += "            Iv G[N_VARS];\n            const Iv nie = adjoint_" + R + "(L, go, bad, G);\n";
             s += "            Iv acc = FC;\n";
             for (int i = 0; i < n; ++i)
-                s += "            acc = iadd(acc, imul_dx(G[" + std::to_string(i) + "], spec_dx(L, " + std::to_string(i) +
-                     ")));\n";
+                s += "            const Iv d" + std::to_string(i) + " = spec_dx(L, " + std::to_string(i) + ");\n";
+            for (int i = 0; i < n; ++i)
+                s += "            acc = iadd(acc, imul_dx(G[" + std::to_string(i) + "], d" + std::to_string(i) + "));\n";
             s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";
             s += "        }\n        if (B.lo != B.lo || B.nh != B.nh) bad = 1;\n";
             s += "        reduce_root(" + R + ", N_ROOTS, B, o);\n";
@@ -1016,10 +1040,16 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
             s += "            {\n                Iv G[" + std::to_string(c) + "];\n";
             s += "                const Iv v = tangent_" + R + "_" + std::to_string(c0) + "(L, go, bad, G);\n";
             if (c0 == 0) s += "                nie = v;\n";
-            for (int t = 0; t < c; ++t)      // a zero component adds nothing
+            // the factors X_i - c_i first (their LDS reads issued together), then the products;
+            // a zero component adds nothing
+            for (int t = 0; t < c; ++t)
                 if (!zero[r][c0 + t])
-                    s += "                acc = iadd(acc, imul_dx(G[" + std::to_string(t) + "], spec_dx(L, " +
-                         std::to_string(c0 + t) + ")));\n";
+                    s += "                const Iv d" + std::to_string(t) + " = spec_dx(L, " + std::to_string(c0 + t) +
+                         ");\n";
+            for (int t = 0; t < c; ++t)
+                if (!zero[r][c0 + t])
+                    s += "                acc = iadd(acc, imul_dx(G[" + std::to_string(t) + "], d" + std::to_string(t) +
+                         "));\n";
             s += "            }\n";
         }
         s += "            B = mode == MVF_MODE_MVF ? acc : Iv{fmax_(acc.lo, nie.lo), fmax_(acc.nh, nie.nh)};\n";

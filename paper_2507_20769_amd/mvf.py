@@ -84,7 +84,7 @@ class BoundArgs(ctypes.Structure):
                 ("grad", ctypes.c_int32), ("reduced", ctypes.c_void_p), ("argmin", ctypes.c_void_p),
                 ("per_sub", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("tuning", ctypes.c_void_p), ("extra", ctypes.c_void_p),
-                ("engine", ctypes.c_int32)]
+                ("engine", ctypes.c_int32), ("kernel_events", ctypes.c_void_p * 2)]
 
 
 class SpecOptions(ctypes.Structure):
@@ -363,6 +363,15 @@ class BoundCall:
                               self.workspace.numel() if self.workspace is not None else 0,
                               ctypes.addressof(tuning) if tuning is not None else None, self.extra.data_ptr(),
                               MVF_ENGINE[engine])
+
+    def time_kernel(self, start, end) -> None:
+        """Record the torch.cuda.Events ``start`` and ``end`` (or None, None) around the
+        bounding kernel alone on later launches."""
+        for ev in (start, end):
+            if ev is not None and not ev.cuda_event:
+                ev.record()            # torch creates its event at the first record
+        self.args.kernel_events[0] = start.cuda_event if start is not None else None
+        self.args.kernel_events[1] = end.cuda_event if end is not None else None
 
     def launch(self, stream=None):
         fn = lib().mvf_bound_noalloc if self.noalloc else lib().mvf_bound
