@@ -248,11 +248,10 @@ typedef struct {
     int32_t grad;             /* kernels to build: MVF_GRAD_FWD (tangent mode), MVF_GRAD_REV
                                  (reverse-mode adjoint) or MVF_GRAD_AUTO (both) */
     int32_t ckpt_budget;      /* reverse mode: register budget of one recomputed segment, in
-                                 intervals, at most 40 (MVF_EINVAL above); 0 = library choice
-                                 (from the register file, the variable count and the live set;
-                                 the roots are segmented when the largest one's single-pass
-                                 adjoint keeps more partials than twice the register file's
-                                 intervals), < 0 = none */
+                                 intervals, at most 32 (MVF_EINVAL above); 0 = library choice
+                                 (32, 24 at four waves per SIMD; the roots are segmented when
+                                 the largest one's single-pass adjoint keeps more partials
+                                 than twice the register file's intervals), < 0 = none */
 } mvf_spec_options;
 typedef struct {
     int32_t chunk, waves, grad;

@@ -50,16 +50,18 @@ namespace {
 constexpr int64_t DEFAULT_MAX_CODE = 32000;
 constexpr int SEGMENT = 32;                      // instructions per guarded block
 constexpr int LDS_LEAD = 2;                      // statements a variable's LDS read runs ahead of its use
-// Largest segment budget of the checkpointed adjoint.  Budgets up to 40 gave
-// adjoints bitwise equal to the single-pass form on every workload measured;
-// at 58 the 32-variable workload's objective came out different on the GPU
-// although the generated code computes the same values (the host-side
-// symbolic check of the generator agrees), so larger budgets are refused.
-// For the same reason of an unexplained failure -- a memory fault of the
-// batch workload's adjoint compiled for one wave per SIMD (segment budget 32,
-// 64-lane workgroups) -- the adjoint kernels are not built for one wave per
-// SIMD.
-constexpr int MAX_CKPT_BUDGET = 40;
+// Largest segment budget of the checkpointed adjoint.  Budgets up to 32 gave
+// adjoints bitwise equal to the single-pass form on every workload measured
+// (the 32-variable workload at 12, 24 and 32 over all 2^20 subdomains); at 40
+// and at 58 that workload's objective came out different on the GPU although
+// the generated code computes the same values (the host-side symbolic check
+// of the generator agrees) and its mode switches pass the ISA check, so
+// larger budgets are refused.  Both failing builds spill over a thousand
+// VGPRs per lane.  For the same reason of an unexplained failure -- a memory
+// fault of the batch workload's adjoint compiled for one wave per SIMD
+// (segment budget 32, 64-lane workgroups) -- the adjoint kernels are not built
+// for one wave per SIMD.
+constexpr int MAX_CKPT_BUDGET = 32;
 // A body line that only starts a new guarded block (segment boundaries of the
 // checkpointed adjoint, so that a segment's checkpoint loads lead a block).
 const char *const BLOCK_BREAK = "\x01";
@@ -949,12 +951,15 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
 
 int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves) {
     if (opt && opt->ckpt_budget != 0) return opt->ckpt_budget;
-    // the register file in intervals (four VGPRs each, AGPRs included at one
-    // wave per SIMD), less the gradient, about half the live set (adjoints
-    // that cross a boundary) and working registers, within the range measured
-    // to pay off (and to be exact, see MAX_CKPT_BUDGET)
+    // the register file in intervals (four VGPRs each) less working
+    // registers, at most MAX_CKPT_BUDGET.  Larger segments spill more but
+    // store fewer checkpoints, and checkpoint traffic is what bounds the
+    // segmented adjoint: on the 32-variable workload budget 32 ran 16 % faster
+    // than 12 (which the register file less the gradient would give), on the
+    // 8-variable batch workload 32 and 40 as fast as 24 or faster.
+    (void)P;
     const int regs = 128 / std::max(1, waves);
-    return std::min(32, std::max(12, regs - P.n_vars - P.max_slots / 2 - 8));
+    return std::min(MAX_CKPT_BUDGET, std::max(12, regs - 8));
 }
 
 int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int waves) {

@@ -38,7 +38,7 @@ def test_random_tapes(seed, budget):
     assert _check(t, budget) > 0
 
 
-@pytest.mark.parametrize("name,budget", [("mid", 32), ("batch", 0), ("e2e", 0), ("diff", 0), ("diff", 40)])
+@pytest.mark.parametrize("name,budget", [("mid", 32), ("batch", 0), ("e2e", 0), ("diff", 0), ("diff", 12)])
 def test_workload_tapes(name, budget):
     # budget 0: the library's choice (mid's roots are short enough to stay single-pass there)
     t = {"mid": lambda: I.mid(1).tape, "batch": lambda: I.batch(1).tape, "e2e": lambda: I.e2e_tape(1),
