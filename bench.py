@@ -49,10 +49,12 @@ FP64_ISSUE_PEAK = 256 * 4 * 16 * 2.4e9          # 39.3e12 op/s
 FP64_PUBLISHED_PEAK = 78.6e12
 # HBM bytes per launch from rocprofv3 counters (FETCH_SIZE x 2.00 + WRITE_SIZE x
 # 1.00, the factors from a 256 MiB copy in the same runs), valid only for the
-# kernel build and tape they were taken on: (engine, grad, tape hash) -> bytes,
-# with the profile they come from
-TRAFFIC = {}
-TRAFFIC_SOURCE = {}
+# kernel build and tape they were taken on: (engine, grad, tape hash, code
+# object bytes) -> bytes, with the profile they come from.  A rebuilt kernel
+# of another size finds no entry and reports null.
+TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea", 940184): (18614.7 * 2.0 + 63995.7) * 1024}
+TRAFFIC_SOURCE = {("spec", "fwd", "aa75c5b416e4faea", 940184):
+                  "profiles/mvf_spec_bound_mid.md (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, per dispatch)"}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 PEAK_UNIT = "T FP64 op/s (one VALU issue slot per op, FMA = 1)"
 
@@ -154,22 +156,27 @@ def time_calls(launch, steps: int, warmup: int, stream, prewarm_s: float = 0.0, 
 
 
 def kernel_times(call, steps: int, stream) -> dict:
-    """K more steps of ``call`` (a BoundCall) with HIP events around each step and around
-    each step's bounding kernel alone (recorded by the library on the launch stream)."""
+    """Two more passes of K steps of ``call`` (a BoundCall): one with an event before every
+    step (each step's own time: median and minimum), one with events around every step's
+    bounding kernel alone (recorded by the library on the launch stream).  Each event
+    record costs a few microseconds of the step it sits in."""
     import torch
-    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ks, ke, s0 = mk(), mk(), mk()
-    s1 = torch.cuda.Event(enable_timing=True)
+    mk = lambda k: [torch.cuda.Event(enable_timing=True) for _ in range(k)]
+    s0 = mk(steps + 1)
     torch.cuda.synchronize()
     for i in range(steps):
-        call.time_kernel(ks[i], ke[i])
         s0[i].record(stream)
         call.launch(stream)
-    s1.record(stream)
+    s0[steps].record(stream)
+    torch.cuda.synchronize()
+    st = np.array([s0[i].elapsed_time(s0[i + 1]) for i in range(steps)])
+    ks, ke = mk(steps), mk(steps)
+    for i in range(steps):
+        call.time_kernel(ks[i], ke[i])
+        call.launch(stream)
     torch.cuda.synchronize()
     call.time_kernel(None, None)
     k = np.array([ks[i].elapsed_time(ke[i]) for i in range(steps)])
-    st = np.array([s0[i].elapsed_time(s0[i + 1] if i + 1 < steps else s1) for i in range(steps)])
     return {"mean_ms": float(k.mean()), "median_ms": float(np.median(k)), "min_ms": float(k.min()),
             "step_median_ms": float(np.median(st)), "step_min_ms": float(st.min())}
 
@@ -185,6 +192,27 @@ def ref_ops(st, grad: str, engine: str) -> int:
     if grad == "rev":
         return st.ref_ops_rev
     return st.ref_ops_fwd_sparse if engine == "spec" else st.ref_ops_fwd
+
+
+HBM_PEAK = 8.0e12                               # bytes/s
+
+
+def checkpoint_bytes(tape, grad: str = "rev") -> int:
+    """Bytes per subdomain that the specialised adjoint's checkpoints move by design:
+    every checkpoint interval (16 bytes) stored once and loaded once, summed over the
+    roots (counted in the generated source at the library's default segment budget)."""
+    import re
+
+    from paper_2507_20769_amd import mvf
+    src = mvf.spec_source(tape, grad=grad, max_code=10 ** 7)
+    return 32 * len(re.findall(r"spec_ck_st\(L,", src))
+
+
+def hbm_roofline(bytes_per_sub: int, n_sub: float, seconds: float) -> dict:
+    a = bytes_per_sub * n_sub / seconds
+    return {"bound": "hbm", "achieved": a / 1e12, "peak": HBM_PEAK / 1e12, "unit": "TB/s",
+            "frac": a / HBM_PEAK, "algorithmic_bytes_per_subdomain": bytes_per_sub,
+            "what": "checkpoint stores + loads of the checkpointed adjoint"}
 
 
 def _form(n_sub, seconds, ops, **extra):
@@ -235,6 +263,8 @@ def diff_forms(seed: int) -> dict:
         res[engine] = call.reduced.cpu().numpy()
         out[f"adjoint_{'interpreter' if engine == 'interp' else 'specialised'}"] = _form(
             w.n_sub, ms * 1e-3, st.ref_ops_rev)
+    out["adjoint_specialised"]["hbm_roofline"] = hbm_roofline(checkpoint_bytes(w.tape), w.n_sub,
+                                                              out["adjoint_specialised"]["ms"] * 1e-3)
     out["adjoint_specialised"].update({"checkpoint_intervals_per_lane": info["ckpt_intervals"],
                                        "segment_budget": info["ckpt_budget"], "compile_s": info["seconds"],
                                        "from_cache": bool(info["from_cache"])})
@@ -323,6 +353,8 @@ def batch_forms(seed: int) -> dict:
         out[name] = _form(total, t, ops, kernel_only=_form(total, t_kernel[(grad, engine)], ops),
                           timing="graph replay with staging H2D and result D2H, host clock; kernel_only: HIP "
                                  "events around plan + persistent kernel + per-node finish")
+    out["adjoint_batched_graph_specialised"]["kernel_only"]["hbm_roofline"] = hbm_roofline(
+        checkpoint_bytes(bw.tape), total, t_kernel[("rev", "spec")])
     out["adjoint_batched_graph_specialised"]["hull_endpoints_equal_to_interpreter"] = float(
         np.mean(red_graph[("rev", "spec")] == red_graph[("rev", "interp")]))
     best_plain = min(t_plain.values())
@@ -456,7 +488,7 @@ def main():
     for _ in range(20):
         e2e()
     e2e_ms = (time.perf_counter() - t1) / 20 * 1e3
-    key = (args.engine, args.grad, w.tape.digest())
+    key = (args.engine, args.grad, w.tape.digest(), spec["code_bytes"] if spec else 0)
     kname = {("spec", "fwd"): "mvf_spec_bound", ("spec", "rev"): "mvf_spec_bound_rev",
               ("interp", "fwd"): f"bound_kernel<{st.tangent_chunk},false>",
               ("interp", "rev"): "bound_kernel<0,true>"}[(args.engine, args.grad)]
