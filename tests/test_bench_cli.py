@@ -23,7 +23,9 @@ def test_module_constants_and_defaults(monkeypatch):
     assert abs(b.FP64_ISSUE_PEAK - 39.3216e12) < 1e6
     assert isinstance(b.TRAFFIC, dict)
     for key, val in b.TRAFFIC.items():
-        assert len(key) == 3 and key[0] in ("spec", "interp") and key[1] in ("fwd", "rev") and val > 0
+        # (engine, grad, tape hash, code-object bytes): a rebuilt kernel finds no stale entry
+        assert len(key) == 4 and key[0] in ("spec", "interp") and key[1] in ("fwd", "rev") and val > 0
+        assert isinstance(key[3], int) and key in b.TRAFFIC_SOURCE
     monkeypatch.setattr(sys, "argv", ["bench.py"])
     a = b.parse()
     assert (a.gpus, a.steps, a.warmup, a.engine, a.grad) == (1, 200, 200, "spec", "fwd")
