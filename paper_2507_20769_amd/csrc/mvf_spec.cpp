@@ -247,6 +247,37 @@ class Scheduler {
     }
 };
 
+// Segments of one root program for the checkpointed adjoint: start[j] are
+// program-relative boundaries (start[0] = 0, start[K] = len); in[j] are the
+// instructions (absolute) whose values segment j reads from before it.  The
+// value pass stores each such value once, at the first boundary j in
+// 1 .. K-2 whose segment reads it (store[j]), at checkpoint index slot[pc];
+// a value that one cheap operation makes from variables and constants alone
+// (again[pc - begin]) is not stored but recomputed where a segment reloads
+// it (the same operation on the same operands: the same bits, no traffic).
+// ck_count intervals per lane in all.
+struct SegPlan {
+    std::vector<int> start;
+    std::vector<std::vector<int>> in;
+    std::vector<std::vector<int>> store;
+    std::map<int, int> slot;
+    std::vector<char> again;
+    int ck_count = 0;
+};
+
+// an instruction whose value is recomputed instead of checkpointed: one cheap
+// operation (no division, root or transcendental) on variables and constants
+bool recompute_at_reload(const Dec &I) {
+    switch (I.op) {
+    case I_ADD: case I_SUB: case I_MUL:
+        return I.ak != K_SLOT && I.bk != K_SLOT;
+    case I_SQR: case I_ADDK: case I_KSUB: case I_LOAD: case I_MULK: case I_MULKN:
+        return I.ak != K_SLOT;
+    default:
+        return false;
+    }
+}
+
 // One pass over one root program.  C == 0: values only, variables at the
 // centre (point) or over the subdomain; C > 0: values and the tangent
 // components [c0, c0 + C).  With tape (C == 0 over the subdomain) the value
@@ -284,16 +315,19 @@ class PassWriter {
     // Value pass and reverse sweep with checkpointed recomputation.  The
     // program is cut into segments [start[j], start[j+1]).  A value-only pass
     // runs segments 0 .. K-2 and stores at each boundary start[j] (j >= 1)
-    // the values produced before it that segment j reads (in[j], to the
-    // checkpoint buffer at ck_base[j] ...).  Segment K-1 then runs with its
-    // local partials and is swept at once; every earlier segment, last first,
-    // reloads its inputs, runs again with its partials and is swept.  The
+    // the values produced before it that segment j reads and no earlier
+    // boundary stored (to the checkpoint buffer, one index per value).
+    // Segment K-1 then runs with its local partials and is swept at once;
+    // every earlier segment, last first, reloads its inputs (cheap values of
+    // variables and constants alone are recomputed instead), runs again with
+    // its partials and is swept.  The
     // adjoints of values that cross a boundary stay in variables.  The
     // recomputation repeats the same operations on the same operands, so the
     // result is bitwise that of reverse() after a single value pass; domain
     // tests are made once, in the first pass.  Writes the NIE value to nie.
-    void adjoint(Decls &decl, std::vector<std::string> &body, const std::vector<int> &start,
-                 const std::vector<std::vector<int>> &in, const std::vector<int> &ck_base) {
+    void adjoint(Decls &decl, std::vector<std::string> &body, const SegPlan &S) {
+        const std::vector<int> &start = S.start;
+        const std::vector<std::vector<int>> &in = S.in;
         const RootProg &rp = P.roots[r];
         const int K = (int)start.size() - 1;
         reset_slots();
@@ -303,9 +337,8 @@ class PassWriter {
             if (j >= 1) {
                 body.push_back(BLOCK_BREAK);
                 std::string st;
-                for (size_t e = 0; e < in[j].size(); ++e)
-                    st += "spec_ck_st(L, " + std::to_string(ck_base[j] + (int)e) + ", v" + std::to_string(in[j][e]) +
-                          "); ";
+                for (int p : S.store[j])
+                    st += "spec_ck_st(L, " + std::to_string(S.slot.at(p)) + ", v" + std::to_string(p) + "); ";
                 body.push_back(st);
             }
             snap[j] = save();
@@ -323,11 +356,14 @@ class PassWriter {
             restore(snap[j]);
             body.push_back(BLOCK_BREAK);
             if (j >= 1) {
-                std::string ld;
-                for (size_t e = 0; e < in[j].size(); ++e)
-                    ld += "v" + std::to_string(in[j][e]) + " = spec_ck_ld(L, " + std::to_string(ck_base[j] + (int)e) +
-                          "); ";
-                body.push_back(ld);
+                std::string ld, re;
+                for (int p : in[j]) {
+                    if (S.again[p - rp.begin])
+                        re += value_stmt.at(p);
+                    else
+                        ld += "v" + std::to_string(p) + " = spec_ck_ld(L, " + std::to_string(S.slot.at(p)) + "); ";
+                }
+                body.push_back(ld + re);
             }
             for (int pc = rp.begin + start[j]; pc < rp.begin + start[j + 1]; ++pc) instr(pc, decl, body);
             sweep(decl, body, rp.begin + start[j], rp.begin + start[j + 1]);
@@ -427,6 +463,7 @@ class PassWriter {
     bool point;
     bool partials;                               // compute the local partials (and record the steps)
     const bool lead;                             // place variable reads LDS_LEAD statements early
+    std::map<int, std::string> value_stmt;       // value-pass statements, for recomputation at reload
     int n_hoist = 0;
     bool checks = true;                          // emit the domain tests
     std::vector<std::string> slot_val;
@@ -711,6 +748,7 @@ class PassWriter {
             sch.add(tn[t], Z[t]);
         }
         s += sch.emit();
+        if (!partials && C == 0) value_stmt[pc] = s;
         body.push_back(s);
         ensure(I.d);
         slot_val[I.d] = z;
@@ -738,19 +776,7 @@ void write_guarded(std::string &out, const std::vector<std::string> &body) {
     if (in_block) out += "    }\n";
 }
 
-// Segments of one root program for the checkpointed adjoint: start[j] are
-// program-relative boundaries (start[0] = 0, start[K] = len); in[j] are the
-// instructions (absolute) whose values segment j reads from before it, which
-// the value pass stores at start[j] for j = 1 .. K-2 at checkpoint indices
-// ck_base[j] ...; ck_count intervals per lane in all.
-struct SegPlan {
-    std::vector<int> start;
-    std::vector<std::vector<int>> in;
-    std::vector<int> ck_base;
-    int ck_count = 0;
-};
-
-// Greedy cut: a segment grows while its inputs from earlier segments plus the
+// A segment fits the budget when its inputs from earlier segments plus the
 // values and local partials it computes (an estimate of what its
 // recomputation and sweep keep in registers) stay within budget intervals.
 // budget <= 0: one segment (no recomputation).
@@ -759,15 +785,17 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
     const int len = rp.len;
     std::vector<int> pa(len, -1), pb(len, -1), cost(len, 1);
     std::vector<int> prod(std::max(rp.n_slots, 1) + 1, -1);
+    SegPlan S;
+    S.again.assign(len, 0);
     for (int i = 0; i < len; ++i) {
         const Dec I = decode(P.instr[rp.begin + i]);
+        S.again[i] = recompute_at_reload(I);
         if (I.ak == K_SLOT && I.a < prod.size()) pa[i] = prod[I.a];
         if (I.op <= I_DIV && I.bk == K_SLOT && I.b < prod.size()) pb[i] = prod[I.b];
         if (I.op == I_DIV || (is_unary_fn(I.op) && I.op != I_EXP)) cost[i] = 2;     // 1/V, or the derivative
         if (I.d >= prod.size()) prod.resize(I.d + 1, -1);
         prod[I.d] = rp.begin + i;
     }
-    SegPlan S;
     S.start.push_back(0);
     if (budget <= 0) {
         S.start.push_back(len);
@@ -788,7 +816,7 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
         for (int s = 0; s < len; ++s) {
             if (best[s] >= INF) continue;
             inset.clear();
-            int c = 0;
+            int c = 0, stored = 0;
             for (int e = s; e < len; ++e) {
                 int np[2], k = 0;
                 for (int p : {pa[e], pb[e]})
@@ -796,10 +824,13 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
                         !(k == 1 && np[0] == p))                 // the same value twice counts once
                         np[k++] = p;
                 if (e > s && c + cost[e] + (int)inset.size() + k > budget) break;
-                for (int q = 0; q < k; ++q) inset.push_back(np[q]);
+                for (int q = 0; q < k; ++q) {
+                    inset.push_back(np[q]);
+                    stored += !S.again[np[q] - rp.begin];
+                }
                 c += cost[e];
                 const int end = e + 1;
-                const int64_t w = (s == 0 || end == len) ? 0 : (int64_t)inset.size();
+                const int64_t w = (s == 0 || end == len) ? 0 : (int64_t)stored;
                 const int64_t cand = best[s] + (w << 20) + 1;
                 if (cand < best[end]) {
                     best[end] = cand;
@@ -813,7 +844,7 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
     }
     const int K = (int)S.start.size() - 1;
     S.in.assign(K, {});
-    S.ck_base.assign(K, 0);
+    S.store.assign(K, {});
     for (int j = 0; j < K; ++j) {
         auto &v = S.in[j];
         for (int i = S.start[j]; i < S.start[j + 1]; ++i)
@@ -821,10 +852,12 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
                 if (p >= 0 && p < rp.begin + S.start[j]) v.push_back(p);
         std::sort(v.begin(), v.end());
         v.erase(std::unique(v.begin(), v.end()), v.end());
-        if (j >= 1 && j + 1 < K) {
-            S.ck_base[j] = S.ck_count;
-            S.ck_count += (int)v.size();
-        }
+        if (j >= 1 && j + 1 < K)
+            for (int p : v)
+                if (!S.again[p - rp.begin] && !S.slot.count(p)) {
+                    S.slot[p] = S.ck_count++;
+                    S.store[j].push_back(p);
+                }
     }
     return S;
 }
@@ -846,7 +879,7 @@ int write_adjoint(std::string &out, const Compiled &P, int r, const std::string 
         body.push_back(w.zero_gradient());
         w.reverse(decl, body);
     } else {
-        w.adjoint(decl, body, S.start, S.in, S.ck_base);
+        w.adjoint(decl, body, S);
         ret = "nie";
     }
     out += "__device__ __forceinline__ Iv " + name + "(const SpecLane &L, bool go, uint32_t &bad, Iv (&G)[" +

@@ -61,6 +61,7 @@ class Machine:
         self.ck: Dict[str, int] = {}
         self.ck_stores = 0
         self.ck_loads = 0
+        self.ck_loaded = set()
 
     def eval(self, expr: str) -> int:
         expr = expr.strip()
@@ -100,6 +101,7 @@ class Machine:
                 raise KeyError(f"checkpoint {key} loaded before it was stored")
             self.env[lhs] = self.ck[key]
             self.ck_loads += 1
+            self.ck_loaded.add(key)
             return
         self.env[lhs] = self.eval(rhs)
 

@@ -5,7 +5,8 @@ Both are generated as straight-line device code; executing them symbolically
 nodes) must give every root's returned value and every gradient component the
 same expression node -- the same operations on the same operands in the same
 order, hence the same bits on any device -- while the checkpointed form
-stores each checkpoint before it is loaded and loads each one it stores.
+stores each checkpoint index once, before it is loaded, and loads each one it
+stores.
 Host only (the generator's source through mvf_spec_source, nothing compiled)."""
 import pytest
 
@@ -27,7 +28,9 @@ def _check(tape, budget, waves=2):
         assert ra == rb, f"root {r}: value differs"
         assert ga == gb, f"root {r}: gradient components {[i for i in range(tape.n_vars) if ga[i] != gb[i]]} differ"
         assert all(x >= 0 for x in gb), f"root {r}: a gradient component is never written"
-        assert Mb.ck_stores == Mb.ck_loads == len(Mb.ck)
+        # every checkpoint index is stored once (no value overwrites another) and read at least
+        # once; a value several segments read is stored once and loaded by each of them
+        assert Mb.ck_stores == len(Mb.ck) == len(Mb.ck_loaded) <= Mb.ck_loads
         stores += Mb.ck_stores
     return stores
 
