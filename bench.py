@@ -199,13 +199,14 @@ HBM_PEAK = 8.0e12                               # bytes/s
 
 def checkpoint_bytes(tape, grad: str = "rev") -> int:
     """Bytes per subdomain that the specialised adjoint's checkpoints move by design:
-    every checkpoint interval (16 bytes) stored once and loaded once, summed over the
-    roots (counted in the generated source at the library's default segment budget)."""
+    16 bytes per checkpoint interval stored and per interval loaded (a value several
+    segments read is stored once and loaded by each), summed over the roots (counted in
+    the generated source at the library's default segment budget)."""
     import re
 
     from paper_2507_20769_amd import mvf
     src = mvf.spec_source(tape, grad=grad, max_code=10 ** 7)
-    return 32 * len(re.findall(r"spec_ck_st\(L,", src))
+    return 16 * (len(re.findall(r"spec_ck_st\(L,", src)) + len(re.findall(r"spec_ck_ld\(L,", src)))
 
 
 def hbm_roofline(bytes_per_sub: int, n_sub: float, seconds: float) -> dict:
