@@ -46,7 +46,8 @@ struct Iv {
 // denormal bits of the same register), so a switch needs no wait states
 // around it.  Two MODE writes need two wait states between them; every switch
 // pair here encloses or is followed by at least two VALU instructions (the
-// build checks the compiled kernels for this).
+// build checks the compiled interpreter kernels for this on every path, a
+// test the compiled code of generated specialised kernels).
 __device__ __forceinline__ void mode_round_down() {
     asm volatile("s_setreg_imm32_b32 hwreg(HW_REG_MODE, 2, 2), 2" ::: "memory");
 }

@@ -123,3 +123,16 @@ def test_points_entry_points_reject_bad_arguments_without_device():
     assert L.mvf_eval_points(None, 1, None, None, None, None, 0, None) == -1
     assert L.mvf_vjp_points(None, 1, None, None, None, None, None, 0, None) == -1
     assert L.mvf_gradient_boxes(None, 1, None, 0, 0, None, None, None, 0, None) == -1
+
+
+def test_batched_entry_points_refuse_host_tensors():
+    # the batched kernels read boxes and splits through raw device pointers: host tensors (or
+    # tensors on two devices) are refused in the binding before any pointer reaches the library
+    import torch
+    cpu_boxes = torch.zeros((2, 1, 2), dtype=torch.float64)
+    cpu_splits = torch.ones((2, 1), dtype=torch.int32)
+    for fn in (lambda: mvf.BatchCall(None, cpu_boxes, cpu_splits),
+               lambda: mvf.autotune(None, cpu_boxes, cpu_splits),
+               lambda: mvf.bound_batch(None, cpu_boxes, cpu_splits)):
+        with pytest.raises(ValueError, match="must be a GPU tensor"):
+            fn()

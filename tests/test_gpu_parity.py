@@ -17,6 +17,21 @@ pytestmark = pytest.mark.gpu
 MODES = {"nie": O.MODE_NIE, "mvf": O.MODE_MVF, "both": O.MODE_BOTH}
 
 
+def _check_enclosure(tape, box, splits, per_sub, sc, n_sub=16, n_pts=8):
+    # the GPU's bounds of seeded subdomains contain the function at points drawn in them
+    # (round-to-nearest point evaluation: a slack of 1e-9 of the root's scale)
+    rng = np.random.default_rng(123)
+    S = per_sub.shape[2]
+    for k in rng.choice(S, min(S, n_sub), replace=False):
+        X, _ = O.subdomain(box, np.asarray(splits), int(k))
+        pts = X[:, 0] + (X[:, 1] - X[:, 0]) * rng.random((n_pts, X.shape[0]))
+        f = I.eval_points_np(tape, pts)                          # [n_pts, m]
+        for r in range(per_sub.shape[0]):
+            lo, hi = per_sub[r, 0, k], per_sub[r, 1, k]
+            tol = 1e-9 * sc[r]
+            assert np.all(f[:, r] >= lo - tol) and np.all(f[:, r] <= hi + tol), f"subdomain {k} root {r}"
+
+
 def _compare(tape, box, splits, mode="both", per_sub=True):
     print(f"[case] n={tape.n_vars} nodes={tape.n_nodes} splits={list(splits)} mode={mode}", flush=True)
     g = gpu_bound(tape, box, splits, mode=mode, per_sub=per_sub)
@@ -31,6 +46,7 @@ def _compare(tape, box, splits, mode="both", per_sub=True):
         assert np.array_equal(g["reduced"][:, 1], g["per_sub"][:, 1, :].max(axis=1))
         lo0 = g["per_sub"][0, 0, :]
         assert int(g["argmin"][0]) == int(np.argmax(lo0 == lo0.min()))
+        _check_enclosure(tape, box, splits, g["per_sub"], sc)
     assert_parity(g["reduced"], o["reduced"], exact, sc, "reduced")
     if exact:
         assert int(g["argmin"][0]) == o["argmin"]
