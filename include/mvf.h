@@ -88,8 +88,10 @@ enum { MVF_GRAD_FWD = 0, MVF_GRAD_REV = 1, MVF_GRAD_AUTO = 2 };
 /*
  * Validate the tape (SSA order, opcodes, operand ranges, finite constants,
  * roots), compile one register program per root (its cone in index order,
- * with slots assigned by linear-scan liveness) and upload it to the current
- * device.  Host arrays are copied; the library owns *out.
+ * with slots assigned by linear-scan liveness), choose the tangent chunk,
+ * plan the adjoint's checkpoints (reported by mvf_tape_stats_get) and upload
+ * the programs to the current device.  Host arrays are copied; the library
+ * owns *out.
  * Returns MVF_ETAPE for a malformed tape, MVF_ELIMIT when a limit above is
  * exceeded or a root needs more register slots than the slot file holds.
  */
@@ -107,6 +109,11 @@ typedef struct {
     int64_t ref_ops_rev;      /* reference FP64 op count per subdomain, reverse mode */
     int64_t ref_ops_fwd_sparse;   /* forward mode without the structurally zero tangent components
                                      (what the specialised kernels compute) */
+    /* the checkpoint plan of the specialised adjoint (Sec. 3.2's DAG in
+     * reverse), at the library's segment budget for two waves per SIMD: */
+    int32_t ckpt_segments;    /* segments over all roots (a root kept in one pass counts one) */
+    int32_t ckpt_stored;      /* checkpoint intervals the value pass stores per subdomain */
+    int32_t ckpt_loaded;      /* checkpoint intervals the reverse sweep loads per subdomain */
 } mvf_tape_stats;
 int mvf_tape_check(const mvf_node *nodes, int32_t n_nodes, const double *consts, int32_t n_consts,
                    int32_t n_vars, const int32_t *roots, int32_t n_roots, mvf_tape_stats *stats);

@@ -128,6 +128,7 @@ void fill_stats(const Compiled &C, mvf_tape_stats *st) {
     st->ref_ops_fwd = C.ref_fwd;
     st->ref_ops_rev = C.ref_rev;
     st->ref_ops_fwd_sparse = C.ref_fwd_sparse;
+    spec_ckpt_plan_stats(C, &st->ckpt_segments, &st->ckpt_stored, &st->ckpt_loaded);
 }
 
 TapeArgs tape_args(const mvf_tape *t, int mode, int chunk) {

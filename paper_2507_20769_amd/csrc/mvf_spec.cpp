@@ -1015,8 +1015,9 @@ int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves) 
     // registers, at most MAX_CKPT_BUDGET.  Larger segments spill more but
     // store fewer checkpoints, and checkpoint traffic is what bounds the
     // segmented adjoint: on the 32-variable workload budget 32 ran 16 % faster
-    // than 12 (which the register file less the gradient would give), on the
-    // 8-variable batch workload 32 and 40 as fast as 24 or faster.
+    // than 12 (which the register file less the gradient would give), and
+    // with the shortest-path cuts within 4 % of 24 and 28; on the 8-variable
+    // batch workload 32 ran faster than 20, 24 and 28.
     (void)P;
     const int regs = 128 / std::max(1, waves);
     return std::min(MAX_CKPT_BUDGET, std::max(12, regs - 8));
@@ -1030,6 +1031,20 @@ int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int wa
     // explicit budget segments every root.
     if (opt && opt->ckpt_budget != 0) return 0;
     return P.max_rec > 2 * 128 / std::max(1, waves) ? 0 : INT32_MAX;
+}
+
+void spec_ckpt_plan_stats(const Compiled &P, int32_t *segments, int32_t *stored, int32_t *loaded) {
+    const int waves = 2;
+    const int budget = spec_ckpt_budget(P, nullptr, waves), min_records = spec_ckpt_min_records(P, nullptr, waves);
+    *segments = *stored = *loaded = 0;
+    for (int r = 0; r < (int)P.roots.size(); ++r) {
+        const SegPlan S = plan_segments(P, r, P.roots[r].n_rec > min_records ? budget : -1);
+        const int K = (int)S.start.size() - 1;
+        *segments += K;
+        *stored += S.ck_count;
+        for (int j = 1; j + 1 < K; ++j)
+            for (int p : S.in[j]) *loaded += !S.again[p - P.roots[r].begin];
+    }
 }
 
 std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int ckpt_budget, int min_records,

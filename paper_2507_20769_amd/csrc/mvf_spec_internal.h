@@ -16,6 +16,9 @@ int spec_plan(const Compiled &P, const mvf_spec_options *opt, int *chunk, int64_
 // and the record count above which a root is segmented (INT32_MAX: none).
 int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves);
 int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int waves);
+// The checkpoint plan of the adjoint at the library's choices (two waves per
+// SIMD): segments over all roots, intervals stored and loaded per subdomain.
+void spec_ckpt_plan_stats(const Compiled &P, int32_t *segments, int32_t *stored, int32_t *loaded);
 
 // The generated device source (compiled with the embedded device headers):
 // forward kernels (grad FWD), reverse-mode kernels (REV) or both (AUTO).

@@ -40,7 +40,8 @@ class TapeStats(ctypes.Structure):
     _fields_ = [("n_vars", ctypes.c_int32), ("n_roots", ctypes.c_int32), ("n_instr", ctypes.c_int32),
                 ("max_slots", ctypes.c_int32), ("tangent_chunk", ctypes.c_int32), ("max_records", ctypes.c_int32),
                 ("ref_ops_fwd", ctypes.c_int64), ("ref_ops_rev", ctypes.c_int64),
-                ("ref_ops_fwd_sparse", ctypes.c_int64)]
+                ("ref_ops_fwd_sparse", ctypes.c_int64), ("ckpt_segments", ctypes.c_int32),
+                ("ckpt_stored", ctypes.c_int32), ("ckpt_loaded", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

@@ -191,3 +191,20 @@ def test_adjoint_settings_outside_the_verified_range_are_refused():
         assert e.value.code == -1, kw
     assert mvf.spec_source(t, grad="fwd", waves=1)                 # tangent mode alone is built at one wave
     assert mvf.spec_source(t, grad="rev", ckpt_budget=32)
+
+
+@pytest.mark.parametrize("name", ["mid", "batch", "diff"])
+def test_tape_stats_report_the_generated_checkpoint_plan(name):
+    # the plan that mvf_tape_check / mvf_tape_stats_get report at load is the one the
+    # generator writes: segments, intervals stored by the value pass and loaded by the sweep
+    import re
+    t = {"mid": lambda: I.mid(1).tape, "batch": lambda: I.batch(1).tape, "diff": lambda: I.diff(1).tape}[name]()
+    st = mvf.check(t)
+    src = mvf.spec_source(t, grad="rev", max_code=10 ** 7)
+    segs = sum(int(k) for k, _ in re.findall(r"// (\d+) segment\(s\), (\d+) checkpoint intervals", src))
+    assert (st.ckpt_segments, st.ckpt_stored, st.ckpt_loaded) == (
+        segs, len(re.findall(r"spec_ck_st\(L,", src)), len(re.findall(r"spec_ck_ld\(L,", src)))
+    if name == "mid":
+        assert st.ckpt_stored == 0 and st.ckpt_segments == t.n_roots      # short roots: one pass each
+    else:
+        assert st.ckpt_loaded >= st.ckpt_stored > 0
