@@ -41,6 +41,18 @@ def test_random_tapes(seed, budget):
     assert _check(t, budget) > 0
 
 
+def test_reloads_recompute_cheap_values_and_share_stores():
+    # the checked plans do exercise both economies: some reloaded inputs are recomputed from
+    # variables and constants instead of loaded, and some stored value is loaded by more than
+    # one segment (one store, several loads)
+    import re
+    t = I.random_small_tape(2, n=4, ops=150, n_con=2, con_ops=40, window=8)
+    src = mvf.spec_source(t, grad="rev", ckpt_budget=6)
+    reload_lines = [ln for ln in src.splitlines() if "spec_ck_ld" in ln]
+    assert sum(len(re.findall(r"v\d+ = (?!spec_ck_ld)\w+\(", ln)) for ln in reload_lines) > 0
+    assert len(re.findall(r"spec_ck_ld\(L,", src)) > len(re.findall(r"spec_ck_st\(L,", src))
+
+
 @pytest.mark.parametrize("name,budget", [("mid", 32), ("batch", 0), ("e2e", 0), ("diff", 0), ("diff", 12)])
 def test_workload_tapes(name, budget):
     # budget 0: the library's choice (mid's roots are short enough to stay single-pass there)
