@@ -13,6 +13,7 @@ one second more, untimed, so that the clocks reach their sustained level.
 The same JSON line carries the other forms, each with its own roofline
 fraction (algorithmic FP64 ops per second over the FP64 issue rate):
   * mid: forward and adjoint, interpreter and specialised kernels;
+  * tiny (2 variables, 4,096 subdomains): forward mode per call (launch-bound);
   * diff (32 variables, 2^20 subdomains): the adjoint, interpreter (record
     tape) and specialised (checkpointed recomputation);
   * batch (512 B&B-like nodes of [-3,3]^8, 2^10..2^18 subdomains each, a
@@ -70,7 +71,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="oracle time per CPU-baseline leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="headline only (used under the profiler)")
-    ap.add_argument("--forms", default="mid,diff,batch,bnb", help="comma list of the forms to run")
+    ap.add_argument("--forms", default="mid,tiny,diff,batch,bnb", help="comma list of the forms to run")
     ap.add_argument("--bnb-nodes", type=int, default=10000, help="B&B node limit of the e2e comparison (0: skip)")
     ap.add_argument("--engine", choices=["spec", "interp"], default="spec",
                     help="headline kernel: the tape's specialised kernel or the interpreter")
@@ -240,6 +241,29 @@ def mid_forms(seed: int, mid_tape) -> dict:
             ms = time_calls(call.launch, 100, 100, stream)
             name = {"fwd": "forward", "rev": "adjoint"}[grad] + {"interp": "_interpreter", "spec": "_specialised"}[engine]
             out[f"mid_{name}"] = _form(w.n_sub, ms * 1e-3, ref)
+    return out
+
+
+def tiny_forms(seed: int) -> dict:
+    """The tiny workload (2 variables, 64 x 64 = 4,096 subdomains): one launch is a few
+    microseconds of work, so this form measures the per-call latency of the path."""
+    import torch
+
+    from paper_2507_20769_amd import inputs as I
+    from paper_2507_20769_amd import mvf
+    stream = torch.cuda.current_stream()
+    w = I.tiny(seed)
+    h = mvf.Tape(w.tape)
+    st = h.stats()
+    info = h.specialize(grad="fwd")
+    box = torch.tensor(w.box, device="cuda")
+    out = {"subdomains": w.n_sub, "specialisation_compile_s": info["seconds"]}
+    for engine in ("interp", "spec"):
+        call = mvf.BoundCall(h, box, w.splits, mode="both", grad="fwd", engine=engine)
+        ms = time_calls(call.launch, 200, 200, stream)
+        out["forward_" + ("interpreter" if engine == "interp" else "specialised")] = _form(
+            w.n_sub, ms * 1e-3, ref_ops(st, "fwd", engine), note="launch-bound: bounding + finish kernel per call")
+    h.close()
     return out
 
 
@@ -538,6 +562,8 @@ def main():
         out["forms"] = {}
         if "mid" in forms and args.workload == "mid":
             out["forms"].update(mid_forms(args.seed, tape))
+        if "tiny" in forms:
+            out["forms"]["tiny"] = tiny_forms(args.seed)
         if "diff" in forms:
             out["forms"]["diff"] = diff_forms(args.seed)
         if "batch" in forms:
