@@ -36,6 +36,7 @@ struct mvf_tape {
     hipFunction_t spec_batch_fn[2] = {nullptr, nullptr};  // batched
     mvf_spec_info spec_info{};
     int32_t spec_ck = 0;                    // checkpoint intervals per lane of the specialised adjoint
+    int32_t spec_gl = 0;                    // gradient components per lane its kernels keep in LDS
     uint64_t spec_id = 0;                   // which specialisation (0: none), for the autotuner's cache
 };
 
@@ -357,7 +358,7 @@ int launch_batched(const mvf_tape *t, int mode, int chunk, bool rev, bool spec, 
                    int block, int max_nodes, hipStream_t stream) {
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
     if (spec) {
-        const size_t lds = spec_lds_bytes(BATCH_TAB_CAP, m);
+        const size_t lds = spec_lds_bytes(BATCH_TAB_CAP, m, rev ? t->spec_gl : 0);
         HIP_TRY(launch_batch_plan(A, stream));
         BatchKArgs K{tape_args(t, mode, 0), A};
         void *params[] = {&K};
@@ -562,7 +563,7 @@ int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_b
                        "workspace too small: the call needs " + std::to_string(L.total) + " bytes, " +
                            std::to_string(ws_bytes) + " given");
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
-    const size_t lds = spec ? spec_lds_bytes(tt, m)
+    const size_t lds = spec ? spec_lds_bytes(tt, m, rev ? t->spec_gl : 0)
                             : lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");
 
@@ -677,6 +678,7 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     const int grad = opt ? opt->grad : MVF_GRAD_FWD;
     const int budget = spec_ckpt_budget(t->C, opt, waves);
     int ck = 0;
+    const int gl = grad == MVF_GRAD_FWD ? 0 : spec_gl_count(t->C, waves);    // the generator's N_GL
     const std::string src =
         spec_source(t->C, chunk, waves, grad, budget, spec_ckpt_min_records(t->C, opt, waves), &ck, &units);
     // the target without its feature suffix (":sramecc+:xnack-"): one code object
@@ -701,6 +703,7 @@ int mvf_tape_specialize(mvf_tape *t, const mvf_spec_options *opt, mvf_spec_info 
     if (t->spec_mod) hipModuleUnload(t->spec_mod);
     t->spec_mod = mod;
     t->spec_ck = grad == MVF_GRAD_FWD ? 0 : ck;
+    t->spec_gl = gl;
     {
         static std::atomic<uint64_t> serial{0};
         t->spec_id = ++serial;

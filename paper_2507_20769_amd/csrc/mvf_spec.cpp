@@ -286,8 +286,8 @@ bool recompute_at_reload(const Dec &I) {
 // adjoint() emits the checkpointed form of both.
 class PassWriter {
   public:
-    PassWriter(const Compiled &Cp, int root, int C, int c0, bool point, bool tape = false)
-        : P(Cp), r(root), C(C), c0(c0), point(point), partials(tape), lead(!tape) {}
+    PassWriter(const Compiled &Cp, int root, int C, int c0, bool point, bool tape = false, int gl = 0)
+        : P(Cp), r(root), C(C), c0(c0), point(point), partials(tape), lead(!tape), gl_base(Cp.n_vars - gl) {}
 
     // body lines (declarations first, then guarded blocks) and the names of
     // the result's value and components
@@ -381,7 +381,17 @@ class PassWriter {
 
     std::string zero_gradient() const {
         std::string s;
-        for (int i = 0; i < P.n_vars; ++i) s += "G[" + std::to_string(i) + "] = kZero; ";
+        for (int i = 0; i < P.n_vars; ++i) s += grad_ref(i) + " = kZero; ";
+        return s;
+    }
+    // gradient component i: a register, or its LDS entry
+    std::string grad_ref(int i) const {
+        return i < gl_base ? "G[" + std::to_string(i) + "]" : "spec_gl(L, " + std::to_string(i - gl_base) + ")";
+    }
+    // the LDS-resident components copied into the register array the caller combines
+    std::string gradient_out() const {
+        std::string s;
+        for (int i = gl_base; i < P.n_vars; ++i) s += "G[" + std::to_string(i) + "] = " + grad_ref(i) + "; ";
         return s;
     }
 
@@ -404,7 +414,7 @@ class PassWriter {
                     if (init) s += y + " = " + (neg ? "ineg(" + c + ")" : c) + "; ";
                     else s += y + " = " + (neg ? "isub(" : "iadd(") + y + ", " + c + "); ";
                 } else if (kind == K_VAR) {
-                    const std::string g = "G[" + std::to_string(a) + "]";
+                    const std::string g = grad_ref((int)a);
                     s += g + " = " + (neg ? "isub(" : "iadd(") + g + ", " + c + "); ";
                 }
             };
@@ -471,6 +481,7 @@ class PassWriter {
     bool point;
     bool partials;                               // compute the local partials (and record the steps)
     const bool lead;                             // place variable reads LDS_LEAD statements early
+    const int gl_base;                           // gradient components from here on live in LDS
     std::map<int, std::string> value_stmt;       // value-pass statements, for recomputation at reload
     int n_hoist = 0;
     bool checks = true;                          // emit the domain tests
@@ -874,11 +885,11 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
 // (checkpointed when the plan has several segments): returns the NIE value,
 // G[0..n) receives the interval gradient.  Returns the checkpoint intervals
 // per lane the function uses.
-int write_adjoint(std::string &out, const Compiled &P, int r, const std::string &name, int budget,
+int write_adjoint(std::string &out, const Compiled &P, int r, const std::string &name, int budget, int gl,
                   int64_t *units) {
     Decls decl;
     std::vector<std::string> body;
-    PassWriter w(P, r, 0, 0, false, true);
+    PassWriter w(P, r, 0, 0, false, true, gl);
     const SegPlan S = plan_segments(P, r, budget);
     std::string ret;
     if (S.start.size() <= 2) {
@@ -894,6 +905,7 @@ int write_adjoint(std::string &out, const Compiled &P, int r, const std::string 
            std::to_string(P.n_vars) + "]) {\n";
     out += "    // " + std::to_string(S.start.size() - 1) + " segment(s), " + std::to_string(S.ck_count) +
            " checkpoint intervals\n";
+    body.push_back(w.gradient_out());
     for (const auto &d : decl.v) out += "    " + d + "\n";
     write_guarded(out, body);
     out += "    return " + ret + ";\n}\n";
@@ -1059,7 +1071,8 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
     if (fwd) s += "#define MVF_SPEC_FWD 1\n";
     if (rev) s += "#define MVF_SPEC_REV 1\n";
     s += "#include \"mvf_spec.h\"\nnamespace mvf {\nnamespace dev {\nnamespace spec {\n";
-    s += "constexpr int N_VARS = " + std::to_string(n) + ", N_ROOTS = " + std::to_string(m) + ";\n";
+    s += "constexpr int N_VARS = " + std::to_string(n) + ", N_ROOTS = " + std::to_string(m) +
+         ", N_GL = " + std::to_string(rev ? spec_gl_count(P, waves) : 0) + ";\n";
     s += "template <bool REV>\n__device__ uint32_t lane(const SpecLane &L, int mode, bool go, const LaneOut &o, "
          "FeasTrack &F);\n";
     std::vector<std::vector<bool>> zero(m, std::vector<bool>(n));     // structurally zero gradient components
@@ -1077,7 +1090,8 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
             }
         if (rev)
             ck = std::max(ck, write_adjoint(s, P, r, "adjoint_" + std::to_string(r),
-                                            P.roots[r].n_rec > min_records ? ckpt_budget : -1, &u));
+                                            P.roots[r].n_rec > min_records ? ckpt_budget : -1,
+                                            spec_gl_count(P, waves), &u));
     }
     if (rev) {
         // every root in turn, as the interpreter's bound_lane with the reverse-mode adjoint
@@ -1254,11 +1268,25 @@ int spec_compile(const std::string &src, const std::string &arch, bool use_cache
     return MVF_OK;
 }
 
-size_t spec_lds_bytes(int tab_total, int m) {
+size_t spec_lds_bytes(int tab_total, int m, int gl) {
     size_t b = (size_t)tab_total * 32;
     b += ((size_t)(BLK / 64) * (2 * m + 5) * 8 + 15) & ~(size_t)15;
     b += (2 * MVF_MAX_VARS + 8) * 4;
+    if (gl > 0) b = ((b + 15) & ~(size_t)15) + (size_t)gl * BLK * 16;
     return b;
+}
+
+int spec_gl_count(const Compiled &P, int waves) {
+    // Tapes whose adjoint the library segments (section on MAX_CKPT_BUDGET):
+    // with up to 12 variables the whole gradient fits in LDS beside the
+    // tables (12 x 256 lanes x 16 bytes = 48 KB per workgroup, two workgroups
+    // per CU at two waves per SIMD).  On the 8-variable batch workload this
+    // freed the 32 VGPRs that the kernels spilled (no scratch left): 38.5 ms
+    // steadily against 39.6-49 ms; the 10-variable workload ran the same; the
+    // 6-variable mid tape, kept in one pass, ran 4 % slower, and moving 8 or 12
+    // of the 32-variable workload's components changed nothing.
+    const bool segmented = spec_ckpt_min_records(P, nullptr, waves) == 0;
+    return waves <= 2 && segmented && P.n_vars <= 12 ? P.n_vars : 0;
 }
 
 }  // namespace mvf

@@ -24,7 +24,13 @@ struct SpecLane {
     int vi[MVF_MAX_VARS];
     double2 *ck;
     int64_t ck_stride;
+    Iv *gl;                 // the lane's gradient components kept in LDS (adjoint kernels)
+    int gl_stride;
 };
+
+// gradient component i of the LDS-resident block of the adjoint's gradient
+// (lane-interleaved: entry i of the lane sits i * gl_stride entries after its first)
+__device__ __forceinline__ Iv &spec_gl(const SpecLane &L, int i) { return L.gl[i * L.gl_stride]; }
 
 // checkpoint entry i of the lane (stored at a segment boundary, reloaded
 // before the segment is recomputed)

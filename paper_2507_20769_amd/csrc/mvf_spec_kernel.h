@@ -18,6 +18,16 @@ namespace dev {
 
 // The workgroup is blockDim.x = 64, 128 or 256 lanes (one to four waves; a
 // launch-time choice of the autotuner); LDS is laid out for up to four waves.
+// LDS after the breakpoint table, the reduction records and the splits: the
+// adjoint's LDS-resident gradient components (spec::N_GL of them per lane, for
+// up to BLK lanes), 16-byte aligned
+__device__ __forceinline__ size_t spec_gl_offset(int tab_total, int m) {
+    size_t b = (size_t)tab_total * 32;
+    b += ((size_t)(BLK / 64) * wred_len(m) * 8 + 15) & ~(size_t)15;
+    b += (2 * MVF_MAX_VARS + 8) * 4;
+    return (b + 15) & ~(size_t)15;
+}
+
 template <bool REV>
 __device__ __forceinline__ void spec_bound_body() {
     constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
@@ -50,6 +60,8 @@ __device__ __forceinline__ void spec_bound_body() {
         L.tab = tab;
         L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * blk + tid;
         L.ck_stride = (int64_t)gridDim.x * blk;
+        L.gl = reinterpret_cast<Iv *>(smem + spec_gl_offset(tab_total, m)) + tid;
+        L.gl_stride = blk;
         int64_t q = active ? k : S - 1;
 #pragma unroll
         for (int i = 0; i < n; ++i) {            // dimension 0 fastest (Sec. 3.1.1)
@@ -154,6 +166,8 @@ __device__ __forceinline__ void spec_batch_body() {
             L.tab = tab;
             L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * blk + tid;
             L.ck_stride = (int64_t)gridDim.x * blk;
+            L.gl = reinterpret_cast<Iv *>(smem + spec_gl_offset(tab_cap, m)) + tid;
+            L.gl_stride = blk;
             int64_t q = active ? k : S - 1;
 #pragma unroll
             for (int i = 0; i < n; ++i) {

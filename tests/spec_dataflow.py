@@ -52,6 +52,9 @@ def _call(expr: str):
     return m.group(1), _split_top(m.group(2), ",")
 
 
+_GL = re.compile(r"^spec_gl\(L,\s*\d+\)$")
+
+
 class Machine:
     """One execution: variable bindings and the lane's checkpoint buffer."""
 
@@ -65,6 +68,11 @@ class Machine:
 
     def eval(self, expr: str) -> int:
         expr = expr.strip()
+        if _GL.match(expr):                 # an LDS-resident gradient component: a variable
+            expr = re.sub(r"\s+", "", expr)
+            if expr not in self.env:
+                raise KeyError(f"read of unassigned variable {expr!r}")
+            return self.env[expr]
         c = _call(expr)
         if c is None:
             if expr in self.env:
@@ -94,6 +102,8 @@ class Machine:
             return
         lhs, rhs = s.split("=", 1)
         lhs, rhs = lhs.strip(), rhs.strip()
+        if _GL.match(lhs):
+            lhs = re.sub(r"\s+", "", lhs)
         lc = _call(rhs)
         if lc is not None and lc[0] == "spec_ck_ld":
             key = lc[1][1]
