@@ -167,7 +167,11 @@ constexpr int MAX_GRID = 2048;
 
 int single_grid(const mvf_tape *t, int64_t S, bool rev) {
     const int64_t need = (S + BLK - 1) / BLK;
-    const int cap = rev ? 2 * t->n_cu : MAX_GRID;       // the reverse tape scales with the grid
+    // reverse mode: as many workgroups as the CUs hold at once (the record tape or
+    // the checkpoint buffer scales with the grid): two per CU, or as many waves per
+    // SIMD as the specialised adjoint is compiled for
+    const int per_cu = t->spec_fn[1] ? std::max(2, t->spec_info.waves) : 2;
+    const int cap = rev ? per_cu * t->n_cu : MAX_GRID;
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, cap));
 }
 
