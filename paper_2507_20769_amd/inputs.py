@@ -95,6 +95,24 @@ class Tape:
         return {OP_NAMES[k]: int(np.count_nonzero(ops == k)) for k in range(len(OP_NAMES))}
 
 
+def save_tape(tape: Tape, path: str) -> None:
+    """Write a tape as an uncompressed .npz: nodes (op, a, b as int32 columns), consts
+    (float64), roots (int32) and n_vars; read back with load_tape (no pickled objects)."""
+    np.savez(path, op=np.ascontiguousarray(tape.nodes["op"], dtype="<i4"),
+             a=np.ascontiguousarray(tape.nodes["a"], dtype="<i4"), b=np.ascontiguousarray(tape.nodes["b"], dtype="<i4"),
+             consts=np.ascontiguousarray(tape.consts, dtype="<f8"), roots=np.ascontiguousarray(tape.roots, dtype="<i4"),
+             n_vars=np.int64(tape.n_vars))
+
+
+def load_tape(path: str) -> Tape:
+    """A tape written by save_tape (plain arrays only: allow_pickle stays off)."""
+    with np.load(path, allow_pickle=False) as z:
+        nodes = np.empty(z["op"].shape[0], dtype=NODE_DTYPE)
+        nodes["op"], nodes["a"], nodes["b"] = z["op"], z["a"], z["b"]
+        return Tape(nodes, np.array(z["consts"], dtype=np.float64), np.array(z["roots"], dtype=np.int32),
+                    int(z["n_vars"]))
+
+
 class TapeBuilder:
     """Append-only SSA tape with hash-consed VAR leaves per function."""
 

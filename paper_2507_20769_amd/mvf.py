@@ -281,6 +281,12 @@ class Tape:
         self.n_vars = int(tape.n_vars)
         self.n_roots = int(tape.n_roots)
 
+    @classmethod
+    def from_file(cls, path: str) -> "Tape":
+        """A tape file written by inputs.save_tape (.npz of plain arrays), compiled and uploaded."""
+        from . import inputs
+        return cls(inputs.load_tape(path))
+
     def set_root_kinds(self, kinds):
         """Root kinds: 0 objective/unconstrained, 1 inequality g <= 0, 2 equality h = 0 (root 0: 0)."""
         self._kinds = None if kinds is None else np.ascontiguousarray(kinds, dtype=np.int32)

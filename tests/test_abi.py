@@ -136,3 +136,18 @@ def test_batched_entry_points_refuse_host_tensors():
                lambda: mvf.bound_batch(None, cpu_boxes, cpu_splits)):
         with pytest.raises(ValueError, match="must be a GPU tensor"):
             fn()
+
+
+def test_tape_files_round_trip(tmp_path):
+    # a tape written to a file and read back is the same tape (digest, every array) and
+    # validates to the same statistics on the host
+    from paper_2507_20769_amd import inputs as I
+    t = I.mid(1).tape
+    path = str(tmp_path / "mid.npz")
+    I.save_tape(t, path)
+    u = I.load_tape(path)
+    assert u.digest() == t.digest() and u.n_vars == t.n_vars
+    assert np.array_equal(u.nodes, t.nodes) and np.array_equal(u.roots, t.roots)
+    assert np.array_equal(u.consts.view(np.int64), t.consts.view(np.int64))
+    a, b = mvf.check(t), mvf.check(u)
+    assert (a.n_instr, a.max_slots, a.ref_ops_fwd) == (b.n_instr, b.max_slots, b.ref_ops_fwd)

@@ -228,3 +228,18 @@ def test_largest_partition_table(engine):
         mvf.bound(h, torch.tensor(box, device="cuda"), [2049, 2048], engine=engine)
     assert e.value.code == -3
     h.close()
+
+
+def test_tape_from_file_bounds_like_the_oracle(tmp_path):
+    # mvf.Tape.from_file reads what inputs.save_tape wrote; the bounds are the oracle's, bitwise
+    import torch
+    from paper_2507_20769_amd import mvf
+    w = I.tiny(2)
+    path = str(tmp_path / "tiny.npz")
+    I.save_tape(w.tape, path)
+    h = mvf.Tape.from_file(path)
+    out = mvf.bound(h, torch.tensor(w.box, device="cuda"), w.splits, mode="both")
+    torch.cuda.synchronize()
+    o = O.bound(w.tape, w.box, w.splits, mode=O.MODE_BOTH, per_sub=False, nthreads=8)
+    assert_parity(out["reduced"].cpu().numpy(), o["reduced"], not has_transcendental(w.tape), None, "reduced")
+    h.close()
