@@ -89,7 +89,6 @@ int check_device(int *n_cu) {
     return MVF_OK;
 }
 
-constexpr int BATCH_TAB_CAP = 256;
 
 // Tangent components per forward pass: the fewest passes over the program
 // (then the fewest LDS spill slots, then the smallest chunk) among the chunks
@@ -362,7 +361,8 @@ int launch_batched(const mvf_tape *t, int mode, int chunk, bool rev, bool spec, 
                    int block, int max_nodes, hipStream_t stream) {
     const int m = (int)t->C.roots.size(), n = t->C.n_vars;
     if (spec) {
-        const size_t lds = spec_lds_bytes(BATCH_TAB_CAP, m, rev ? t->spec_gl : 0);
+        // the batched kernels keep their table and gradient in static LDS
+        const size_t lds = spec_lds_bytes(0, m);
         HIP_TRY(launch_batch_plan(A, stream));
         BatchKArgs K{tape_args(t, mode, 0), A};
         void *params[] = {&K};

@@ -12,6 +12,7 @@
 namespace mvf {
 
 constexpr int BLK = 256;            // lanes (subdomains) per workgroup
+constexpr int BATCH_TAB_CAP = 256;  // breakpoint-table entries of a batched launch (sum of a node's splits)
 
 // Per-tape arguments (wave-uniform).
 struct TapeArgs {

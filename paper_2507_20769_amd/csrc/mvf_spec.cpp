@@ -369,8 +369,9 @@ class PassWriter {
         for (int j = K - 2; j >= 0; --j) {
             restore(snap[j]);
             body.push_back(BLOCK_BREAK);
-            // loads issued at the segment's start: issued a segment earlier (ahead of the previous
-            // segment's sweep) they held registers through it and ran the batch workload 1.7x slower
+            // loads issued at the segment's start: issued a segment earlier, into registers they
+            // held through the previous segment's sweep (1.7x slower on the batch workload), into
+            // LDS by the memory system (global_load_lds) they still ran 1.2-1.5x slower
             if (j >= 1) body.push_back(loads_of(j) + recomputed_of(j));
             for (int pc = rp.begin + start[j]; pc < rp.begin + start[j + 1]; ++pc) instr(pc, decl, body);
             sweep(decl, body, rp.begin + start[j], rp.begin + start[j + 1]);
@@ -1117,8 +1118,9 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
     }
     if (ck_count) *ck_count = ck;
     if (units) *units = u;
+    const std::string n_pf = "constexpr int N_CK = " + std::to_string(rev ? ck : 0) + ";\n";
     if (!fwd) {
-        s += "}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n#include \"mvf_spec_kernel.h\"\n";
+        s += n_pf + "}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n#include \"mvf_spec_kernel.h\"\n";
         return s;
     }
     // every root in turn, as the interpreter's bound_lane with tangent passes
@@ -1151,7 +1153,7 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
         s += "        reduce_root(" + R + ", N_ROOTS, B, o);\n";
         s += "        track_root(F, " + R + ", B, FC, mode != MVF_MODE_NIE, o);\n    }\n";
     }
-    s += "    return bad;\n}\n}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n";
+    s += "    return bad;\n}\n" + n_pf + "}  // namespace spec\n}  // namespace dev\n}  // namespace mvf\n";
     s += "#include \"mvf_spec_kernel.h\"\n";
     return s;
 }

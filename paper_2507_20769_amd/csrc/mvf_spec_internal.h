@@ -31,8 +31,8 @@ std::string spec_source(const Compiled &P, int chunk, int waves, int grad, int c
 int spec_compile(const std::string &src, const std::string &arch, bool use_cache, std::vector<char> &code,
                  bool *from_cache, double *seconds);
 
-// dynamic LDS of the specialised kernel; gl gradient components per lane in
-// LDS (the adjoint kernels' launch: spec_gl_count of the tape, else 0)
+// dynamic LDS of the specialised single-box kernel; gl gradient components
+// per lane in LDS (the adjoint kernel's launch: the tape's, else 0)
 size_t spec_lds_bytes(int tab_total, int m, int gl = 0);
 int spec_gl_count(const Compiled &P, int waves);
 

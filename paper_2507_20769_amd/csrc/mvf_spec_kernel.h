@@ -19,8 +19,8 @@ namespace dev {
 // The workgroup is blockDim.x = 64, 128 or 256 lanes (one to four waves; a
 // launch-time choice of the autotuner); LDS is laid out for up to four waves.
 // LDS after the breakpoint table, the reduction records and the splits: the
-// adjoint's LDS-resident gradient components (spec::N_GL of them per lane, for
-// up to BLK lanes), 16-byte aligned
+// single-box adjoint's LDS-resident gradient components (spec::N_GL of them
+// per lane, for up to BLK lanes), 16-byte aligned
 __device__ __forceinline__ size_t spec_gl_offset(int tab_total, int m) {
     size_t b = (size_t)tab_total * 32;
     b += ((size_t)(BLK / 64) * wred_len(m) * 8 + 15) & ~(size_t)15;
@@ -58,8 +58,8 @@ __device__ __forceinline__ void spec_bound_body() {
         const bool active = k < S;
         SpecLane L;
         L.tab = tab;
-        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * blk + tid;
-        L.ck_stride = (int64_t)gridDim.x * blk;
+        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * spec::N_CK * blk + tid;
+        L.ck_stride = blk;
         L.gl = reinterpret_cast<Iv *>(smem + spec_gl_offset(tab_total, m)) + tid;
         L.gl_stride = blk;
         int64_t q = active ? k : S - 1;
@@ -103,15 +103,17 @@ __device__ __forceinline__ void spec_bound_body() {
 template <bool REV>
 __device__ __forceinline__ void spec_batch_body() {
     constexpr int n = spec::N_VARS, m = spec::N_ROOTS;
+    constexpr int GL = REV ? spec::N_GL : 0;
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ int64_t sh_item;
     __shared__ int sh_node;
+    // the table and the adjoint's gradient as static LDS objects, the reduction
+    // records and splits in the dynamic LDS
+    __shared__ __align__(16) double4 tab[BATCH_TAB_CAP];
+    __shared__ __align__(16) Iv gl_lds[GL > 0 ? GL * BLK : 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, blk = blockDim.x;
-    const int tab_cap = kargs<BatchKArgs>()->A.tab_cap;
-    double4 *tab = reinterpret_cast<double4 *>(smem);
-    double *wred = reinterpret_cast<double *>(smem + (size_t)tab_cap * 32);
-    int32_t *ints = reinterpret_cast<int32_t *>(smem + (size_t)tab_cap * 32 +
-                                                (((size_t)(BLK / 64) * wred_len(m) * 8 + 15) & ~(size_t)15));
+    double *wred = reinterpret_cast<double *>(smem);
+    int32_t *ints = reinterpret_cast<int32_t *>(smem + (((size_t)(BLK / 64) * wred_len(m) * 8 + 15) & ~(size_t)15));
     const bool go = kargs<BatchKArgs>()->T.n == n;        // always true, opaque (see mvf_spec_bound)
     int cur = -1;
     for (;;) {
@@ -164,9 +166,9 @@ __device__ __forceinline__ void spec_batch_body() {
             const bool active = k < S;
             SpecLane L;
             L.tab = tab;
-            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * blk + tid;
-            L.ck_stride = (int64_t)gridDim.x * blk;
-            L.gl = reinterpret_cast<Iv *>(smem + spec_gl_offset(tab_cap, m)) + tid;
+            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * spec::N_CK * blk + tid;
+            L.ck_stride = blk;
+            L.gl = gl_lds + tid;
             L.gl_stride = blk;
             int64_t q = active ? k : S - 1;
 #pragma unroll
