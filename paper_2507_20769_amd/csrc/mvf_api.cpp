@@ -252,6 +252,7 @@ struct PointsLayout {
     int grid = 1, chunk = 0, spill = 0;
     bool g_lds = true;
     size_t rec = 0, gacc = 0, total = 0, lds = 0;
+    int64_t recs = 0;        // records per lane
 };
 
 int points_layout(const mvf_tape *t, int op, int64_t B, PointsLayout *L) {
@@ -270,6 +271,7 @@ int points_layout(const mvf_tape *t, int op, int64_t B, PointsLayout *L) {
     L->lds = points_lds_bytes((int)C.instr.size(), C.n_vars, rev && L->g_lds, spill);
     if (L->lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "programs exceed the LDS budget of the point kernels");
     const int recs = op == PT_VJP ? C.uprog.n_rec : C.max_rec;
+    L->recs = recs;
     L->rec = 0;
     L->gacc = align_up(rev ? (size_t)recs * L->grid * BLK * 16 : 0);
     L->total = L->gacc + (rev && !L->g_lds ? (size_t)C.n_vars * L->grid * BLK * 16 : 0);
@@ -302,6 +304,7 @@ int launch_points_op(const mvf_tape *t, int op, int64_t B, const double *x, cons
     A.flags = flags;
     uint8_t *w = static_cast<uint8_t *>(ws);
     A.rec = L.total > 0 ? reinterpret_cast<double2 *>(w + L.rec) : nullptr;
+    A.rec_lane = L.recs;
     A.gacc = (op == PT_VJP || op == PT_GRAD_REV) && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     hipError_t e = launch_points(A, op, L.chunk, L.grid, L.lds, stream);
     if (e != hipSuccess) return hip_err(e, "launch_points");
@@ -351,6 +354,7 @@ int fill_batch_args(const mvf_tape *t, int32_t n_nodes, const int32_t *n_nodes_d
     A->partial_ext = reinterpret_cast<double *>(w + L.ext);
     A->extra = extra;
     A->rec = reinterpret_cast<double2 *>(w + L.rec);
+    A->rec_lane = (int64_t)rec_per_lane(t);
     A->gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     A->item_cap = (int64_t)(max_sub / BLK) + max_nodes + 1;
     return MVF_OK;
@@ -592,6 +596,7 @@ int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_b
     B.partial_ext = reinterpret_cast<double *>(w + L.ext);
     B.extra = a->extra;
     B.rec = reinterpret_cast<double2 *>(w + L.rec);
+    B.rec_lane = (int64_t)rec_lane;
     B.gacc = rev && !L.g_lds ? reinterpret_cast<double2 *>(w + L.gacc) : nullptr;
     if (a->kernel_events[0]) HIP_TRY(hipEventRecord(a->kernel_events[0], stream));
     if (spec) {
