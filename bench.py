@@ -53,8 +53,8 @@ FP64_PUBLISHED_PEAK = 78.6e12
 # kernel build and tape they were taken on: (engine, grad, tape hash, code
 # object bytes) -> bytes, with the profile they come from.  A rebuilt kernel
 # of another size finds no entry and reports null.
-TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea", 940184): (18614.7 * 2.0 + 63995.7) * 1024}
-TRAFFIC_SOURCE = {("spec", "fwd", "aa75c5b416e4faea", 940184):
+TRAFFIC = {("spec", "fwd", "aa75c5b416e4faea", 944920): (12576.5 * 2.0 + 57174.5) * 1024}
+TRAFFIC_SOURCE = {("spec", "fwd", "aa75c5b416e4faea", 944920):
                   "profiles/mvf_spec_bound_mid.md (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, per dispatch)"}
 METRIC = "MVF subdomain bounds/sec (obj+constraints) and % FP64 vector peak; adjoint+batched vs plain"
 PEAK_UNIT = "T FP64 op/s (one VALU issue slot per op, FMA = 1)"
