@@ -39,8 +39,8 @@ struct BoxArgs {
     int64_t *partial_k;      // [grid]
     double *partial_ext;     // [grid][2]: feasibility-filtered objective bound, upper bound from centres
     double *extra;           // [2] or null
-    double2 *rec;            // reverse-mode tape, per workgroup [rec_lane][BLK]
-    double2 *gacc;           // reverse-mode gradient accumulators, per workgroup [n][BLK], when not in LDS
+    double2 *rec;            // reverse-mode tape, per wave [rec_lane][64]
+    double2 *gacc;           // reverse-mode gradient accumulators, per wave [n][64], when not in LDS
     int64_t rec_lane;        // records (or checkpoint intervals) per lane that rec holds
 };
 
@@ -65,8 +65,8 @@ struct BatchArgs {
     int64_t *partial_k;      // [items]
     double *partial_ext;     // [items][2]
     double *extra;           // [N][2] or null
-    double2 *rec;            // reverse-mode tape, per workgroup [rec_lane][BLK]
-    double2 *gacc;           // reverse-mode gradient accumulators, per workgroup [n][BLK], when not in LDS
+    double2 *rec;            // reverse-mode tape, per wave [rec_lane][64]
+    double2 *gacc;           // reverse-mode gradient accumulators, per wave [n][64], when not in LDS
     int64_t rec_lane;        // records (or checkpoint intervals) per lane that rec holds
 };
 
@@ -93,8 +93,8 @@ struct PointsArgs {
     const double *gout;      // [B][m] cotangents (vector-Jacobian product)
     double *out;             // values [B][m][2], or gradients [B][n][2]
     uint32_t *flags;         // [B] or null: domain violation
-    double2 *rec;            // reverse-mode records, per workgroup [rec_lane][BLK]
-    double2 *gacc;           // gradient accumulators, per workgroup [n][BLK], when not in LDS
+    double2 *rec;            // reverse-mode records, per wave [rec_lane][64]
+    double2 *gacc;           // gradient accumulators, per wave [n][64], when not in LDS
     int64_t rec_lane;        // records per lane that rec holds
 };
 struct PointsKArgs {

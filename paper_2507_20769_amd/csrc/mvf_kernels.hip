@@ -555,9 +555,9 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         __syncthreads();
         build_table(n, K->B.box, s.ints, s.ints + MVF_MAX_VARS, s.tab, tid, BLK);
         if (lane == 0) reset_wred(s.wred + wave * wred_len(m), m);
-        X.G = g_lds ? s.G + tid : K->B.gacc + (int64_t)blockIdx.x * n * BLK + tid;
-        X.gstride = BLK;
-        X.rec = K->B.rec + (int64_t)blockIdx.x * K->B.rec_lane * BLK + tid;
+        X.G = g_lds ? s.G + tid : K->B.gacc + ((int64_t)blockIdx.x * BLK + wave * 64) * n + lane;
+        X.gstride = g_lds ? BLK : 64;
+        X.rec = K->B.rec + ((int64_t)blockIdx.x * BLK + wave * 64) * K->B.rec_lane + lane;
         X.nreg = (uint32_t)K->T.nreg;
     }
     __syncthreads();
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     X.vrec = s.vrec;
     X.tid = tid;
     X.blk = BLK;
-    X.rec_stride = BLK;
+    X.rec_stride = 64;
     X.spill = s.spill + tid;
     for (int64_t base = (int64_t)blockIdx.x * BLK;; base += (int64_t)gridDim.x * BLK) {
         const int64_t S = kargs<BoundKArgs>()->B.S;
@@ -769,9 +769,9 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         const bool g_lds = K->A.gacc == nullptr;
         s = carve(smem, K->T, K->A.tab_cap, BLK, REV && g_lds, C);
         stage_program(K->T, s.prog, tid, BLK);
-        X.G = g_lds ? s.G + tid : K->A.gacc + (int64_t)blockIdx.x * n * BLK + tid;
-        X.gstride = BLK;
-        X.rec = K->A.rec + (int64_t)blockIdx.x * K->A.rec_lane * BLK + tid;
+        X.G = g_lds ? s.G + tid : K->A.gacc + ((int64_t)blockIdx.x * BLK + wave * 64) * n + lane;
+        X.gstride = g_lds ? BLK : 64;
+        X.rec = K->A.rec + ((int64_t)blockIdx.x * BLK + wave * 64) * K->A.rec_lane + lane;
         X.nreg = (uint32_t)K->T.nreg;
     }
     X.prog = s.prog;
@@ -779,7 +779,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     X.vrec = s.vrec;
     X.tid = tid;
     X.blk = BLK;
-    X.rec_stride = BLK;
+    X.rec_stride = 64;
     X.spill = s.spill + tid;
     int cur = -1;
     for (;;) {
@@ -940,11 +940,12 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
         // host sizes the LDS the same way: programs, accumulators, spill slots)
         constexpr bool REVOP = OP == PT_VJP || OP == PT_GRAD_REV;
         const bool g_lds = REVOP && K->P.gacc == nullptr;
-        X.G = g_lds ? reinterpret_cast<double2 *>(p) + tid : K->P.gacc + (int64_t)blockIdx.x * n * BLK + tid;
-        X.gstride = BLK;
+        X.G = g_lds ? reinterpret_cast<double2 *>(p) + tid
+                    : K->P.gacc + ((int64_t)blockIdx.x * BLK + (tid >> 6) * 64) * n + (tid & 63);
+        X.gstride = g_lds ? BLK : 64;
         if (g_lds) p += (size_t)n * BLK * 16;
         X.spill = reinterpret_cast<double2 *>(p) + tid;
-        X.rec = K->P.rec + (int64_t)blockIdx.x * K->P.rec_lane * BLK + tid;
+        X.rec = K->P.rec + ((int64_t)blockIdx.x * BLK + (tid >> 6) * 64) * K->P.rec_lane + (tid & 63);
         X.nreg = (uint32_t)K->P.nreg;
     }
     __syncthreads();
@@ -953,7 +954,7 @@ __global__ __launch_bounds__(BLK) __attribute__((amdgpu_num_vgpr(SLOT_BASE), amd
     X.vrec = nullptr;
     X.tid = tid;
     X.blk = BLK;
-    X.rec_stride = BLK;
+    X.rec_stride = 64;
     constexpr int VS = OP >= PT_GRAD_FWD ? VS_BOX : VS_POINT;
     for (int64_t base = (int64_t)blockIdx.x * BLK;; base += (int64_t)gridDim.x * BLK) {
         int64_t B, k, kk;

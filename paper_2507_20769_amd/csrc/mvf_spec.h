@@ -18,10 +18,10 @@ namespace dev {
 
 // A lane's subdomain: the breakpoint table in LDS and, per variable, the
 // index of the lane's table entry {lo, -hi, c, -c}; the lane's checkpoint
-// buffer of the adjoint: each workgroup owns a contiguous block of the
-// workspace laid out [index][lane] (coalesced; a wave's checkpoints lie
-// within N_CK x blk x 16 bytes instead of one stretch per index across the
-// whole grid's buffer, which took a TLB entry per index).
+// buffer of the adjoint: each wave owns a contiguous block of the workspace
+// laid out [index][lane] (coalesced, 1 KB per index; a wave's checkpoints
+// lie within N_CK KB instead of one stretch per index across the whole
+// grid's buffer, which took a translation entry per index).
 struct SpecLane {
     const double4 *tab;
     int vi[MVF_MAX_VARS];

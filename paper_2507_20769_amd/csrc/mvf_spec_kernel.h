@@ -58,8 +58,8 @@ __device__ __forceinline__ void spec_bound_body() {
         const bool active = k < S;
         SpecLane L;
         L.tab = tab;
-        L.ck = kargs<BoundKArgs>()->B.rec + (int64_t)blockIdx.x * spec::N_CK * blk + tid;
-        L.ck_stride = blk;
+        L.ck = kargs<BoundKArgs>()->B.rec + ((int64_t)blockIdx.x * blk + wave * 64) * spec::N_CK + lane;
+        L.ck_stride = 64;
         L.gl = reinterpret_cast<Iv *>(smem + spec_gl_offset(tab_total, m)) + tid;
         L.gl_stride = blk;
         int64_t q = active ? k : S - 1;
@@ -166,8 +166,8 @@ __device__ __forceinline__ void spec_batch_body() {
             const bool active = k < S;
             SpecLane L;
             L.tab = tab;
-            L.ck = kargs<BatchKArgs>()->A.rec + (int64_t)blockIdx.x * spec::N_CK * blk + tid;
-            L.ck_stride = blk;
+            L.ck = kargs<BatchKArgs>()->A.rec + ((int64_t)blockIdx.x * blk + wave * 64) * spec::N_CK + lane;
+            L.ck_stride = 64;
             L.gl = gl_lds + tid;
             L.gl_stride = blk;
             int64_t q = active ? k : S - 1;
