@@ -493,6 +493,16 @@ def mid(seed: int = 1) -> Workload:
                     "6 vars, 200-op objective + 3x80-op constraints, 8^6 = 262,144 subdomains")
 
 
+def rational(tape: Tape) -> Tape:
+    """The tape with exp replaced by sqr and log by sqrt: a variant of the same
+    shape whose bounds every implementation must reproduce bit for bit (the
+    remaining operations are correctly rounded)."""
+    nodes = tape.nodes.copy()
+    nodes["op"][nodes["op"] == EXP] = SQR
+    nodes["op"][nodes["op"] == LOG] = SQRT
+    return Tape(nodes, tape.consts, tape.roots, tape.n_vars)
+
+
 def diff(seed: int = 1) -> Workload:
     rng = np.random.Generator(np.random.PCG64(seed + 2000))
     box = _random_box(rng, 32)

@@ -146,6 +146,33 @@ def test_mid_full_size_sampled():
     h.close()
 
 
+@pytest.mark.parametrize("grad", ["fwd", "rev"])
+def test_mid_rational_full_size_bitwise(grad):
+    # the mid workload's shape with exp -> sqr and log -> sqrt, at full size in the
+    # benchmark's launch: every per-subdomain endpoint, flag, hull, argmin and both
+    # branch-and-bound bounds bitwise equal to the interpreter's, and 1,024 sampled
+    # subdomains (the grid's first and last among them) bitwise equal to the oracle's
+    w = I.mid(1)
+    t = I.rational(w.tape)
+    assert not has_transcendental(t)
+    kinds = [0, 1, 1, 1]
+    h = _handle(t, kinds, grad="auto")   # both gradient modes' kernels (the precompiled object)
+    g = gpu_bound(t, w.box, w.splits, mode="both", grad=grad, handle=h, engine="spec")
+    gi = gpu_bound(t, w.box, w.splits, mode="both", grad=grad, handle=h, engine="interp")
+    for key in ("per_sub", "reduced", "argmin", "flags", "extra"):
+        assert_parity(g[key], gi[key], True, None, f"mid rational {grad}: {key} vs interpreter")
+    assert not g["flags"].any()
+    S = w.n_sub
+    rng = np.random.default_rng(2)
+    ks = np.unique(np.concatenate([rng.choice(S, 1020, replace=False), [0, 255, 256, S - 1]]))
+    o = O.bound(t, w.box, w.splits, mode=O.MODE_BOTH, grad=O.GRAD_FWD if grad == "fwd" else O.GRAD_REV,
+                ks=ks, nthreads=8, kinds=kinds)
+    assert_parity(g["per_sub"][:, :, ks], o["per_sub"], True, None, f"mid rational {grad}: sampled vs oracle")
+    assert np.array_equal(g["reduced"][:, 0], g["per_sub"][:, 0, :].min(axis=1))
+    assert np.array_equal(g["reduced"][:, 1], g["per_sub"][:, 1, :].max(axis=1))
+    h.close()
+
+
 def test_engine_selection_errors():
     import torch
     from paper_2507_20769_amd import mvf
