@@ -97,9 +97,66 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(w, seconds: float) -> dict:
+def gpu_clocks() -> dict:
+    """The GPU's current clocks and power as rocm-smi reports them (sampled
+    right after the timed steps; the clock under load comes from the
+    counters: busy cycles over kernel time)."""
+    import subprocess
+    try:
+        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showmaxpower", "--json"],
+                           capture_output=True, text=True, timeout=30)
+        card = next(iter(json.loads(r.stdout).values()))
+        keep = ("sclk", "mclk", "fclk", "power", "Power")
+        return {k.strip().rstrip(":"): v for k, v in card.items() if any(x in k for x in keep)}
+    except Exception as e:          # no rocm-smi, no card, or output it cannot parse
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def _oracle_rate(O, cases, grad: int, threads: int, seconds: float) -> dict:
+    """The oracle over (tape, box, splits, ks) cases, 64 subdomains per thread
+    at a time, until the cases are done or ``seconds`` have passed."""
+    done, t0 = 0, time.perf_counter()
+    for tape, box, splits, ks in cases:
+        for i in range(0, len(ks), 64 * threads):
+            O.bound(tape, box, splits, mode=O.MODE_BOTH, grad=grad, ks=ks[i:i + 64 * threads], per_sub=False,
+                    nthreads=threads)
+            done += len(ks[i:i + 64 * threads])
+            if time.perf_counter() - t0 >= seconds:
+                break
+        if time.perf_counter() - t0 >= seconds:
+            break
+    t = time.perf_counter() - t0
+    return {"value": done / t, "subdomains": done, "seconds": t}
+
+
+def other_workload_rates(seed: int, threads: int, seconds: float) -> dict:
+    """The oracle's forward and reverse modes on seeded samples of the 32-variable
+    and batch workloads (16,384 subdomains each at most, ``seconds`` per leg)."""
+    from oracle import oracle as O
+    from paper_2507_20769_amd import inputs as I
+    rng = np.random.default_rng(seed)
+    d = I.diff(seed)
+    diff_case = [(d.tape, d.box, d.splits, np.sort(rng.choice(d.n_sub, 16384, replace=False)))]
+    bw = I.batch(seed)
+    nodes = np.sort(rng.choice(len(bw.boxes), 16, replace=False))
+    batch_cases = [(bw.tape, bw.boxes[i], bw.splits[i],
+                    np.sort(rng.choice(int(bw.n_sub[i]), min(1024, int(bw.n_sub[i])), replace=False)))
+                   for i in nodes]
+    out = {}
+    for name, cases in (("diff", diff_case), ("batch", batch_cases)):
+        for gname, grad in (("adjoint", O.GRAD_REV), ("forward", O.GRAD_FWD)):
+            r = _oracle_rate(O, cases, grad, threads, seconds)
+            r["unit"] = "subdomain-bounds/s"
+            r["sample"] = ("seeded 16,384 of the 1,048,576 subdomains" if name == "diff" else
+                           "seeded 1,024 subdomains (or all) of each of 16 seeded nodes of the 512")
+            out[f"{name}_{gname}"] = r
+    return out
+
+
+def cpu_baseline(w, seconds: float, other: bool = True) -> dict:
     """The oracle (untuned) on contiguous samples of the workload's subdomains:
-    one thread, then every host core the process may use."""
+    one thread, then every host core the process may use; other: also its rates
+    on samples of the 32-variable and batch workloads, every core."""
     from oracle import oracle as O
     try:
         cores = len(os.sched_getaffinity(0))
@@ -123,7 +180,8 @@ def cpu_baseline(w, seconds: float) -> dict:
             "sample": f"subdomains {n1}..{n1 + na - 1} of the {w.name} workload ({na} of {S}), forward-mode MVF "
                       f"with MVF and NIE, {ta:.1f} s on {cores} threads",
             "cpu_model": cpu_model(),
-            "one_thread": {"value": n1 / t1, "sample": f"subdomains 0..{n1 - 1}, {t1:.1f} s"}}
+            "one_thread": {"value": n1 / t1, "sample": f"subdomains 0..{n1 - 1}, {t1:.1f} s"},
+            "other_workloads": other_workload_rates(1, cores, min(seconds, 4.0)) if other else None}
 
 
 def time_calls(launch, steps: int, warmup: int, stream, prewarm_s: float = 0.0, per_step: bool = False):
@@ -555,6 +613,7 @@ def main():
                    "end_to_end": "box H2D + bound + reduced D2H + synchronise, host clock, 20 calls",
                    "prewarm_s": args.prewarm_s, "wall_s": wall},
         "objective_lower_bound": float(reduced[0, 0]),
+        "gpu_clocks": gpu_clocks(),
     }
     if spec:
         out["specialisation"] = {"kernels": spec["grad"], "compile_s": spec["seconds"],
@@ -574,7 +633,7 @@ def main():
         if "bnb" in forms and args.bnb_nodes > 0:
             out["forms"]["bnb"] = bnb_forms(args.seed, args.bnb_nodes)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds, other=not args.no_forms)
     print(json.dumps(out), flush=True)
 
 
