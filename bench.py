@@ -98,18 +98,29 @@ def cpu_model() -> str:
 
 
 def gpu_clocks() -> dict:
-    """The GPU's current clocks and power as rocm-smi reports them (sampled
-    right after the timed steps; the clock under load comes from the
-    counters: busy cycles over kernel time)."""
-    import subprocess
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks", "--showpower", "--showmaxpower", "--json"],
-                           capture_output=True, text=True, timeout=30)
-        card = next(iter(json.loads(r.stdout).values()))
-        keep = ("sclk", "mclk", "fclk", "power", "Power")
-        return {k.strip().rstrip(":"): v for k, v in card.items() if any(x in k for x in keep)}
-    except Exception as e:          # no rocm-smi, no card, or output it cannot parse
-        return {"error": f"{type(e).__name__}: {e}"}
+    """The GPU's current clock levels and power cap from the driver's sysfs files
+    (sampled right after the timed steps; the clock under load comes from the
+    counters: busy cycles over kernel time).  Files only: no child process."""
+    import glob
+    out = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        for name in ("pp_dpm_sclk", "pp_dpm_mclk", "pp_dpm_fclk"):
+            try:
+                cur = [ln.split(":", 1)[1].strip().rstrip("*").strip()
+                       for ln in open(os.path.join(dev, name)) if ln.rstrip().endswith("*")]
+            except OSError:
+                continue
+            if cur:
+                out[name[7:]] = cur[0]
+        for cap in glob.glob(os.path.join(dev, "hwmon", "hwmon*", "power1_cap")):
+            try:
+                out["power_cap_w"] = int(open(cap).read()) / 1e6
+            except (OSError, ValueError):
+                pass
+        if out:
+            out["device"] = dev
+            return out
+    return {"error": "no clock files under /sys/class/drm"}
 
 
 def _oracle_rate(O, cases, grad: int, threads: int, seconds: float) -> dict:

@@ -105,8 +105,12 @@ typedef struct {
     int32_t max_slots;        /* largest live set of any root program */
     int32_t tangent_chunk;    /* tangent components carried per forward pass (0: forward mode unavailable) */
     int32_t max_records;      /* reverse-mode tape records per subdomain (largest root program) */
-    int64_t ref_ops_fwd;      /* reference FP64 op count per subdomain, forward mode */
-    int64_t ref_ops_rev;      /* reference FP64 op count per subdomain, reverse mode */
+    /* Reference (algorithmic) FP64 op counts per subdomain: values, tangents
+     * and the centre pass once per node of the union of the root cones (a
+     * node several roots share counts once), an adjoint sweep per root over
+     * its own cone, the mean value forms and Step 1. */
+    int64_t ref_ops_fwd;      /* forward mode */
+    int64_t ref_ops_rev;      /* reverse mode */
     int64_t ref_ops_fwd_sparse;   /* forward mode without the structurally zero tangent components
                                      (what the specialised kernels compute) */
     /* the checkpoint plan of the specialised adjoint (Sec. 3.2's DAG in

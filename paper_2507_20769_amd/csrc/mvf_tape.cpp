@@ -279,12 +279,17 @@ int compile_tape(const mvf_node *nodes, int32_t n_nodes, const double *consts, i
             ins.w0 |= (init & 1u ? W0_INIT_A : 0u) | (init & 2u ? W0_INIT_B : 0u) | (nowrite ? W0_NOWRITE : 0u);
             C.instr.push_back(ins);
             P.n_rec += n_records(op, ak, bk);
-            if (!uni) {
-                int cv, ct, ca;
-                ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
-                sum_val += cv; sum_tan += ct; sum_adj += ca; ++n_ops;
+            // Algorithmic work: values, tangents and the centre pass once per
+            // node of the union of the root cones (a node shared by several
+            // roots is computed once); an adjoint sweep per root over its cone.
+            int cv, ct, ca;
+            ref_cost(nd.op, a_const, b_const, &cv, &ct, &ca);
+            if (uni) {
+                sum_val += cv; sum_tan += ct; ++n_ops;
                 sum_tan_sparse += sparse_tan_cost(nodes, nd, dep);
                 if (nd.op == MVF_SQR || nd.op == MVF_SQRT) sum_val += 2;   // 2U or 1/(2Z), once per op
+            } else {
+                sum_adj += ca;
             }
         }
         if (!uni) {

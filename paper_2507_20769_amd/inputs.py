@@ -570,6 +570,30 @@ def random_small_tape(seed: int, n: int, ops: int, n_con: int = 1, con_ops: int 
     return random_tape(seed, n, ops, [con_ops] * n_con, np.full(n, lo), np.full(n, hi), window=window)
 
 
+def shared_roots_tape(seed: int, n: int = 3, ops: int = 60, con_ops: int = 20) -> Tape:
+    """Roots that share subexpressions: a random objective, two random
+    constraints each plus (minus) a node of the objective's cone, and the
+    product of two more of the objective's nodes as a third constraint."""
+    base = random_small_tape(seed, n=n, ops=ops, n_con=2, con_ops=con_ops, window=8)
+    nodes = [tuple(int(v) for v in nd) for nd in base.nodes.tolist()]
+    arith = {ADD, SUB, MUL, DIV, SQR, SQRT, EXP, LOG, TANH, SIN, COS}
+    cone, todo = set(), [int(base.roots[0])]
+    while todo:
+        i = todo.pop()
+        if i in cone or nodes[i][0] not in arith:
+            continue
+        cone.add(i)
+        todo.append(nodes[i][1])
+        if nodes[i][0] in (ADD, SUB, MUL, DIV):
+            todo.append(nodes[i][2])
+    rng = np.random.default_rng(seed + 7)
+    p = [int(x) for x in rng.choice(sorted(cone - {int(base.roots[0])}), 4, replace=False)]
+    nodes += [(ADD, int(base.roots[1]), p[0]), (SUB, int(base.roots[2]), p[1]), (MUL, p[2], p[3])]
+    T = len(nodes)
+    return Tape(np.array(nodes, dtype=NODE_DTYPE), base.consts.copy(),
+                np.array([base.roots[0], T - 3, T - 2, T - 1], dtype=np.int32), n)
+
+
 def random_points(seed: int, box: np.ndarray, count: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     lo, hi = box[:, 0], box[:, 1]

@@ -81,6 +81,19 @@ def test_sparse_forward_op_count():
         assert 0 < st.ref_ops_fwd_sparse <= st.ref_ops_fwd
 
 
+def test_shared_nodes_count_once():
+    # m = x0 x1 feeds both roots f = sqr(m) and g = exp(m) (n = 2).  Values, tangents and the
+    # centre pass count once per node of the union of the cones: values 14 + (5 + 2) + 2,
+    # tangents 30 + 14 + 14 per component, 2 per op; the adjoint sweeps once per root over
+    # its own cone: (32 + 18) + (32 + 16); combine 2 x (16 n + 2), Step 1 10 n
+    st = mvf.check(_tape([(I.VAR, 0, -1), (I.VAR, 1, -1), (I.MUL, 0, 1), (I.SQR, 2, -1), (I.EXP, 2, -1)],
+                         [], [3, 4], 2))
+    assert st.ref_ops_fwd == 23 + 2 * 58 + 3 * 2 + 2 * 34 + 20
+    assert st.ref_ops_rev == 23 + 98 + 3 * 2 + 2 * 34 + 20
+    t = I.shared_roots_tape(1)
+    assert 0 < mvf.check(t).ref_ops_fwd_sparse < mvf.check(t).ref_ops_fwd
+
+
 def test_leaf_roots_compile():
     st = mvf.check(_tape([(I.VAR, 0, -1), (I.CONST, 0, -1)], [2.5], [0, 1], 1))
     assert st.n_instr == 2

@@ -147,6 +147,23 @@ def test_mid_full_size_sampled():
 
 
 @pytest.mark.parametrize("grad", ["fwd", "rev"])
+@pytest.mark.parametrize("rational", [True, False])
+def test_roots_sharing_subexpressions(grad, rational):
+    # every node of the union of the root cones is computed once per pass and
+    # each root's bound is taken where its value is computed: bitwise the
+    # interpreter's (which computes each root's cone on its own) and the oracle's
+    t = I.shared_roots_tape(11)
+    if rational:
+        t = I.rational(t)
+    kinds = [0, 1, 2, 1]
+    h = _handle(t, kinds, grad="auto")
+    box = np.array([[-2.0, 2.0], [-1.5, 2.5], [-2.0, 1.0]])
+    for mode in MODES:
+        _compare(h, t, box, [5, 7, 11], mode, kinds, grad=grad)
+    h.close()
+
+
+@pytest.mark.parametrize("grad", ["fwd", "rev"])
 def test_mid_rational_full_size_bitwise(grad):
     # the mid workload's shape with exp -> sqr and log -> sqrt, at full size in the
     # benchmark's launch: every per-subdomain endpoint, flag, hull, argmin and both

@@ -45,11 +45,12 @@ def _deps(tape):
     return dep
 
 
-def _peak_live(tape, root, cmask, dep):
-    """Intervals a tangent pass keeps live: each operation's value from its node to its last
-    reader (the root's to the end) with its structurally nonzero components in cmask."""
+def _peak_live(tape, cmask, dep):
+    """Intervals a tangent pass over the union of the root cones keeps live: each
+    operation's value from its node to its last reader (a root is consumed where it is
+    computed) with its structurally nonzero components in cmask."""
     ops, A, B = tape.nodes["op"], tape.nodes["a"], tape.nodes["b"]
-    cone, stack = set(), [int(root)]
+    cone, stack = set(), [int(r) for r in tape.roots]
     while stack:
         x = stack.pop()
         if x not in cone:
@@ -59,7 +60,7 @@ def _peak_live(tape, root, cmask, dep):
             if ops[x] in (I.ADD, I.SUB, I.MUL, I.DIV):
                 stack.append(int(B[x]))
     order = sorted(x for x in cone if ops[x] not in (I.VAR, I.CONST))
-    last = {int(root): len(tape.nodes)}
+    last = {}
     for x in order:
         for y in ([A[x], B[x]] if ops[x] in (I.ADD, I.SUB, I.MUL, I.DIV) else [A[x]]):
             last[int(y)] = max(last.get(int(y), -1), x)
@@ -72,8 +73,7 @@ def _default_chunk(tape, limit=100):
     n, dep = tape.n_vars, _deps(tape)
     for passes in range(1, n + 1):
         c = -(-n // passes)
-        peak = max(_peak_live(tape, r, ((1 << min(c, n - c0)) - 1) << c0, dep)
-                   for r in tape.roots for c0 in range(0, n, c))
+        peak = max(_peak_live(tape, ((1 << min(c, n - c0)) - 1) << c0, dep) for c0 in range(0, n, c))
         if peak <= limit:
             return c
     return 1
@@ -123,6 +123,28 @@ def test_structurally_zero_components_are_not_computed(tmp_path, monkeypatch):
     assert "spec_dx(L, 0)" in root1 and "spec_dx(L, 1)" not in root1 and "spec_dx(L, 2)" not in root1
     f_pass = funcs["tangent_0_0"]
     assert "kZero;" not in f_pass.split("return")[0].split("G[0]")[-1]       # f: no zero component
+    assert "utangent_0" not in funcs                                        # disjoint cones: a pass per root
+
+
+def test_roots_sharing_nodes_take_passes_over_the_union(tmp_path, monkeypatch):
+    # the product x0 x1 feeds f = x0 x1 + sqr(x2) and g = exp(x0) + x0 x1: one centre pass and
+    # one tangent pass over both cones compute it once, and g's terms skip component 2
+    V = I.VAR
+    t = _tape([(V, 0, -1), (V, 1, -1), (V, 2, -1), (I.MUL, 0, 1), (I.SQR, 2, -1), (I.ADD, 3, 4),
+               (I.EXP, 0, -1), (I.ADD, 6, 3)], [], [5, 7], 3)
+    dump = tmp_path / "u.hip"
+    monkeypatch.setenv("MVF_SPEC_DUMP", str(dump))
+    info = mvf.spec_check(t, grad="fwd")
+    st = mvf.check(t)
+    assert info["code_units"] < st.n_instr * (2 + 1)                          # the shared product once per pass
+    src = dump.read_text()
+    funcs = {f.split("(")[0].split()[-1]: f for f in src.split("__device__")[1:]}
+    assert "tangent_0_0" not in funcs and "point_0" not in funcs
+    u = funcs["utangent_0"]
+    g_terms = u[u.index("nie[1] ="):].split("}")[0]
+    assert "spec_dx(L, 0)" in g_terms and "spec_dx(L, 1)" in g_terms and "spec_dx(L, 2)" not in g_terms
+    f_terms = u[u.index("nie[0] ="):].split("}")[0]
+    assert all(f"spec_dx(L, {i})" in f_terms for i in range(3)) and f_terms.count("acc[0] = iadd(") == 3
 
 
 def test_chunk_and_waves_options():
@@ -156,6 +178,8 @@ def test_both_gradient_modes_compile_and_are_counted():
     for grad, extra in (("fwd", None), ("rev", 2), ("auto", None)):
         info = mvf.spec_check(t, grad=grad, ckpt_budget=-1)
         passes = -(-t.n_vars // info["chunk"])
+        # a centre and a value pass per root; forward: the tangent passes; reverse: the
+        # adjoint's value pass and its sweep
         want = st.n_instr * (2 + (passes if grad != "rev" else 0) + (2 if grad != "fwd" else 0))
         assert info["code_units"] == want and info["grad"] == {"fwd": 0, "rev": 1, "auto": 2}[grad]
         assert info["ckpt_intervals"] == 0
