@@ -562,7 +562,12 @@ int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_b
     if (rc != MVF_OK) return rc;
     if (a->engine == MVF_ENGINE_SPEC && !t->spec_fn[rev])
         return set_err(MVF_EINVAL, "no specialised kernel for this gradient mode: see mvf_tape_specialize");
-    const bool spec = t->spec_fn[rev] && a->engine != MVF_ENGINE_INTERP;
+    const int m = (int)t->C.roots.size(), n = t->C.n_vars;
+    // the specialised kernel, unless the caller asks for the interpreter, or
+    // leaves the choice and the kernel's tables and LDS gradient would not fit
+    bool spec = t->spec_fn[rev] && a->engine != MVF_ENGINE_INTERP;
+    if (spec && a->engine == MVF_ENGINE_AUTO && spec_lds_bytes(tt, m, rev ? t->spec_gl : 0) > LDS_BUDGET - 1024)
+        spec = false;
     const int grid = single_grid(t, S, rev);
     const size_t rec_lane = engine_rec ? (size_t)(spec ? t->spec_ck : t->C.max_rec) : rec_per_lane(t);
     const SingleLayout L = single_layout(t, grid, rev, tt, rec_lane);
@@ -570,7 +575,6 @@ int bound_impl(const mvf_tape *t, const mvf_bound_args *a, void *ws, size_t ws_b
         return set_err(engine_rec ? MVF_ELIMIT : MVF_EINVAL,
                        "workspace too small: the call needs " + std::to_string(L.total) + " bytes, " +
                            std::to_string(ws_bytes) + " given");
-    const int m = (int)t->C.roots.size(), n = t->C.n_vars;
     const size_t lds = spec ? spec_lds_bytes(tt, m, rev ? t->spec_gl : 0)
                             : lds_bytes(t->C.n_bound, tt, n, m, rev && L.g_lds, spill_bytes(spill_for(t->C, chunk), chunk));
     if (lds > LDS_BUDGET - 1024) return set_err(MVF_ELIMIT, "tape and tables exceed the LDS budget");

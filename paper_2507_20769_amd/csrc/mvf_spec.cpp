@@ -1417,16 +1417,19 @@ size_t spec_lds_bytes(int tab_total, int m, int gl) {
 }
 
 int spec_gl_count(const Compiled &P, int waves) {
-    // Tapes whose adjoint the library segments (section on MAX_CKPT_BUDGET):
-    // with up to 12 variables the whole gradient fits in LDS beside the
-    // tables (12 x 256 lanes x 16 bytes = 48 KB per workgroup, two workgroups
-    // per CU at two waves per SIMD).  On the 8-variable batch workload this
-    // freed the 32 VGPRs that the kernels spilled (no scratch left): 38.5 ms
-    // steadily against 39.6-49 ms; the 10-variable workload ran the same; the
-    // 6-variable mid tape, kept in one pass, ran 4 % slower, and moving 8 or 12
-    // of the 32-variable workload's components changed nothing.
+    // Tapes whose adjoint the library segments (section on MAX_CKPT_BUDGET)
+    // keep up to 16 gradient components in LDS beside the tables (16 x 256
+    // lanes x 16 bytes = 64 KB per workgroup, two workgroups per CU at two
+    // waves per SIMD), the last ones of a larger gradient.  On the 8-variable
+    // batch workload the whole gradient in LDS freed the 32 VGPRs that the
+    // kernels spilled (no scratch left): 38.5 ms steadily against 39.6-49 ms;
+    // the 10-variable workload ran the same; on the 32-variable workload 16
+    // components in LDS halved the scratch per lane and ran 4 % faster (8 or
+    // 12 had changed nothing there); the 6-variable mid tape, kept in one pass,
+    // ran 4 % slower.  A table too large to sit beside them makes mvf_bound's
+    // automatic choice take the interpreter.
     const bool segmented = spec_ckpt_min_records(P, nullptr, waves) == 0;
-    return waves <= 2 && segmented && P.n_vars <= 12 ? P.n_vars : 0;
+    return waves <= 2 && segmented ? std::min(P.n_vars, 16) : 0;
 }
 
 }  // namespace mvf

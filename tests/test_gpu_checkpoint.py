@@ -120,3 +120,27 @@ def test_diff_workload_checkpointed_adjoint_sampled():
     assert_parity(g["per_sub"][:, :, ks], o["per_sub"], not has_transcendental(w.tape), sc,
                   "diff adjoint sampled vs oracle")
     h.close()
+
+
+def test_automatic_engine_takes_the_interpreter_when_the_lds_gradient_leaves_no_room():
+    # 13 variables: the specialised adjoint keeps the 13 gradient components in LDS (52 KB per
+    # workgroup); beside a 3,500-entry breakpoint table (112 KB) they no longer fit, so the
+    # automatic choice runs the interpreter and an explicit request for the specialised kernel
+    # is refused; with a small table the automatic choice is the specialised kernel, bitwise
+    # the interpreter's bounds either way
+    from paper_2507_20769_amd import mvf
+    t = _rational(I.random_small_tape(21, n=13, ops=300, n_con=1, con_ops=20, window=8))
+    h, info = _spec(t)
+    assert info["ckpt_intervals"] > 0
+    box = np.array([[-2.0, 2.0]] * 13)
+    for splits in ([3500] + [1] * 12, [5, 3] + [1] * 11):
+        print(f"[case] splits={splits[:2]}...", flush=True)
+        ga = gpu_bound(t, box, splits, mode="both", grad="rev", handle=h, engine="auto")
+        gi = gpu_bound(t, box, splits, mode="both", grad="rev", handle=h, engine="interp")
+        for key in ("per_sub", "reduced", "argmin", "flags", "extra"):
+            assert_parity(ga[key], gi[key], True, None, f"{key}: automatic engine vs interpreter")
+    with pytest.raises(mvf.MVFError):
+        gpu_bound(t, box, [3500] + [1] * 12, mode="both", grad="rev", handle=h, engine="spec")
+    gs = gpu_bound(t, box, [5, 3] + [1] * 11, mode="both", grad="rev", handle=h, engine="spec")
+    assert_parity(gs["per_sub"], gi["per_sub"], True, None, "specialised vs interpreter")
+    h.close()
