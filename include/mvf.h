@@ -260,8 +260,8 @@ typedef struct {
                                  (reverse-mode adjoint) or MVF_GRAD_AUTO (both) */
     int32_t ckpt_budget;      /* reverse mode: register budget of one recomputed segment, in
                                  intervals, at most 32 (MVF_EINVAL above); 0 = library choice
-                                 (32; 24 at four waves per SIMD or with more than 12 variables,
-                                 whose gradient stays in registers; the roots are segmented when
+                                 (32; 24 at four waves per SIMD or with more than 16 variables,
+                                 part of whose gradient stays in registers; the roots are segmented when
                                  the largest one's single-pass adjoint keeps more partials
                                  than twice the register file's intervals), < 0 = none */
 } mvf_spec_options;

@@ -1099,13 +1099,14 @@ int spec_ckpt_budget(const Compiled &P, const mvf_spec_options *opt, int waves) 
     // store fewer checkpoints, and checkpoint traffic is what bounds the
     // segmented adjoint: on the 32-variable workload budget 32 ran 16 % faster
     // than 12 (which the register file less the gradient would give); on the
-    // 8-variable batch workload 32 ran faster than 20, 24 and 28.  A gradient
-    // of more than 12 variables stays in VGPRs (spec_gl_count): there 24 is
-    // taken, which ran 3 % faster than 32 on the 32-variable workload with the
-    // per-wave checkpoint layout (16: 1 %, 20: 2 %, 28: 2 %).
+    // 8-variable batch workload 32 ran faster than 20, 24 and 28.  With more
+    // than 16 variables part of the gradient stays in VGPRs (spec_gl_count):
+    // there 24 is taken, which on the 32-variable workload ran 3 % faster than
+    // 32 with the whole gradient in VGPRs and 4 % faster with 16 components in
+    // LDS (20 within 1 % of 24, 28 2-5 % slower).
     const int regs = 128 / std::max(1, waves);
     const int b = std::min(MAX_CKPT_BUDGET, std::max(12, regs - 8));
-    return P.n_vars > 12 ? std::min(b, 24) : b;
+    return P.n_vars > 16 ? std::min(b, 24) : b;
 }
 
 int spec_ckpt_min_records(const Compiled &P, const mvf_spec_options *opt, int waves) {
