@@ -1081,7 +1081,7 @@ __device__ __forceinline__ bool iempty(Iv a) { return !(a.lo <= -a.nh); }
 __device__ __forceinline__ bool has_zero(Iv a) { return a.lo <= 0.0 && a.nh <= 0.0; }
 
 // returns 1 when the box is proven infeasible (X then undefined)
-__device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
+__device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, int64_t stride, Iv *X) {
     constexpr double inf = __builtin_inf();
     const Iv nonneg = {0.0, -inf}, unit = {-1.0, -1.0};
     for (int round = 0; round < A.rounds; ++round) {
@@ -1089,9 +1089,9 @@ __device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
         for (int i = 0; i < A.n_nodes; ++i) {
             const DagNode nd = A.nodes[i];
             if (!nd.live) continue;
-            const Iv U = nd.op >= MVF_ADD ? Iv{val[(int64_t)nd.a * A.stride].x, val[(int64_t)nd.a * A.stride].y} : kZero;
+            const Iv U = nd.op >= MVF_ADD ? Iv{val[(int64_t)nd.a * stride].x, val[(int64_t)nd.a * stride].y} : kZero;
             const Iv V = nd.op >= MVF_ADD && nd.op <= MVF_DIV
-                             ? Iv{val[(int64_t)nd.b * A.stride].x, val[(int64_t)nd.b * A.stride].y} : kZero;
+                             ? Iv{val[(int64_t)nd.b * stride].x, val[(int64_t)nd.b * stride].y} : kZero;
             Iv Z = kZero;
             int info = 1;
             switch (nd.op) {
@@ -1115,12 +1115,12 @@ __device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
             case MVF_SIN: Z = isin(U); break;
             default: Z = icos(U); break;
             }
-            val[(int64_t)i * A.stride] = make_double2(Z.lo, Z.nh);
-            val[((int64_t)A.n_nodes + i) * A.stride].x = info ? 1.0 : 0.0;    // rows n_nodes..: the marks
+            val[(int64_t)i * stride] = make_double2(Z.lo, Z.nh);
+            val[((int64_t)A.n_nodes + i) * stride].x = info ? 1.0 : 0.0;    // rows n_nodes..: the marks
         }
         // the roots' feasible ranges
         for (int r = 0; r < A.m; ++r) {
-            double2 &z = val[(int64_t)A.roots[r] * A.stride];
+            double2 &z = val[(int64_t)A.roots[r] * stride];
             Iv c = {-inf, -inf};
             if ((A.ineq_mask >> r) & 1u) c = Iv{-inf, -0.0};
             else if ((A.eq_mask >> r) & 1u) c = Iv{0.0, -0.0};
@@ -1132,16 +1132,16 @@ __device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
         for (int i = A.n_nodes - 1; i >= 0; --i) {
             const DagNode nd = A.nodes[i];
             if (!nd.live) continue;
-            const double2 zv = val[(int64_t)i * A.stride];
+            const double2 zv = val[(int64_t)i * stride];
             Iv Z = {zv.x, zv.y};
             if (iempty(Z)) return 1;
-            if (nd.op < MVF_ADD || val[((int64_t)A.n_nodes + i) * A.stride].x == 0.0) continue;
-            double2 &us = val[(int64_t)nd.a * A.stride];
+            if (nd.op < MVF_ADD || val[((int64_t)A.n_nodes + i) * stride].x == 0.0) continue;
+            double2 &us = val[(int64_t)nd.a * stride];
             Iv U = {us.x, us.y};
             const bool bin = nd.op <= MVF_DIV;
             Iv V = kZero;
             if (bin) {
-                const double2 vs = val[(int64_t)nd.b * A.stride];
+                const double2 vs = val[(int64_t)nd.b * stride];
                 V = Iv{vs.x, vs.y};
             }
             switch (nd.op) {
@@ -1205,13 +1205,13 @@ __device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
             }
             if (iempty(U) || (bin && iempty(V))) return 1;
             us = make_double2(U.lo, U.nh);
-            if (bin) val[(int64_t)nd.b * A.stride] = make_double2(V.lo, V.nh);
+            if (bin) val[(int64_t)nd.b * stride] = make_double2(V.lo, V.nh);
         }
         // the box
         for (int i = 0; i < A.n_nodes; ++i) {
             const DagNode nd = A.nodes[i];
             if (!nd.live || nd.op != MVF_VAR) continue;
-            const double2 v = val[(int64_t)i * A.stride];
+            const double2 v = val[(int64_t)i * stride];
             X[nd.a] = imeet(X[nd.a], Iv{v.x, v.y});
         }
         for (int j = 0; j < A.n; ++j)
@@ -1222,14 +1222,20 @@ __device__ uint32_t fbbt_lane(const FbbtArgs &A, double2 *val, Iv *X) {
 
 }  // namespace dev
 
+// One lane per box; LDS: the node values and marks of the workgroup's lanes
+// (lane-interleaved) in LDS, else in the workspace (lane-interleaved over all
+// boxes).  The propagation walks the DAG node by node, each step reading what
+// the previous ones wrote, so the latency of those accesses is its time.
+template <bool LDS>
 __global__ __launch_bounds__(64) void fbbt_kernel(FbbtArgs A) {
     using namespace dev;
-    const int64_t b = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    extern __shared__ __align__(16) double2 sval[];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= A.N) return;
     Iv X[MVF_MAX_VARS];
     for (int j = 0; j < A.n; ++j) X[j] = Iv{A.boxes[(b * A.n + j) * 2], -A.boxes[(b * A.n + j) * 2 + 1]};
     mode_round_down();
-    const uint32_t bad = fbbt_lane(A, A.val + b, X);
+    const uint32_t bad = LDS ? fbbt_lane(A, sval + threadIdx.x, blockDim.x, X) : fbbt_lane(A, A.val + b, A.stride, X);
     mode_round_nearest();
     A.status[b] = (int32_t)bad;
     for (int j = 0; j < A.n; ++j) {
@@ -1240,7 +1246,21 @@ __global__ __launch_bounds__(64) void fbbt_kernel(FbbtArgs A) {
 
 hipError_t launch_fbbt(const FbbtArgs &A, hipStream_t stream) {
     if (A.N == 0) return hipSuccess;
-    hipLaunchKernelGGL(fbbt_kernel, dim3((unsigned)((A.N + 63) / 64)), dim3(64), 0, stream, A);
+    // LDS when a lane's values and marks (2 x n_nodes x 16 bytes) fit: as many
+    // lanes per workgroup as keep it within 64 KB (two or more workgroups per
+    // CU), at least one
+    const size_t lane_bytes = (size_t)2 * A.n_nodes * 16;
+    if (lane_bytes <= LDS_BUDGET - 1024) {
+        static std::once_flag once;
+        static hipError_t ae = hipSuccess;
+        std::call_once(once, [] { ae = allow_lds(fbbt_kernel<true>); });
+        if (ae != hipSuccess) return ae;
+        const int lanes = (int)std::max<size_t>(1, std::min<size_t>(64, (64 * 1024) / lane_bytes));
+        hipLaunchKernelGGL(fbbt_kernel<true>, dim3((unsigned)((A.N + lanes - 1) / lanes)), dim3(lanes),
+                           lane_bytes * lanes, stream, A);
+    } else {
+        hipLaunchKernelGGL(fbbt_kernel<false>, dim3((unsigned)((A.N + 63) / 64)), dim3(64), 0, stream, A);
+    }
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 tightened boxes and the infeasibility status, bitwise for + - * / sqr sqrt
 tapes and within 1e-12 of the box scale where library functions appear, for
 hand cases, random constrained problems with an objective cut, one to three
-rounds, and batches with a ragged last wave."""
+rounds, batches with a ragged last wave, and tapes whose node values fill
+many lanes', one lane's, or more than the LDS."""
 import numpy as np
 import pytest
 
@@ -86,6 +87,19 @@ def test_random_problems_ragged_batches(seed):
         for rounds in (1, 3):
             _compare(tape, [0, 1, 1], boxes, rounds=rounds, what=f"seed {seed}")
             _compare(tape, [0, 1, 2], boxes, ub=float(np.median(f)), rounds=rounds, what=f"seed {seed} eq+ub")
+
+
+@pytest.mark.parametrize("ops,con_ops", [(1200, 300), (2600, 700)])
+def test_large_tapes(ops, con_ops):
+    # 2,506 nodes: a lane's values and marks (78 KB) in LDS, one lane per workgroup; 5,542
+    # nodes (173 KB): more than the LDS holds, the values in the workspace
+    rng = np.random.default_rng(ops)
+    t = _rational(I.random_small_tape(301, n=3, ops=ops, n_con=2, con_ops=con_ops, window=8))
+    N = 70
+    lo = rng.uniform(-2.5, 0.5, (N, 3))
+    boxes = np.stack([lo, lo + rng.uniform(0.2, 2.5, (N, 3))], axis=2)
+    f = I.eval_points_np(t, boxes.mean(axis=2))[:, 0]
+    _compare(t, [0, 1, 1], boxes, ub=float(np.median(f)), rounds=2, what=f"{t.n_nodes} nodes")
 
 
 def test_bnb_with_tightening_matches_the_reference():
