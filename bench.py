@@ -532,7 +532,7 @@ def batch_profile(args) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the path is not sharded across GPUs); --gpus must be 1"}))
         sys.exit(2)
     import torch
 
