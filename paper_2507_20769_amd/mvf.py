@@ -487,12 +487,19 @@ class BatchCall:
         N = int(self.boxes.shape[0])
         assert tuple(self.boxes.shape) == (N, tape.n_vars, 2) and self.boxes.dtype == torch.float64
         assert tuple(self.splits.shape) == (N, tape.n_vars)
-        total = int(torch.prod(self.splits.to(torch.int64), dim=1).sum().item())
+        total = int(torch.prod(self.splits.to(torch.int64), dim=1).sum().item()) if N else 0
         self.total = total
         cap = max_subdomains if max_subdomains is not None else total
         dev = self.boxes.device
         m = tape.n_roots
         self.tuning = tuning
+        self.empty = N == 0                    # an empty batch: no call, empty results
+        if self.empty:
+            self.reduced = torch.empty((0, m, 2), dtype=torch.float64, device=dev)
+            self.argmin = torch.empty(0, dtype=torch.int64, device=dev)
+            self.status = torch.empty(0, dtype=torch.int32, device=dev)
+            self.extra = torch.empty((0, 2), dtype=torch.float64, device=dev)
+            return
         tp = ctypes.byref(tuning) if tuning is not None else None
         ws = ctypes.c_size_t()
         rc = lib().mvf_batch_workspace(tape.handle, N, max(cap, 1), MVF_MODE[mode], MVF_GRAD[grad], tp,
@@ -509,6 +516,8 @@ class BatchCall:
                               self.workspace.data_ptr(), self.workspace.numel(), self.extra.data_ptr())
 
     def launch(self, stream=None):
+        if self.empty:
+            return self
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
         rc = lib().mvf_bound_batch(self.tape.handle, ctypes.byref(self.args), tp, _stream_ptr(stream))
         if rc != 0:

@@ -163,6 +163,39 @@ def test_graph_replay_matches_fresh_launches():
     g.close()
 
 
+def test_empty_batches():
+    # no nodes: the batched call is a no-op with empty results, and a graph replay with no
+    # nodes between replays with nodes leaves them unaffected
+    import torch
+    from paper_2507_20769_amd import mvf
+    bw = I.small_batch(15, 8, k_range=(3, 8))
+    h = mvf.Tape(bw.tape)
+    n = bw.tape.n_vars
+    out = mvf.bound_batch(h, torch.empty((0, n, 2), dtype=torch.float64, device="cuda"),
+                          torch.empty((0, n), dtype=torch.int32, device="cuda"))
+    assert out["reduced"].shape == (0, bw.tape.n_roots, 2) and out["status"].numel() == 0
+    total = int(np.prod(bw.splits.astype(np.int64), axis=1).sum())
+    stream = torch.cuda.Stream()
+    for grad in ("fwd", "rev"):
+        g = mvf.BatchGraph(h, max_nodes=8, max_subdomains=total, mode="both", grad=grad)
+        for rep, sel in enumerate([slice(0, 8), slice(0, 0), slice(2, 5), slice(4, 4), slice(0, 8)]):
+            print(f"[case] grad={grad} replay={rep} nodes={sel.stop - sel.start}", flush=True)
+            boxes, splits = bw.boxes[sel], bw.splits[sel]
+            g.launch(boxes, splits, stream=stream)
+            stream.synchronize()
+            red, am, st = g.result()
+            assert red.shape[0] == sel.stop - sel.start
+            if red.shape[0]:
+                fresh = mvf.bound_batch(h, torch.tensor(boxes, device="cuda"), torch.tensor(splits, device="cuda"),
+                                        mode="both", grad=grad)
+                torch.cuda.synchronize()
+                assert not st.any(), rep
+                assert np.array_equal(red, fresh["reduced"].cpu().numpy()), rep
+                assert np.array_equal(am, fresh["argmin"].cpu().numpy()), rep
+        g.close()
+    h.close()
+
+
 def test_autotuner_returns_a_feasible_config():
     import torch
     from paper_2507_20769_amd import mvf
