@@ -163,6 +163,32 @@ def test_roots_sharing_subexpressions(grad, rational):
     h.close()
 
 
+def test_largest_variable_count():
+    # 64 variables (MVF_MAX_VARS): many tangent passes in forward mode, a gradient partly in
+    # LDS and partly in registers in the adjoint; ragged and power-of-two partitions
+    rng = np.random.default_rng(64)
+    tb = I.TapeBuilder(64)
+    xs = [tb.var(i) for i in range(64)]
+    f = tb.const(0.5)
+    for i in range(64):                    # f = 0.5 + sum_i (x_i - k_i)^2 / (1 + x_{i+1}^2) in a running sum
+        d = tb.add(I.SUB, xs[i], tb.const(float(rng.uniform(-1, 1))))
+        q = tb.add(I.DIV, tb.add(I.SQR, d), tb.add(I.ADD, tb.const(1.0), tb.add(I.SQR, xs[(i + 1) % 64])))
+        f = tb.add(I.ADD, f, q)
+    tb.roots.append(f)
+    g = tb.const(-1.0)
+    for i in range(0, 64, 2):              # g = sum_i x_{2i} x_{2i+1} - 1 <= 0
+        g = tb.add(I.ADD, g, tb.add(I.MUL, xs[i], xs[i + 1]))
+    tb.roots.append(g)
+    t = tb.build()
+    kinds = [0, 1]
+    h = _handle(t, kinds, grad="auto")
+    box = np.array([[-2.0, 2.0]] * 64) + rng.uniform(-0.3, 0.3, (64, 1))
+    for splits in ([3, 5] + [1] * 62, [2] * 8 + [1] * 56):
+        for grad in ("fwd", "rev"):
+            _compare(h, t, box, splits, "both", kinds, grad=grad)
+    h.close()
+
+
 @pytest.mark.parametrize("grad", ["fwd", "rev"])
 def test_mid_rational_full_size_bitwise(grad):
     # the mid workload's shape with exp -> sqr and log -> sqrt, at full size in the
