@@ -26,6 +26,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <sys/stat.h>
 #include <utime.h>
@@ -62,6 +63,10 @@ constexpr int LDS_LEAD = 2;                      // statements a variable's LDS 
 // (segment budget 32, 64-lane workgroups) -- the adjoint kernels are not built
 // for one wave per SIMD.
 constexpr int MAX_CKPT_BUDGET = 32;
+// Values recomputed at a segment's reload instead of stored: chains of at most
+// this many cheap operations (sums, differences, products, squares, constant
+// forms) from variables and constants.
+constexpr int MAX_RELOAD_DEPTH = 2;
 // A body line that only starts a new guarded block (segment boundaries of the
 // checkpointed adjoint, so that a segment's checkpoint loads lead a block).
 const char *const BLOCK_BREAK = "\x01";
@@ -257,6 +262,7 @@ class Scheduler {
 // it (the same operation on the same operands: the same bits, no traffic).
 // ck_count intervals per lane in all.
 struct SegPlan {
+    std::vector<int> pa, pb;                     // producers of an instruction's slot operands (or -1)
     std::vector<int> start;
     std::vector<std::vector<int>> in;
     std::vector<std::vector<int>> store;
@@ -265,8 +271,18 @@ struct SegPlan {
     int ck_count = 0;
 };
 
-// an instruction whose value is recomputed instead of checkpointed: one cheap
-// operation (no division, root or transcendental) on variables and constants
+// A cheap operation (no division, root or transcendental), slot operands allowed.
+bool cheap_op(const Dec &I) {
+    switch (I.op) {
+    case I_ADD: case I_SUB: case I_MUL: case I_SQR: case I_ADDK: case I_KSUB: case I_MULK: case I_MULKN:
+        return true;
+    default:
+        return false;
+    }
+}
+
+// One cheap operation on variables and constants: the first step of a value
+// recomputed at reload instead of checkpointed (chains of MAX_RELOAD_DEPTH).
 bool recompute_at_reload(const Dec &I) {
     switch (I.op) {
     case I_ADD: case I_SUB: case I_MUL:
@@ -388,10 +404,21 @@ class PassWriter {
                     ld += "v" + std::to_string(p) + " = spec_ck_ld(L, " + std::to_string(S.slot.at(p)) + "); ";
             return ld;
         };
+        // recomputed inputs, each after the recomputed values it reads (program order)
         auto recomputed_of = [&](int j) {
-            std::string re;
+            std::set<int> need;
+            std::vector<int> todo;
             for (int p : in[j])
-                if (S.again[p - rp.begin]) re += value_stmt.at(p);
+                if (S.again[p - rp.begin]) todo.push_back(p);
+            while (!todo.empty()) {
+                const int p = todo.back();
+                todo.pop_back();
+                if (!need.insert(p).second) continue;
+                for (int q : {S.pa[p - rp.begin], S.pb[p - rp.begin]})
+                    if (q >= 0) todo.push_back(q);
+            }
+            std::string re;
+            for (int p : need) re += value_stmt.at(p);
             return re;
         };
         partials = true;
@@ -846,11 +873,20 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
     std::vector<int> prod(std::max(rp.n_slots, 1) + 1, -1);
     SegPlan S;
     S.again.assign(len, 0);
+    std::vector<int> depth(len, 0);                // cheap operations from variables and constants
     for (int i = 0; i < len; ++i) {
         const Dec I = decode(P.instr[rp.begin + i]);
-        S.again[i] = recompute_at_reload(I);
         if (I.ak == K_SLOT && I.a < prod.size()) pa[i] = prod[I.a];
         if (I.op <= I_DIV && I.bk == K_SLOT && I.b < prod.size()) pb[i] = prod[I.b];
+        if (recompute_at_reload(I)) {
+            depth[i] = 1;
+        } else if (cheap_op(I)) {
+            int d = 0;
+            for (int p : {pa[i], pb[i]})
+                if (p >= 0) d = std::max(d, depth[p - rp.begin] > 0 ? depth[p - rp.begin] : MAX_RELOAD_DEPTH);
+            if ((I.ak != K_SLOT || pa[i] >= 0) && (I.op > I_DIV || I.bk != K_SLOT || pb[i] >= 0)) depth[i] = d + 1;
+        }
+        S.again[i] = depth[i] > 0 && depth[i] <= MAX_RELOAD_DEPTH;
         if (I.op == I_DIV || (is_unary_fn(I.op) && I.op != I_EXP)) cost[i] = 2;     // 1/V, or the derivative
         if (I.d >= prod.size()) prod.resize(I.d + 1, -1);
         prod[I.d] = rp.begin + i;
@@ -901,6 +937,8 @@ SegPlan plan_segments(const Compiled &P, int r, int budget) {
         for (int e = len; e > 0; e = from[e]) cuts.push_back(e);
         S.start.insert(S.start.end(), cuts.rbegin(), cuts.rend());
     }
+    S.pa = pa;
+    S.pb = pb;
     const int K = (int)S.start.size() - 1;
     S.in.assign(K, {});
     S.store.assign(K, {});
